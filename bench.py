@@ -1,0 +1,149 @@
+"""Throughput benchmark of the gain-dissipative solver on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload xy1024|ising64|...]
+
+A step is one integration step (one RK4 step = four coupling launches) of
+all R trajectories, including the device energy check (discretise, energy
+GEMM, best-of-R) every `check` steps.  Default workload: XY model, N = 1024,
+J_ij ~ N(0, 1/N), R = 1024 complex trajectories, RK4 dt = 0.02, FP32, 5000
+steps.  Prints one JSON line with spin-updates/s (N * R * steps / s), the
+roofline position of the dominant kernel (device time per launch from HIP
+events recorded around every coupling launch on the solver's stream) and the
+FP64 oracle timed on the host CPU over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (model, n, R, integrator, dt, steps, generator)
+    "xy1024": dict(model="xy", n=1024, R=1024, integrator="rk4", dt=0.02, steps=5000,
+                   J="dense_gaussian", desc="XY, N=1024, J~N(0,1/N), R=1024, RK4 dt=0.02, FP32"),
+    "ising64": dict(model="ising", n=64, R=100, integrator="euler", dt=0.05, steps=2000,
+                    J="dense_pm1", desc="Ising, N=64, J iid {-1,+1}, R=100, Euler dt=0.05, FP32"),
+    "ising4096_fp32": dict(model="ising", n=4096, R=4096, integrator="euler", dt=0.05, steps=200,
+                           J="sparse_pm1", desc="Ising, N=4096, J in {-1,0,1} density 0.5, "
+                                                "R=4096, Euler dt=0.05, FP32 operands"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="xy1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--check", type=int, default=50, help="steps between device energy checks")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, J, psi0, target_s):
+    """Oracle (FP64, OpenMP over trajectories) on a bounded sample: a subset
+    of trajectories for a few steps, scaled to spin-updates/s."""
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    integ = O.RK4 if wl["integrator"] == "rk4" else O.EULER
+    n = wl["n"]
+    R_s = min(wl["R"], threads * 2)
+    steps = 1
+    # pilot, then size the sample to ~target_s
+    t0 = time.perf_counter()
+    O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
+          integrator=integ, nthreads=threads)
+    pilot = time.perf_counter() - t0
+    steps = max(1, int(target_s / max(pilot, 1e-6)))
+    steps = min(steps, wl["steps"])
+    t0 = time.perf_counter()
+    O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
+          integrator=integ, nthreads=threads)
+    el = time.perf_counter() - t0
+    return {"value": n * R_s * steps / el, "unit": "spin-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{R_s} of {wl['R']} trajectories x {steps} steps, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); restarts are independent, "
+              "so N GPUs would each run their own share of trajectories with no communication.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    wl = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else wl["steps"]
+    n, R = wl["n"], wl["R"]
+    J = getattr(I, wl["J"])(n, 1)
+    psi0 = I.psi0_complex(n, R, 1) if wl["model"] == "xy" else I.psi0_real(n, R, 1)
+    model = gd.GD_XY if wl["model"] == "xy" else gd.GD_ISING
+    integ = gd.GD_RK4 if wl["integrator"] == "rk4" else gd.GD_EULER
+    torch.cuda.init()
+    # inputs resident in HBM before the timed region; HIP events around every
+    # coupling launch on the solver's stream (GD_F_PROFILE)
+    S = gd.Solver(J, model=model, integrator=integ, dt=wl["dt"], eps=0.1,
+                  check_interval=args.check, flags=gd.GD_F_PROFILE)
+    S.set_init(R, psi0)
+    if args.warmup:
+        S.run(args.warmup)
+    torch.cuda.synchronize()
+    st0 = S.stats()
+    t0 = time.perf_counter()
+    S.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = S.stats()
+    E, best = S.energy()
+    S.close()
+
+    P = 2 if wl["model"] == "xy" else 1
+    launches = st.kernel_launches - st0.kernel_launches
+    kms = st.kernel_ms - st0.kernel_ms
+    avg_s = kms / 1e3 / max(launches, 1)
+    flops_launch = 2.0 * n * n * P * R          # coupling GEMM of one launch
+    achieved = flops_launch / avg_s / 1e12
+    out = {
+        "metric": "spin-updates/s (N*R*steps/s)",
+        "value": n * R * steps / el,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "R": R, "integrator": wl["integrator"],
+                   "dt": wl["dt"], "energy_check_every": args.check, "kernel_config": st.kernel_config},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "kernel": "dense_step_f32", "launches": int(launches),
+                     "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops_launch},
+        "best_energy": float(E[best]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, J, psi0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

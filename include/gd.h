@@ -1,0 +1,217 @@
+/*
+ * gd.h -- C ABI of libgd.so, a gfx950 (MI355X) implementation of the
+ * gain-dissipative (GD) optimiser of Kalinin & Berloff, "Global optimization
+ * of spin Hamiltonians with gain-dissipative systems" (arXiv:1807.00699).
+ *
+ * The library time-steps, for R independent trajectories ("restarts") of one
+ * coupling matrix J, the rate equations
+ *
+ *   dPsi_i/dt   = Psi_i (gamma_i - gamma_c - |Psi_i|^2)
+ *                 + (1/s) sum_{j != i} J_ij Psi_j  + h_1i            Eq. (main)
+ *   dgamma_i/dt = eps_i (rho_th - |Psi_i|^2)                         Eq. (gamma)
+ *
+ * (GD form: Delta_ij = 1, K_ij = J_ij; noise D = 0) for real amplitudes
+ * (Ising, Sec. 3, on the real subspace where the q = 2 penalty is a shift of
+ * gamma_c) or complex amplitudes (XY, Sec. 2), and scores the discretised
+ * states with the Hamiltonian of Eq. (h):
+ *
+ *   H = - sum_{i != j} J_ij cos(theta_i - theta_j) + sum_i g_i cos(theta_i).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns GD_OK (0) or a negative gd_error code; no
+ *    exception or abort crosses the ABI.  gd_last_error() returns a
+ *    thread-local message for the last failure on the calling thread.
+ *  - Pointers are host pointers unless GD_F_DEVICE_PTRS is set in the
+ *    solver's params, in which case every array argument (inputs and outputs)
+ *    is a device pointer on the solver's device.  The caller always keeps
+ *    ownership of its arrays; the library copies what it needs.
+ *  - Matrices are row-major.  Per-trajectory arrays are trajectory-major:
+ *    element (r, i) of a [batch][n] array is at r*n + i; complex values are
+ *    interleaved (re, im), i.e. [batch][n][2].
+ *  - A handle is not thread-safe: calls on one handle must not overlap.
+ *  - Work is enqueued on params.stream (a hipStream_t; NULL = a stream the
+ *    library creates).  Calls synchronise that stream before returning unless
+ *    GD_F_ASYNC is set (then only gd_run may return early).
+ */
+#ifndef GD_H_
+#define GD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GD_ABI_VERSION 1
+
+/* Error codes (all negative). */
+typedef enum gd_error {
+    GD_OK = 0,
+    GD_E_INVALID_ARG = -1,   /* bad size, NULL pointer, unknown enum, bad struct_size */
+    GD_E_NOT_SYMMETRIC = -2, /* J[i][j] != J[j][i] for some i != j (exact compare) */
+    GD_E_NONFINITE = -3,     /* NaN/Inf in J, g, eps or an initial state */
+    GD_E_OOM = -4,           /* device allocation failed; the handle stays valid */
+    GD_E_DEVICE = -5,        /* HIP runtime error (message in gd_last_error) */
+    GD_E_STATE = -6,         /* call out of order (e.g. energy before any state exists) */
+    GD_E_DIVERGED = -7,      /* a trajectory became non-finite (see gd_stats.diverged) */
+    GD_E_UNSUPPORTED = -8    /* valid request the library does not implement */
+} gd_error;
+
+/* Spin model.  GD_ISING integrates real amplitudes (theta in {0, pi});
+ * GD_XY integrates complex amplitudes (theta in [0, 2pi)). */
+typedef enum gd_model { GD_ISING = 0, GD_XY = 1 } gd_model;
+
+/* Time integrator: explicit Euler, or the classical 4th-order Runge-Kutta
+ * scheme on the joint state (Psi, gamma) (Sec. 2 uses RK4 for XY). */
+typedef enum gd_integrator { GD_EULER = 0, GD_RK4 = 1 } gd_integrator;
+
+/* Operand precision of the coupling product sum_j J_ij Psi_j.  Accumulation,
+ * the amplitude/gain update and the energies are FP32 (energies are also
+ * re-scored in FP64) in every mode. */
+typedef enum gd_precision {
+    GD_PREC_FP32 = 0,  /* J and Psi in FP32 */
+    GD_PREC_BF16 = 1,  /* Psi operand rounded to BF16; J in BF16 (FP8 storage when exact) */
+    GD_PREC_FP16 = 2   /* Psi operand rounded to FP16; J in FP16 (FP8 storage when exact) */
+} gd_precision;
+
+/* Output format of gd_spins. */
+typedef enum gd_spin_fmt {
+    GD_SPINS_I8 = 0,        /* Ising: int8 +-1, [batch][n] */
+    GD_SPINS_ANGLE_F32 = 1  /* XY (or Ising): float theta in [0, 2pi), [batch][n] */
+} gd_spin_fmt;
+
+#define GD_F_DEVICE_PTRS 0x1u  /* array arguments are device pointers */
+#define GD_F_ASYNC 0x2u        /* gd_run returns without synchronising the stream */
+#define GD_F_PROFILE 0x4u      /* time each coupling-step launch with HIP events */
+
+/* Parameters of a solver.  Fill with gd_default_params(), then override.
+ * struct_size must be sizeof(gd_params) of the caller's header. */
+typedef struct gd_params {
+    uint32_t struct_size;
+    int32_t integrator;      /* gd_integrator */
+    int32_t precision;       /* gd_precision */
+    uint32_t flags;          /* GD_F_* */
+    double dt;               /* time step (default 0.05) */
+    double eps;              /* gain-adjustment rate epsilon of Eq. (gamma) (default 0.1) */
+    double rho_th;           /* threshold density rho_th of Eq. (gamma) (default 1) */
+    double gamma_c;          /* loss rate gamma_c of Eq. (main) (default 0) */
+    double gamma0;           /* initial gain gamma_i(0) when none is given (default 0) */
+    double j_scale;          /* coupling scale s; 0 selects s = sqrt(sum_{i!=j} J_ij^2 / n) */
+    double init_amp;         /* amplitude of the default initial state (default 0.1) */
+    uint64_t seed;           /* seed of the default initial state */
+    int32_t check_interval;  /* steps between device energy checks inside gd_run (0 = none) */
+    int32_t has_target;      /* nonzero: gd_run stops at the first check with min_r E_r <= target */
+    double target_energy;    /* target of Eq. (h) energy for time-to-target */
+    void *stream;            /* hipStream_t or NULL */
+} gd_params;
+
+/* Counters of a solver (cumulative over gd_run calls since the last
+ * gd_set_init / gd_set_state). */
+typedef struct gd_run_stats {
+    uint32_t struct_size;
+    int32_t batch;            /* R */
+    int64_t steps_done;       /* integration steps of the current trajectories */
+    int64_t spin_updates;     /* sum over gd_run calls of n * R * steps */
+    double run_seconds;       /* host wall time inside gd_run (synchronous calls) */
+    double kernel_ms;         /* summed device time of coupling-step launches (GD_F_PROFILE) */
+    int64_t kernel_launches;  /* number of coupling-step launches timed in kernel_ms */
+    int32_t diverged;         /* trajectories whose state became non-finite */
+    int32_t target_reached;   /* 1 once a check met the target */
+    double ttt_seconds;       /* wall time from the start of gd_run to that check */
+    int64_t ttt_steps;        /* steps done at that check */
+    double best_energy;       /* lowest device-checked energy so far (+inf if none) */
+    int32_t best_index;       /* its trajectory */
+    int32_t kernel_config;    /* id of the coupling kernel variant in use */
+} gd_run_stats;
+
+typedef struct gd_solver gd_solver;
+
+/* Defaults: Euler, FP32, dt 0.05, eps 0.1, rho_th 1, gamma_c 0, gamma0 0,
+ * automatic coupling scale, init_amp 0.1, seed 0, no checks, NULL stream. */
+void gd_default_params(gd_params *p);
+
+/*
+ * gd_create: build a solver for one instance.
+ *   n      number of spins (1 <= n <= 65536).
+ *   J      n*n row-major couplings; must be finite and exactly symmetric; the
+ *          diagonal is ignored (the sums of Eq. (main) and Eq. (hs) skip j = i).
+ *   g      external field g_i of Eq. (h), length n, or NULL for g = 0.  It
+ *          enters Eq. (main) as the q = 1 resonant term h_1i = -g_i sqrt(rho_th)/s,
+ *          so that the dynamics minimise Eq. (h) as printed.
+ *   model  gd_model.  p: parameters (copied), NULL = defaults.
+ * Errors: GD_E_INVALID_ARG, GD_E_NOT_SYMMETRIC, GD_E_NONFINITE, GD_E_OOM,
+ * GD_E_DEVICE, GD_E_UNSUPPORTED (reduced precision with J not exactly
+ * representable in it).  On error *out is set to NULL.
+ */
+int gd_create(gd_solver **out, int32_t n, const float *J, const float *g,
+              int32_t model, const gd_params *p);
+
+/* gd_destroy: free the handle and its device memory (NULL is a no-op). */
+void gd_destroy(gd_solver *s);
+
+/*
+ * gd_set_init: set the initial state of `batch` trajectories and reset the
+ * step counter and statistics.
+ *   psi0   Ising [batch][n], XY [batch][n][2]; NULL = default initial state
+ *          (Ising U(-a, a); XY a*exp(i*phi), phi ~ U[0, 2pi); a = init_amp,
+ *          drawn from SplitMix64 keyed by seed, trajectory and spin).
+ *   gamma0 [batch][n] initial gains, or NULL for params.gamma0.
+ *   eps    [n] per-spin gain rates eps_i (the site-dependent rates suggested
+ *          in Sec. 3), or NULL for params.eps.
+ */
+int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gamma0,
+                const float *eps);
+
+/*
+ * gd_run: integrate `steps` steps of all trajectories.  If no state exists
+ * yet, the default initial state with `batch` trajectories is created first;
+ * otherwise `batch` must equal the current batch and the trajectories
+ * continue.  With check_interval > 0 the discretised energies are evaluated
+ * on the device every check_interval steps; with has_target the run stops at
+ * the first check where min_r E_r <= target_energy (gd_stats.ttt_*).
+ * Returns GD_E_DIVERGED if any trajectory is non-finite at the end.
+ */
+int gd_run(gd_solver *s, int32_t batch, int64_t steps);
+
+/*
+ * gd_energy: Eq. (h) energies of the discretised current state (Ising:
+ * s_i = sign(x_i) with sign(+-0) = +1; XY: theta_i = arg Psi_i, Psi_i = 0 ->
+ * theta_i = 0), evaluated on the device in FP64 from the FP32 state (exact
+ * for integer-valued J and g).
+ *   E     [batch] doubles.  best: argmin_r E_r (ties -> lowest r), nullable.
+ */
+int gd_energy(gd_solver *s, double *E, int32_t *best);
+
+/*
+ * gd_energy_device: the same energies as computed by the device check path
+ * (FP32 coupling product, FP64 accumulation of the per-spin terms).  Exact,
+ * and equal to gd_energy, for integer-valued J and g with n < 2^24.
+ */
+int gd_energy_device(gd_solver *s, double *E, int32_t *best);
+
+/* gd_spins: discretised current state into caller memory, format gd_spin_fmt
+ * (GD_SPINS_I8 needs model GD_ISING). */
+int gd_spins(gd_solver *s, void *out, int32_t fmt);
+
+/* gd_get_state / gd_set_state: amplitudes ([batch][n] or [batch][n][2]),
+ * gains [batch][n] and step counter; NULL pointers are skipped on get.
+ * gd_set_state needs both psi and gamma and keeps the per-spin eps. */
+int gd_get_state(gd_solver *s, float *psi, float *gamma, int64_t *step);
+int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gamma,
+                 int64_t step);
+
+/* gd_stats: copy the counters (out->struct_size must be set). */
+int gd_stats(gd_solver *s, gd_run_stats *out);
+
+/* gd_coupling_scale: the scale s in use. */
+int gd_coupling_scale(gd_solver *s, double *scale);
+
+const char *gd_error_string(int code);
+const char *gd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GD_H_ */

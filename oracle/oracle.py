@@ -179,6 +179,50 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
     raise ValueError(f"unknown model {model!r}")
 
 
+def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
+            rho_th: float = 1.0, gamma_c: float = 0.0, s: float | None = None, g=None,
+            integrator: int = EULER):
+    """The same integration as `run` carried out in float32 with numpy
+    (no resonant terms beyond the field).  Used only to measure the FP32
+    noise floor of a trajectory: |run_f32 - run| / |run| shows how far
+    rounding at single precision alone moves it, independent of any GPU."""
+    f32 = np.float32
+    J = np.asarray(J, np.float32).copy()
+    np.fill_diagonal(J, 0.0)
+    n = J.shape[0]
+    if s is None:
+        s = coupling_scale(J)
+    inv_s = f32(1.0 / s)
+    epsv = np.full(n, eps, f32) if np.isscalar(eps) else np.asarray(eps, f32)
+    h1 = np.zeros(n, f32) if g is None else field_h1(g, rho_th, s).astype(f32)
+    cx = model == "xy"
+    p = np.asarray(psi, f32).copy()
+    z = (p[..., 0] + 1j * p[..., 1]).astype(np.complex64) if cx else p
+    gam = np.zeros(z.shape, f32) if gamma is None else np.asarray(gamma, f32).reshape(z.shape).copy()
+    dt = f32(dt)
+
+    def F(y, gm):
+        c = (y @ J.T) * inv_s
+        rho = (y.real * y.real + y.imag * y.imag) if cx else y * y
+        return y * (gm - f32(gamma_c) - rho) + c + h1, epsv * (f32(rho_th) - rho)
+
+    for _ in range(int(steps)):
+        k1 = F(z, gam)
+        if integrator == EULER:
+            z, gam = z + dt * k1[0], gam + dt * k1[1]
+            continue
+        h = dt * f32(0.5)
+        k2 = F(z + h * k1[0], gam + h * k1[1])
+        k3 = F(z + h * k2[0], gam + h * k2[1])
+        k4 = F(z + dt * k3[0], gam + dt * k3[1])
+        c6 = dt / f32(6.0)
+        z = z + c6 * (k1[0] + f32(2) * k2[0] + f32(2) * k3[0] + k4[0])
+        gam = gam + c6 * (k1[1] + f32(2) * k2[1] + f32(2) * k3[1] + k4[1])
+    if cx:
+        z = np.stack([z.real, z.imag], -1).astype(f32)
+    return z, gam
+
+
 # ---------------------------------------------------------------- readout
 
 def ising_spins(x) -> np.ndarray:

@@ -1,0 +1,90 @@
+// Internal interfaces between the host runtime and the gfx950 kernels of
+// libgd.so.  Not part of the public ABI (include/gd.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gd {
+
+// Epilogue of the dense coupling kernel.
+enum StepMode : int {
+    MODE_EULER = 0,   // psi_out = psi + dt f, gamma += dt phi
+    MODE_RK1 = 1,     // k1; acc = k1; stage = y + dt/2 k1
+    MODE_RK2 = 2,     // k2; acc += 2 k2; stage = y + dt/2 k2
+    MODE_RK3 = 3,     // k3; acc += 2 k3; stage = y + dt k3
+    MODE_RK4 = 4,     // k4; y += dt/6 (acc + k4)
+    MODE_ENERGY = 5,  // per-trajectory partial sums of Eq. (h) over a row tile
+};
+
+// Operand precision of the coupling product.
+enum OperandKind : int { OP_F32 = 0, OP_BF16 = 1, OP_F16 = 2 };
+
+// Row tile of every dense kernel and the padding unit of n.
+constexpr int kRowTile = 64;
+
+// All pointers are device pointers.  Per-trajectory arrays are "planes" of
+// [Rp][Np] floats (trajectory-major, spin contiguous, zero padded); complex
+// amplitudes use two consecutive planes (re, im) of plane_stride floats.
+struct DenseStepArgs {
+    const void *J;         // [Np][Np] coupling, operand precision (FP32 / BF16 / FP16)
+    const void *B;         // GEMM operand planes (FP32, or BF16/FP16 shadow)
+    const float *psi_in;   // stage-input amplitudes at (r, i) (FP32 planes)
+    float *psi_out;        // output amplitudes (next stage / next step)
+    void *shadow_out;      // reduced-precision copy of psi_out for the next GEMM (or null)
+    const float *gam_in;   // stage-input gains
+    float *gam_out;        // output gains (may alias gam_in)
+    const float *y_psi;    // RK4: amplitudes at the start of the step
+    const float *y_gam;    // RK4: gains at the start of the step
+    float *acc_psi;        // RK4: k1 + 2 k2 + 2 k3 accumulators
+    float *acc_gam;
+    const float *eps;      // [Np] per-spin gain rates
+    const float *h1;       // [Np] q = 1 resonant term h_1i (zero padded)
+    const float *g;        // [Np] external field g_i (energy mode)
+    int *flags;            // [Rp] nonzero when trajectory r became non-finite
+    double *partial;       // energy mode: [n_row_tiles][Rp]
+    long long plane_stride;
+    int Np, Rp, n, R;
+    float inv_s, dt, gamma_c, rho_th;
+};
+
+// Kernel variants of the dense path.  traj_tile = trajectories per workgroup.
+struct DenseConfig {
+    int id;
+    int bn;        // GEMM columns per workgroup
+    int wn;        // waves along the column dimension (2 waves along rows)
+    int traj_tile; // trajectories per workgroup
+    int threads;
+};
+
+int dense_config_count(bool complex_mode);
+DenseConfig dense_config(bool complex_mode, int idx);
+
+hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
+                             const DenseStepArgs &a, hipStream_t st);
+
+// ---- auxiliary kernels (gd_aux.hip)
+// user [R][n] (or [R][n][2]) -> zero-padded planes [P][Rp][Np]
+hipError_t launch_pack_planes(const float *user, float *planes, int n, int R, int Np, int Rp,
+                              int nplanes, hipStream_t st);
+hipError_t launch_unpack_planes(const float *planes, float *user, int n, int R, int Np, int Rp,
+                                int nplanes, hipStream_t st);
+// discretised spins: Ising D = sign(x) (+-0 -> +1); XY D = (cos, sin) of arg psi
+// (psi = 0 -> (1, 0)); zero outside n x R.  Optional outputs (null to skip):
+// spins8 [R][n] int8, angle [R][n] float in [0, 2pi).  flags[r] set on NaN.
+hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int8_t *spins8,
+                             float *angle, int *flags, int n, int R, int Np, int Rp, int nplanes,
+                             long long plane_stride, hipStream_t st);
+// E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r)
+hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
+                                int *best, hipStream_t st);
+// FP64 re-score from the FP32 amplitudes (unit phasors / signs formed in FP64):
+// partial[t][r] = sum_{i in tile t} [-Re(conj(d_i) (J d)_i) + g_i Re(d_i)]
+hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *partial,
+                              int Np, int Rp, int n, int R, int nplanes, long long plane_stride,
+                              hipStream_t st);
+// shadow copy of FP32 planes in BF16 / FP16
+hipError_t launch_make_shadow(const float *src, void *dst, long long count, int op, hipStream_t st);
+// any_flag: out[0] = number of r < R with flags[r] != 0
+hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st);
+
+}  // namespace gd

@@ -1,0 +1,797 @@
+// Host runtime and C ABI of libgd.so (declarations and contracts: include/gd.h).
+//
+// Ingest (once per instance): validate J (finite, exactly symmetric), zero
+// the diagonal, compute the coupling scale s, map the external field g of
+// Eq. (h) onto the q = 1 term h_1 = -g sqrt(rho_th)/s of Eq. (main), pad to
+// the row tile and upload.  Run: one dense coupling launch per Euler step or
+// per RK4 stage, with the amplitude/gain update fused in (gd_dense.hip).
+#include "gd_internal.h"
+#include "../../include/gd.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace gd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define GD_HIP(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? GD_E_OOM : GD_E_DEVICE,                 \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+        }                                                                                   \
+    } while (0)
+
+inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+constexpr int kTrajAlign = 128;  // Rp granularity: every dense variant tiles it
+
+// SplitMix64 (Steele, Lea, Flood 2014) -> uniform double in [0, 1).
+inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+inline double uniform01(uint64_t seed, uint64_t ctr) {
+    return double(splitmix64(seed ^ splitmix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (complex, Np, Rp, integrator) -> cfg
+
+}  // namespace
+
+struct gd_solver {
+    int n = 0, Np = 0, model = 0, P = 1;
+    gd_params prm{};
+    double s = 1.0;
+    bool j_integer = false, g_integer = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::vector<float> hJ;     // padded host copy (for re-validation and tests)
+    std::vector<float> hEps;   // per-spin eps actually in use (length n)
+    // device constants
+    float *dJ = nullptr, *dEps = nullptr, *dH1 = nullptr, *dG = nullptr;
+    // state
+    int R = 0, Rp = 0;
+    bool have_state = false;
+    DenseConfig cfg{};
+    float *psi[3] = {nullptr, nullptr, nullptr};
+    float *gam = nullptr, *gam_s = nullptr, *acc_psi = nullptr, *acc_gam = nullptr;
+    float *D = nullptr;
+    double *partial = nullptr, *dE = nullptr;
+    int *flags = nullptr, *dBest = nullptr, *dCount = nullptr;
+    int cur = 0;
+    // stats
+    int64_t steps_done = 0, spin_updates = 0, launches_timed = 0;
+    double run_seconds = 0.0, kernel_ms = 0.0;
+    int diverged = 0, target_reached = 0, best_index = -1;
+    double ttt_seconds = 0.0, best_energy = HUGE_VAL;
+    int64_t ttt_steps = 0;
+    std::vector<hipEvent_t> events;
+    int64_t ev_used = 0;       // events recorded by the current gd_run call
+
+    long long plane() const { return (long long)Rp * Np; }
+    bool complex_mode() const { return model == GD_XY; }
+    int integrator() const { return prm.integrator; }
+};
+
+namespace {
+
+void free_state(gd_solver *s) {
+    for (float *&p : s->psi) { if (p) (void)hipFree(p); p = nullptr; }
+    float **fl[] = {&s->gam, &s->gam_s, &s->acc_psi, &s->acc_gam, &s->D};
+    for (float **p : fl) { if (*p) (void)hipFree(*p); *p = nullptr; }
+    if (s->partial) (void)hipFree(s->partial);
+    if (s->dE) (void)hipFree(s->dE);
+    if (s->flags) (void)hipFree(s->flags);
+    if (s->dBest) (void)hipFree(s->dBest);
+    if (s->dCount) (void)hipFree(s->dCount);
+    s->partial = s->dE = nullptr;
+    s->flags = s->dBest = s->dCount = nullptr;
+    s->have_state = false;
+    s->R = s->Rp = 0;
+}
+
+void reset_stats(gd_solver *s) {
+    s->steps_done = s->spin_updates = s->launches_timed = 0;
+    s->run_seconds = s->kernel_ms = 0.0;
+    s->diverged = s->target_reached = 0;
+    s->best_index = -1;
+    s->ttt_seconds = 0.0;
+    s->ttt_steps = 0;
+    s->best_energy = HUGE_VAL;
+}
+
+template <class T>
+int dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? GD_E_OOM : GD_E_DEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return GD_OK;
+}
+
+int alloc_state(gd_solver *s, int R) {
+    free_state(s);
+    s->R = R;
+    s->Rp = (int)round_up(R, kTrajAlign);
+    const size_t pl = (size_t)s->plane();
+    const size_t P = (size_t)s->P;
+    int rc = GD_OK;
+    const int npsi = s->integrator() == GD_RK4 ? 3 : 2;
+    for (int k = 0; k < npsi && rc == GD_OK; ++k) rc = dalloc(&s->psi[k], pl * P);
+    if (rc == GD_OK) rc = dalloc(&s->gam, pl);
+    if (rc == GD_OK && s->integrator() == GD_RK4) {
+        rc = dalloc(&s->gam_s, pl);
+        if (rc == GD_OK) rc = dalloc(&s->acc_psi, pl * P);
+        if (rc == GD_OK) rc = dalloc(&s->acc_gam, pl);
+    }
+    if (rc == GD_OK) rc = dalloc(&s->D, pl * P);
+    if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / kRowTile) * s->Rp);
+    if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp);
+    if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
+    if (rc == GD_OK) rc = dalloc(&s->dBest, 1);
+    if (rc == GD_OK) rc = dalloc(&s->dCount, 1);
+    if (rc != GD_OK) {
+        free_state(s);
+        return rc;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (s->psi[k]) GD_HIP(hipMemsetAsync(s->psi[k], 0, pl * P * sizeof(float), s->stream));
+    GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
+    s->cur = 0;
+    s->have_state = true;
+    return GD_OK;
+}
+
+DenseStepArgs base_args(gd_solver *s) {
+    DenseStepArgs a{};
+    a.J = s->dJ;
+    a.eps = s->dEps;
+    a.h1 = s->dH1;
+    a.g = s->dG;
+    a.flags = s->flags;
+    a.partial = s->partial;
+    a.plane_stride = s->plane();
+    a.Np = s->Np;
+    a.Rp = s->Rp;
+    a.n = s->n;
+    a.R = s->R;
+    a.inv_s = float(1.0 / s->s);
+    a.dt = float(s->prm.dt);
+    a.gamma_c = float(s->prm.gamma_c);
+    a.rho_th = float(s->prm.rho_th);
+    return a;
+}
+
+// Enqueue one integration step.  `dt_override` >= 0 replaces dt (used with
+// 0 by the tuner: the state is then left bit-for-bit unchanged).
+int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed) {
+    DenseStepArgs a = base_args(s);
+    if (dt_override >= 0.0f) a.dt = dt_override;
+    const bool cx = s->complex_mode();
+    auto launch = [&](int mode, const DenseStepArgs &x) -> int {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            const size_t k = (size_t)s->ev_used * 2;
+            while (s->events.size() < k + 2) {
+                hipEvent_t e;
+                GD_HIP(hipEventCreate(&e));
+                s->events.push_back(e);
+            }
+            e0 = s->events[k];
+            e1 = s->events[k + 1];
+            GD_HIP(hipEventRecord(e0, s->stream));
+        }
+        GD_HIP(launch_dense_step(cfg, cx, mode, OP_F32, x, s->stream));
+        if (timed) {
+            GD_HIP(hipEventRecord(e1, s->stream));
+            s->ev_used++;
+        }
+        return GD_OK;
+    };
+    int rc;
+    if (s->integrator() == GD_EULER) {
+        a.B = s->psi[s->cur];
+        a.psi_in = s->psi[s->cur];
+        a.psi_out = s->psi[s->cur ^ 1];
+        a.gam_in = s->gam;
+        a.gam_out = s->gam;
+        if ((rc = launch(MODE_EULER, a)) != GD_OK) return rc;
+        s->cur ^= 1;
+        return GD_OK;
+    }
+    float *Y = s->psi[s->cur], *Sa = s->psi[s->cur ^ 1], *Sb = s->psi[2];
+    a.y_psi = Y;
+    a.y_gam = s->gam;
+    a.acc_psi = s->acc_psi;
+    a.acc_gam = s->acc_gam;
+    // stage 1: input y
+    a.B = Y; a.psi_in = Y; a.gam_in = s->gam; a.psi_out = Sa; a.gam_out = s->gam_s;
+    if ((rc = launch(MODE_RK1, a)) != GD_OK) return rc;
+    a.B = Sa; a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Sb; a.gam_out = s->gam_s;
+    if ((rc = launch(MODE_RK2, a)) != GD_OK) return rc;
+    a.B = Sb; a.psi_in = Sb; a.gam_in = s->gam_s; a.psi_out = Sa; a.gam_out = s->gam_s;
+    if ((rc = launch(MODE_RK3, a)) != GD_OK) return rc;
+    a.B = Sa; a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Y; a.gam_out = s->gam;
+    if ((rc = launch(MODE_RK4, a)) != GD_OK) return rc;
+    return GD_OK;
+}
+
+// Pick the dense kernel variant: GD_DENSE_CONFIG forces one; otherwise each
+// variant is timed on the live buffers with dt = 0 (state unchanged) and the
+// fastest is cached per (model, Np, Rp, integrator).
+int choose_config(gd_solver *s) {
+    const bool cx = s->complex_mode();
+    const int nc = dense_config_count(cx);
+    if (const char *env = std::getenv("GD_DENSE_CONFIG")) {
+        int id = std::atoi(env);
+        if (id < 0 || id >= nc) return fail(GD_E_INVALID_ARG, "GD_DENSE_CONFIG out of range");
+        s->cfg = dense_config(cx, id);
+        return GD_OK;
+    }
+    auto key = std::make_tuple(int(cx), s->Np, s->Rp, s->integrator());
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            s->cfg = dense_config(cx, it->second);
+            return GD_OK;
+        }
+    }
+    // tiny problems: no point timing
+    const long long work = (long long)s->Np * s->Np * s->Rp * s->P;
+    int best = 0;
+    if (work >= (1ll << 26)) {
+        hipEvent_t e0, e1;
+        GD_HIP(hipEventCreate(&e0));
+        GD_HIP(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        const int reps = 3;
+        for (int id = 0; id < nc; ++id) {
+            DenseConfig c = dense_config(cx, id);
+            int rc = enqueue_step(s, c, 0.0f, false);  // warm-up
+            if (rc != GD_OK) return rc;
+            GD_HIP(hipEventRecord(e0, s->stream));
+            for (int k = 0; k < reps; ++k)
+                if ((rc = enqueue_step(s, c, 0.0f, false)) != GD_OK) return rc;
+            GD_HIP(hipEventRecord(e1, s->stream));
+            GD_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            GD_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = id; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
+    } else {
+        // most workgroups while keeping >= 2 trajectory blocks of work per wave
+        best = cx ? 0 : 0;
+    }
+    s->cfg = dense_config(cx, best);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return GD_OK;
+}
+
+int check_params(const gd_params *p) {
+    if (p->struct_size != sizeof(gd_params)) return fail(GD_E_INVALID_ARG, "gd_params.struct_size mismatch");
+    if (p->integrator != GD_EULER && p->integrator != GD_RK4) return fail(GD_E_INVALID_ARG, "unknown integrator");
+    if (p->precision < GD_PREC_FP32 || p->precision > GD_PREC_FP16) return fail(GD_E_INVALID_ARG, "unknown precision");
+    if (!(std::isfinite(p->dt) && p->dt > 0)) return fail(GD_E_INVALID_ARG, "dt must be finite and > 0");
+    if (!std::isfinite(p->eps) || !std::isfinite(p->rho_th) || !std::isfinite(p->gamma_c) ||
+        !std::isfinite(p->gamma0) || !std::isfinite(p->init_amp))
+        return fail(GD_E_INVALID_ARG, "non-finite parameter");
+    if (!(std::isfinite(p->j_scale) && p->j_scale >= 0)) return fail(GD_E_INVALID_ARG, "j_scale must be >= 0");
+    if (p->check_interval < 0) return fail(GD_E_INVALID_ARG, "check_interval must be >= 0");
+    return GD_OK;
+}
+
+int copy_in(const gd_solver *s, const float *src, size_t count, std::vector<float> &dst) {
+    dst.resize(count);
+    if (count == 0) return GD_OK;
+    if (s->prm.flags & GD_F_DEVICE_PTRS) {
+        GD_HIP(hipMemcpy(dst.data(), src, count * sizeof(float), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(dst.data(), src, count * sizeof(float));
+    }
+    return GD_OK;
+}
+
+bool all_finite(const std::vector<float> &v) {
+    for (float x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+// user [R][n](x P) host/device -> device planes
+int upload_planes(gd_solver *s, const float *user, float *planes, int R) {
+    const size_t cnt = (size_t)R * s->n * s->P;
+    float *tmp = nullptr;
+    int rc = dalloc(&tmp, cnt);
+    if (rc != GD_OK) return rc;
+    hipError_t e;
+    if (s->prm.flags & GD_F_DEVICE_PTRS)
+        e = hipMemcpyAsync(tmp, user, cnt * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+    else
+        e = hipMemcpyAsync(tmp, user, cnt * sizeof(float), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_pack_planes(tmp, planes, s->n, R, s->Np, s->Rp, s->P, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(GD_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    return GD_OK;
+}
+
+int download_planes(gd_solver *s, const float *planes, float *user, int P) {
+    const size_t cnt = (size_t)s->R * s->n * P;
+    float *tmp = nullptr;
+    int rc = dalloc(&tmp, cnt);
+    if (rc != GD_OK) return rc;
+    hipError_t e = launch_unpack_planes(planes, tmp, s->n, s->R, s->Np, s->Rp, P, s->stream);
+    if (e == hipSuccess) {
+        if (s->prm.flags & GD_F_DEVICE_PTRS)
+            e = hipMemcpyAsync(user, tmp, cnt * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+        else
+            e = hipMemcpyAsync(user, tmp, cnt * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(GD_E_DEVICE, std::string("download: ") + hipGetErrorString(e));
+    return GD_OK;
+}
+
+int set_eps(gd_solver *s, const float *eps) {
+    std::vector<float> pad((size_t)s->Np, 0.0f);
+    if (eps) {
+        std::vector<float> e;
+        int rc = copy_in(s, eps, (size_t)s->n, e);
+        if (rc != GD_OK) return rc;
+        if (!all_finite(e)) return fail(GD_E_NONFINITE, "eps has non-finite entries");
+        s->hEps = e;
+    } else {
+        s->hEps.assign((size_t)s->n, float(s->prm.eps));
+    }
+    std::copy(s->hEps.begin(), s->hEps.end(), pad.begin());
+    GD_HIP(hipMemcpy(s->dEps, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
+    return GD_OK;
+}
+
+int default_init(gd_solver *s, int R, const float *gamma0) {
+    const int n = s->n, P = s->P;
+    std::vector<float> h((size_t)R * n * P);
+    const double amp = s->prm.init_amp;
+    for (int r = 0; r < R; ++r)
+        for (int i = 0; i < n; ++i) {
+            const uint64_t ctr = (uint64_t)r * (uint64_t)n + (uint64_t)i;
+            const double u = uniform01(s->prm.seed, ctr);
+            if (P == 1) {
+                h[(size_t)r * n + i] = float(amp * (2.0 * u - 1.0));
+            } else {
+                const double phi = 2.0 * M_PI * u;
+                h[((size_t)r * n + i) * 2] = float(amp * std::cos(phi));
+                h[((size_t)r * n + i) * 2 + 1] = float(amp * std::sin(phi));
+            }
+        }
+    const uint32_t saved = s->prm.flags;
+    s->prm.flags &= ~GD_F_DEVICE_PTRS;  // h is host memory
+    int rc = upload_planes(s, h.data(), s->psi[0], R);
+    const int savedP = s->P;
+    s->P = 1;
+    if (rc == GD_OK && !gamma0) {
+        std::vector<float> g((size_t)R * n, float(s->prm.gamma0));
+        rc = upload_planes(s, g.data(), s->gam, R);
+    }
+    s->prm.flags = saved;
+    if (rc == GD_OK && gamma0) rc = upload_planes(s, gamma0, s->gam, R);
+    s->P = savedP;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gd_default_params(gd_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(gd_params);
+    p->integrator = GD_EULER;
+    p->precision = GD_PREC_FP32;
+    p->flags = 0;
+    p->dt = 0.05;
+    p->eps = 0.1;
+    p->rho_th = 1.0;
+    p->gamma_c = 0.0;
+    p->gamma0 = 0.0;
+    p->j_scale = 0.0;
+    p->init_amp = 0.1;
+    p->seed = 0;
+    p->check_interval = 0;
+    p->has_target = 0;
+    p->target_energy = 0.0;
+    p->stream = nullptr;
+}
+
+const char *gd_error_string(int code) {
+    switch (code) {
+    case GD_OK: return "ok";
+    case GD_E_INVALID_ARG: return "invalid argument";
+    case GD_E_NOT_SYMMETRIC: return "J is not symmetric";
+    case GD_E_NONFINITE: return "non-finite input";
+    case GD_E_OOM: return "out of device memory";
+    case GD_E_DEVICE: return "device (HIP) error";
+    case GD_E_STATE: return "call out of order";
+    case GD_E_DIVERGED: return "a trajectory diverged";
+    case GD_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+    }
+}
+
+const char *gd_last_error(void) { return g_last_error.c_str(); }
+
+int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_t model,
+              const gd_params *p) {
+    if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 65536) return fail(GD_E_INVALID_ARG, "n out of range [1, 65536]");
+    if (!J) return fail(GD_E_INVALID_ARG, "J is NULL");
+    if (model != GD_ISING && model != GD_XY) return fail(GD_E_INVALID_ARG, "unknown model");
+    gd_params prm;
+    if (p) prm = *p;
+    else gd_default_params(&prm);
+    int rc = check_params(&prm);
+    if (rc != GD_OK) return rc;
+    if (prm.precision != GD_PREC_FP32)
+        return fail(GD_E_UNSUPPORTED, "only FP32 operands are implemented for dense solvers");
+
+    gd_solver *s = new (std::nothrow) gd_solver();
+    if (!s) return fail(GD_E_OOM, "host allocation failed");
+    s->n = n;
+    s->model = model;
+    s->P = model == GD_XY ? 2 : 1;
+    s->prm = prm;
+    s->Np = (int)round_up(n, kRowTile);
+    auto bail = [&](int code) {
+        gd_destroy(s);
+        return code;
+    };
+
+    std::vector<float> hj, hg;
+    if ((rc = copy_in(s, J, (size_t)n * n, hj)) != GD_OK) return bail(rc);
+    if (!all_finite(hj)) return bail(fail(GD_E_NONFINITE, "J has non-finite entries"));
+    if (g) {
+        if ((rc = copy_in(s, g, (size_t)n, hg)) != GD_OK) return bail(rc);
+        if (!all_finite(hg)) return bail(fail(GD_E_NONFINITE, "g has non-finite entries"));
+    }
+    double ss = 0.0;
+    bool integer = true;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            const float v = hj[(size_t)i * n + j];
+            if (v != hj[(size_t)j * n + i]) {
+                char buf[96];
+                std::snprintf(buf, sizeof buf, "J[%d][%d] != J[%d][%d]", i, j, j, i);
+                return bail(fail(GD_E_NOT_SYMMETRIC, buf));
+            }
+            ss += double(v) * double(v);
+            integer = integer && (v == std::nearbyint(v));
+        }
+    s->j_integer = integer;
+    for (float v : hg) s->g_integer = s->g_integer && (v == std::nearbyint(v));
+    s->s = prm.j_scale > 0 ? prm.j_scale : std::sqrt(ss / n);
+    if (!(s->s > 0)) s->s = 1.0;
+
+    if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(GD_E_DEVICE, "no HIP device"));
+    const int Np = s->Np;
+    s->hJ.assign((size_t)Np * Np, 0.0f);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            if (i != j) s->hJ[(size_t)i * Np + j] = hj[(size_t)i * n + j];
+    std::vector<float> h1((size_t)Np, 0.0f), gp((size_t)Np, 0.0f);
+    const double k1 = -std::sqrt(prm.rho_th) / s->s;
+    for (int i = 0; i < (int)hg.size(); ++i) {
+        h1[i] = float(k1 * hg[i]);
+        gp[i] = hg[i];
+    }
+
+    if (prm.stream) {
+        s->stream = static_cast<hipStream_t>(prm.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(GD_E_DEVICE, "hipStreamCreate failed"));
+        s->own_stream = true;
+    }
+    if ((rc = dalloc(&s->dJ, (size_t)Np * Np)) != GD_OK) return bail(rc);
+    if ((rc = dalloc(&s->dEps, (size_t)Np)) != GD_OK) return bail(rc);
+    if ((rc = dalloc(&s->dH1, (size_t)Np)) != GD_OK) return bail(rc);
+    if ((rc = dalloc(&s->dG, (size_t)Np)) != GD_OK) return bail(rc);
+    if (hipMemcpy(s->dJ, s->hJ.data(), s->hJ.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->dH1, h1.data(), h1.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->dG, gp.data(), gp.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(GD_E_DEVICE, "upload of J failed"));
+    if ((rc = set_eps(s, nullptr)) != GD_OK) return bail(rc);
+    *out = s;
+    return GD_OK;
+}
+
+void gd_destroy(gd_solver *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_state(s);
+    if (s->dJ) (void)hipFree(s->dJ);
+    if (s->dEps) (void)hipFree(s->dEps);
+    if (s->dH1) (void)hipFree(s->dH1);
+    if (s->dG) (void)hipFree(s->dG);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gamma0,
+                const float *eps) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (batch < 1 || batch > (1 << 22)) return fail(GD_E_INVALID_ARG, "batch out of range");
+    int rc;
+    if ((rc = set_eps(s, eps)) != GD_OK) return rc;
+    if (psi0 || gamma0) {
+        std::vector<float> chk;
+        if (psi0) {
+            if ((rc = copy_in(s, psi0, (size_t)batch * s->n * s->P, chk)) != GD_OK) return rc;
+            if (!all_finite(chk)) return fail(GD_E_NONFINITE, "psi0 has non-finite entries");
+        }
+        if (gamma0) {
+            if ((rc = copy_in(s, gamma0, (size_t)batch * s->n, chk)) != GD_OK) return rc;
+            if (!all_finite(chk)) return fail(GD_E_NONFINITE, "gamma0 has non-finite entries");
+        }
+    }
+    if ((rc = alloc_state(s, batch)) != GD_OK) return rc;
+    reset_stats(s);
+    if (psi0) {
+        if ((rc = upload_planes(s, psi0, s->psi[0], batch)) != GD_OK) return rc;
+        const int savedP = s->P;
+        s->P = 1;
+        if (gamma0) {
+            rc = upload_planes(s, gamma0, s->gam, batch);
+        } else {
+            std::vector<float> g((size_t)batch * s->n, float(s->prm.gamma0));
+            const uint32_t saved = s->prm.flags;
+            s->prm.flags &= ~GD_F_DEVICE_PTRS;
+            rc = upload_planes(s, g.data(), s->gam, batch);
+            s->prm.flags = saved;
+        }
+        s->P = savedP;
+        if (rc != GD_OK) return rc;
+    } else {
+        if ((rc = default_init(s, batch, gamma0)) != GD_OK) return rc;
+    }
+    return choose_config(s);
+}
+
+int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (steps < 0) return fail(GD_E_INVALID_ARG, "steps must be >= 0");
+    int rc;
+    if (!s->have_state) {
+        if ((rc = gd_set_init(s, batch, nullptr, nullptr, nullptr)) != GD_OK) return rc;
+    } else if (batch != s->R) {
+        return fail(GD_E_INVALID_ARG, "batch differs from the current number of trajectories");
+    }
+    const bool timed = (s->prm.flags & GD_F_PROFILE) != 0;
+    s->ev_used = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int ci = s->prm.check_interval;
+    int64_t done = 0;
+    while (done < steps) {
+        int64_t chunk = steps - done;
+        if (ci > 0) {
+            const int64_t to_check = ci - (s->steps_done % ci);
+            chunk = std::min<int64_t>(chunk, to_check);
+        }
+        for (int64_t k = 0; k < chunk; ++k)
+            if ((rc = enqueue_step(s, s->cfg, -1.0f, timed)) != GD_OK) return rc;
+        done += chunk;
+        s->steps_done += chunk;
+        s->spin_updates += (int64_t)s->n * s->R * chunk;
+        if (ci > 0 && s->steps_done % ci == 0) {
+            // device check: discretise, energy GEMM, deterministic reduction
+            const float *cur = s->psi[s->cur];
+            GD_HIP(launch_discretise(cur, s->D, nullptr, OP_F32, nullptr, nullptr, s->flags, s->n,
+                                     s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
+            DenseStepArgs a = base_args(s);
+            a.B = s->D;
+            a.psi_in = s->D;
+            GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
+            GD_HIP(launch_energy_reduce(s->partial, s->Np / kRowTile, s->Rp, s->R, s->dE, s->dBest,
+                                        s->stream));
+            double emin = 0.0;
+            int bi = 0;
+            GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+            GD_HIP(hipStreamSynchronize(s->stream));
+            GD_HIP(hipMemcpy(&emin, s->dE + bi, sizeof(double), hipMemcpyDeviceToHost));
+            if (emin < s->best_energy) {
+                s->best_energy = emin;
+                s->best_index = bi;
+            }
+            if (s->prm.has_target && !s->target_reached && emin <= s->prm.target_energy) {
+                s->target_reached = 1;
+                s->ttt_steps = s->steps_done;
+                s->ttt_seconds = s->run_seconds +
+                                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                break;
+            }
+        }
+    }
+    if (s->prm.flags & GD_F_ASYNC) return GD_OK;
+    GD_HIP(hipStreamSynchronize(s->stream));
+    s->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (timed) {
+        for (int64_t k = 0; k < s->ev_used; ++k) {
+            float ms = 0.0f;
+            GD_HIP(hipEventElapsedTime(&ms, s->events[(size_t)k * 2], s->events[(size_t)k * 2 + 1]));
+            s->kernel_ms += ms;
+        }
+        s->launches_timed += s->ev_used;
+        s->ev_used = 0;
+    }
+    GD_HIP(launch_count_flags(s->flags, s->R, s->dCount, s->stream));
+    int cnt = 0;
+    GD_HIP(hipMemcpyAsync(&cnt, s->dCount, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
+    s->diverged = cnt;
+    if (cnt) {
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%d trajectories became non-finite", cnt);
+        return fail(GD_E_DIVERGED, buf);
+    }
+    return GD_OK;
+}
+
+static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (!s->have_state) return fail(GD_E_STATE, "no state: call gd_set_init or gd_run first");
+    if (!E) return fail(GD_E_INVALID_ARG, "E is NULL");
+    const float *cur = s->psi[s->cur];
+    GD_HIP(launch_discretise(cur, s->D, nullptr, OP_F32, nullptr, nullptr, s->flags, s->n, s->R,
+                             s->Np, s->Rp, s->P, s->plane(), s->stream));
+    if (fp64) {
+        GD_HIP(launch_energy_fp64(s->dJ, cur, s->dG, s->partial, s->Np, s->Rp, s->n, s->R, s->P,
+                                  s->plane(), s->stream));
+    } else {
+        DenseStepArgs a = base_args(s);
+        a.B = s->D;
+        a.psi_in = s->D;
+        GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
+    }
+    GD_HIP(launch_energy_reduce(s->partial, s->Np / kRowTile, s->Rp, s->R, s->dE, s->dBest, s->stream));
+    int bi = 0;
+    if (s->prm.flags & GD_F_DEVICE_PTRS) {
+        GD_HIP(hipMemcpyAsync(E, s->dE, sizeof(double) * s->R, hipMemcpyDeviceToDevice, s->stream));
+        if (best) GD_HIP(hipMemcpyAsync(best, s->dBest, sizeof(int), hipMemcpyDeviceToDevice, s->stream));
+    } else {
+        GD_HIP(hipMemcpyAsync(E, s->dE, sizeof(double) * s->R, hipMemcpyDeviceToHost, s->stream));
+        GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    }
+    GD_HIP(hipStreamSynchronize(s->stream));
+    if (best && !(s->prm.flags & GD_F_DEVICE_PTRS)) *best = bi;
+    return GD_OK;
+}
+
+int gd_energy(gd_solver *s, double *E, int32_t *best) { return energies(s, E, best, true); }
+
+int gd_energy_device(gd_solver *s, double *E, int32_t *best) { return energies(s, E, best, false); }
+
+int gd_spins(gd_solver *s, void *out, int32_t fmt) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (!s->have_state) return fail(GD_E_STATE, "no state");
+    if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+    if (fmt != GD_SPINS_I8 && fmt != GD_SPINS_ANGLE_F32) return fail(GD_E_INVALID_ARG, "unknown format");
+    if (fmt == GD_SPINS_I8 && s->model != GD_ISING)
+        return fail(GD_E_INVALID_ARG, "int8 spins need the Ising model");
+    const size_t cnt = (size_t)s->R * s->n;
+    const size_t bytes = cnt * (fmt == GD_SPINS_I8 ? 1 : 4);
+    void *tmp = nullptr;
+    GD_HIP(hipMalloc(&tmp, bytes));
+    hipError_t e = launch_discretise(s->psi[s->cur], s->D, nullptr, OP_F32,
+                                     fmt == GD_SPINS_I8 ? static_cast<int8_t *>(tmp) : nullptr,
+                                     fmt == GD_SPINS_ANGLE_F32 ? static_cast<float *>(tmp) : nullptr,
+                                     s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(), s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, tmp, bytes,
+                           (s->prm.flags & GD_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(GD_E_DEVICE, std::string("gd_spins: ") + hipGetErrorString(e));
+    return GD_OK;
+}
+
+int gd_get_state(gd_solver *s, float *psi, float *gamma, int64_t *step) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (!s->have_state) return fail(GD_E_STATE, "no state");
+    int rc;
+    if (psi && (rc = download_planes(s, s->psi[s->cur], psi, s->P)) != GD_OK) return rc;
+    if (gamma && (rc = download_planes(s, s->gam, gamma, 1)) != GD_OK) return rc;
+    if (step) *step = s->steps_done;
+    return GD_OK;
+}
+
+int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gamma, int64_t step) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (!psi || !gamma) return fail(GD_E_INVALID_ARG, "psi and gamma are required");
+    if (batch < 1 || batch > (1 << 22) || step < 0) return fail(GD_E_INVALID_ARG, "bad batch or step");
+    std::vector<float> chk;
+    int rc;
+    if ((rc = copy_in(s, psi, (size_t)batch * s->n * s->P, chk)) != GD_OK) return rc;
+    if (!all_finite(chk)) return fail(GD_E_NONFINITE, "psi has non-finite entries");
+    if ((rc = copy_in(s, gamma, (size_t)batch * s->n, chk)) != GD_OK) return rc;
+    if (!all_finite(chk)) return fail(GD_E_NONFINITE, "gamma has non-finite entries");
+    if (!s->have_state || batch != s->R) {
+        if ((rc = alloc_state(s, batch)) != GD_OK) return rc;
+        reset_stats(s);
+        if ((rc = choose_config(s)) != GD_OK) return rc;
+    }
+    s->cur = 0;
+    if ((rc = upload_planes(s, psi, s->psi[0], batch)) != GD_OK) return rc;
+    const int savedP = s->P;
+    s->P = 1;
+    rc = upload_planes(s, gamma, s->gam, batch);
+    s->P = savedP;
+    if (rc != GD_OK) return rc;
+    GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
+    s->steps_done = step;
+    return GD_OK;
+}
+
+int gd_stats(gd_solver *s, gd_run_stats *out) {
+    if (!s || !out) return fail(GD_E_INVALID_ARG, "NULL argument");
+    if (out->struct_size != sizeof(gd_run_stats)) return fail(GD_E_INVALID_ARG, "gd_run_stats.struct_size mismatch");
+    out->batch = s->R;
+    out->steps_done = s->steps_done;
+    out->spin_updates = s->spin_updates;
+    out->run_seconds = s->run_seconds;
+    out->kernel_ms = s->kernel_ms;
+    out->kernel_launches = s->launches_timed;
+    out->diverged = s->diverged;
+    out->target_reached = s->target_reached;
+    out->ttt_seconds = s->ttt_seconds;
+    out->ttt_steps = s->ttt_steps;
+    out->best_energy = s->best_energy;
+    out->best_index = s->best_index;
+    out->kernel_config = s->cfg.id;
+    return GD_OK;
+}
+
+int gd_coupling_scale(gd_solver *s, double *scale) {
+    if (!s || !scale) return fail(GD_E_INVALID_ARG, "NULL argument");
+    *scale = s->s;
+    return GD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+"""Python binding of libgd.so (include/gd.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+(host pointers) or torch CUDA/HIP tensors (device pointers, with
+GD_F_DEVICE_PTRS) into the plain pointers and sizes of the C ABI, and turns
+negative return codes into ``GDError``.  Loading fails loudly when the
+library has not been built (``python -m paper_1807_00699_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgd.so")
+
+# enums / flags (mirror include/gd.h)
+GD_OK = 0
+GD_E_INVALID_ARG, GD_E_NOT_SYMMETRIC, GD_E_NONFINITE, GD_E_OOM = -1, -2, -3, -4
+GD_E_DEVICE, GD_E_STATE, GD_E_DIVERGED, GD_E_UNSUPPORTED = -5, -6, -7, -8
+GD_ISING, GD_XY = 0, 1
+GD_EULER, GD_RK4 = 0, 1
+GD_PREC_FP32, GD_PREC_BF16, GD_PREC_FP16 = 0, 1, 2
+GD_SPINS_I8, GD_SPINS_ANGLE_F32 = 0, 1
+GD_F_DEVICE_PTRS, GD_F_ASYNC, GD_F_PROFILE = 0x1, 0x2, 0x4
+
+# exported symbols of include/gd.h
+EXPORTS = (
+    "gd_default_params", "gd_create", "gd_destroy", "gd_set_init", "gd_run", "gd_energy",
+    "gd_energy_device", "gd_spins", "gd_get_state", "gd_set_state", "gd_stats",
+    "gd_coupling_scale", "gd_error_string", "gd_last_error",
+)
+
+
+class gd_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("integrator", C.c_int32), ("precision", C.c_int32),
+        ("flags", C.c_uint32), ("dt", C.c_double), ("eps", C.c_double), ("rho_th", C.c_double),
+        ("gamma_c", C.c_double), ("gamma0", C.c_double), ("j_scale", C.c_double),
+        ("init_amp", C.c_double), ("seed", C.c_uint64), ("check_interval", C.c_int32),
+        ("has_target", C.c_int32), ("target_energy", C.c_double), ("stream", C.c_void_p),
+    ]
+
+
+class gd_run_stats(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("batch", C.c_int32), ("steps_done", C.c_int64),
+        ("spin_updates", C.c_int64), ("run_seconds", C.c_double), ("kernel_ms", C.c_double),
+        ("kernel_launches", C.c_int64), ("diverged", C.c_int32), ("target_reached", C.c_int32),
+        ("ttt_seconds", C.c_double), ("ttt_steps", C.c_int64), ("best_energy", C.c_double),
+        ("best_index", C.c_int32), ("kernel_config", C.c_int32),
+    ]
+
+
+class GDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgd.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_1807_00699_amd.build`")
+    # torch ships its own HIP runtime with the same SONAME as ROCm's.  Loading
+    # torch first makes libgd.so bind to that copy, so the process has one HIP
+    # runtime and torch tensors / streams are valid handles for the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.gd_default_params.argtypes = [C.POINTER(gd_params)]
+    lib.gd_default_params.restype = None
+    lib.gd_create.argtypes = [C.POINTER(vp), i32, vp, vp, i32, C.POINTER(gd_params)]
+    lib.gd_destroy.argtypes = [vp]
+    lib.gd_destroy.restype = None
+    lib.gd_set_init.argtypes = [vp, i32, vp, vp, vp]
+    lib.gd_run.argtypes = [vp, i32, i64]
+    lib.gd_energy.argtypes = [vp, vp, vp]
+    lib.gd_energy_device.argtypes = [vp, vp, vp]
+    lib.gd_spins.argtypes = [vp, vp, i32]
+    lib.gd_get_state.argtypes = [vp, vp, vp, vp]
+    lib.gd_set_state.argtypes = [vp, i32, vp, vp, i64]
+    lib.gd_stats.argtypes = [vp, C.POINTER(gd_run_stats)]
+    lib.gd_coupling_scale.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.gd_error_string.argtypes = [C.c_int]
+    lib.gd_error_string.restype = C.c_char_p
+    lib.gd_last_error.argtypes = []
+    lib.gd_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("gd_default_params", "gd_destroy", "gd_error_string", "gd_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != GD_OK:
+        msg = load().gd_last_error().decode(errors="replace")
+        raise GDError(rc, f"{what}: {msg}")
+
+
+def _ptr(a, dtype=np.float32, device=False):
+    """Pointer of a numpy array (host) or torch tensor (device); None -> NULL."""
+    if a is None:
+        return None, None
+    if device:
+        return C.c_void_p(a.data_ptr()), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(C.c_void_p), arr
+
+
+def default_params(**kw) -> gd_params:
+    p = gd_params()
+    load().gd_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------- C-named calls
+
+def gd_create(J, g=None, model=GD_ISING, params: gd_params | None = None):
+    """Returns an opaque handle (c_void_p).  J: [n][n] float32 (numpy, or a
+    device tensor when params.flags has GD_F_DEVICE_PTRS)."""
+    lib = load()
+    dev = bool(params is not None and params.flags & GD_F_DEVICE_PTRS)
+    n = int(J.shape[0])
+    if tuple(J.shape) != (n, n):
+        raise ValueError("J must be square")
+    pj, _kj = _ptr(J, device=dev)
+    pg, _kg = _ptr(g, device=dev)
+    h = C.c_void_p()
+    _check(lib.gd_create(C.byref(h), n, pj, pg, int(model),
+                         C.byref(params) if params is not None else None), "gd_create")
+    return h
+
+
+def gd_destroy(h):
+    load().gd_destroy(h)
+
+
+def gd_set_init(h, batch, psi0=None, gamma0=None, eps=None, device=False):
+    p0, _a = _ptr(psi0, device=device)
+    pg, _b = _ptr(gamma0, device=device)
+    pe, _c = _ptr(eps, device=device)
+    _check(load().gd_set_init(h, int(batch), p0, pg, pe), "gd_set_init")
+
+
+def gd_run(h, batch, steps):
+    rc = load().gd_run(h, int(batch), int(steps))
+    _check(rc, "gd_run")
+
+
+def gd_energy(h, batch, device_path=False):
+    """Energies [batch] (float64) and argmin."""
+    E = np.empty(int(batch), np.float64)
+    best = C.c_int32()
+    fn = load().gd_energy_device if device_path else load().gd_energy
+    _check(fn(h, E.ctypes.data_as(C.c_void_p), C.byref(best)), "gd_energy")
+    return E, int(best.value)
+
+
+def gd_spins(h, batch, n, fmt=GD_SPINS_I8):
+    out = np.empty((int(batch), int(n)), np.int8 if fmt == GD_SPINS_I8 else np.float32)
+    _check(load().gd_spins(h, out.ctypes.data_as(C.c_void_p), int(fmt)), "gd_spins")
+    return out
+
+
+def gd_get_state(h, batch, n, complex_mode):
+    psi = np.empty((batch, n, 2) if complex_mode else (batch, n), np.float32)
+    gam = np.empty((batch, n), np.float32)
+    step = C.c_int64()
+    _check(load().gd_get_state(h, psi.ctypes.data_as(C.c_void_p), gam.ctypes.data_as(C.c_void_p),
+                               C.byref(step)), "gd_get_state")
+    return psi, gam, int(step.value)
+
+
+def gd_set_state(h, batch, psi, gamma, step=0):
+    pp, _a = _ptr(psi)
+    pg, _b = _ptr(gamma)
+    _check(load().gd_set_state(h, int(batch), pp, pg, int(step)), "gd_set_state")
+
+
+def gd_stats(h) -> gd_run_stats:
+    st = gd_run_stats()
+    st.struct_size = C.sizeof(gd_run_stats)
+    _check(load().gd_stats(h, C.byref(st)), "gd_stats")
+    return st
+
+
+def gd_coupling_scale(h) -> float:
+    v = C.c_double()
+    _check(load().gd_coupling_scale(h, C.byref(v)), "gd_coupling_scale")
+    return float(v.value)
+
+
+class Solver:
+    """Owning wrapper of one gd_solver handle (host arrays)."""
+
+    def __init__(self, J, g=None, model=GD_ISING, **params):
+        self.n = int(J.shape[0])
+        self.model = model
+        self.params = default_params(**params)
+        self.h = gd_create(np.asarray(J, np.float32), None if g is None else np.asarray(g, np.float32),
+                           model, self.params)
+        self.batch = 0
+
+    def close(self):
+        if self.h is not None:
+            gd_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_init(self, batch, psi0=None, gamma0=None, eps=None):
+        gd_set_init(self.h, batch, psi0, gamma0, eps)
+        self.batch = int(batch)
+
+    def run(self, steps, batch=None):
+        gd_run(self.h, self.batch if batch is None else batch, steps)
+        if batch is not None:
+            self.batch = int(batch)
+
+    def state(self):
+        return gd_get_state(self.h, self.batch, self.n, self.model == GD_XY)
+
+    def set_state(self, psi, gamma, step=0):
+        psi = np.asarray(psi, np.float32)
+        gd_set_state(self.h, psi.shape[0], psi, gamma, step)
+        self.batch = psi.shape[0]
+
+    def energy(self, device_path=False):
+        return gd_energy(self.h, self.batch, device_path)
+
+    def spins(self, fmt=None):
+        if fmt is None:
+            fmt = GD_SPINS_I8 if self.model == GD_ISING else GD_SPINS_ANGLE_F32
+        return gd_spins(self.h, self.batch, self.n, fmt)
+
+    def stats(self):
+        return gd_stats(self.h)
+
+    @property
+    def scale(self):
+        return gd_coupling_scale(self.h)
