@@ -47,8 +47,24 @@ def parse():
     ap.add_argument("--workload", default="xy1024", choices=sorted(WORKLOADS))
     ap.add_argument("--check", type=int, default=50, help="steps between device energy checks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB (reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain 256 MiB device-to-device copy, 5 times: the bytes it must move
+    are known (256 MiB read + 256 MiB written per launch), so the FETCH_SIZE /
+    WRITE_SIZE counters it produces calibrate those of the solver kernels."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 5}), flush=True)
 
 
 def cpu_baseline(wl, J, psi0, target_s):
@@ -59,13 +75,13 @@ def cpu_baseline(wl, J, psi0, target_s):
     integ = O.RK4 if wl["integrator"] == "rk4" else O.EULER
     n = wl["n"]
     R_s = min(wl["R"], threads * 2)
-    steps = 1
+    steps = 2
     # pilot, then size the sample to ~target_s
     t0 = time.perf_counter()
     O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
           integrator=integ, nthreads=threads)
     pilot = time.perf_counter() - t0
-    steps = max(1, int(target_s / max(pilot, 1e-6)))
+    steps = max(1, int(target_s * steps / max(pilot, 1e-6)))
     steps = min(steps, wl["steps"])
     t0 = time.perf_counter()
     O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
@@ -83,6 +99,9 @@ def main():
               "so N GPUs would each run their own share of trajectories with no communication.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from paper_1807_00699_amd import gd

@@ -2,7 +2,7 @@
 //
 // One launch evaluates, for every spin i and trajectory r of a tile, the
 // coupling sum C_ir = (1/s) sum_j J_ij Psi_jr of Eq. (main) as a GEMM on the
-// matrix cores (v_mfma_f32_32x32x2_f32, FP32 in and out), and then applies the
+// matrix cores (v_mfma_f32_16x16x4_f32, FP32 in and out), and then applies the
 // pointwise part of Eq. (main) and Eq. (gamma) in the epilogue, so that the
 // coupling result never leaves registers:
 //   f   = Psi (gamma - gamma_c - |Psi|^2) + C + h_1
@@ -15,30 +15,27 @@
 // per-trajectory quantity is a plane [Rp][Np] (trajectory-major, spin index
 // contiguous).  The product is C[i][r] = sum_k J[i][k] Psi[r][k]: both
 // operands are K-contiguous, so global->LDS copies are plain 16-byte vector
-// loads and LDS holds both tiles as [row][k].
+// loads and LDS holds both tiles as [row][k] with a 4-float pad per row
+// (conflict-free 16-byte LDS reads).
 //
-// Tiling: a workgroup owns 64 rows x BN GEMM columns; two waves along rows
-// (32 rows each) and WN waves along columns.  Complex amplitudes use BN/2
-// trajectories, real part in LDS columns [0, BN/2) and imaginary part in
-// [BN/2, BN), arranged so that each wave holds the real and imaginary
-// accumulators of the same (i, r) in the same lane and register.
+// Tiling: a workgroup owns BM rows x BN GEMM columns, WM x WN waves; a wave
+// owns (BM/WM) x (BN/WN) as 16x16 MFMA blocks.  Complex amplitudes use BN/2
+// trajectories: the real parts sit in LDS columns [0, BN/2), the imaginary
+// parts in [BN/2, BN), and every wave takes matching real/imaginary blocks,
+// so the real and imaginary accumulators of one (i, r) live in the same lane
+// and register and the epilogue needs no data exchange.
 //
-// K order inside a 16-wide slice is permuted so that lane half h feeds
-// k = 8h + t to MFMA number t; A and B use the same permutation, so each lane
-// fetches 8 contiguous floats with two ds_read_b128 per operand block.
+// K order inside a 16-wide slice is permuted: lane group q = lane/16 feeds
+// k = 4q + t to MFMA number t (A and B use the same permutation), so each
+// lane fetches its 4 operands of a slice with one ds_read_b128.
 #include "gd_internal.h"
 
 namespace gd {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int BM = kRowTile;  // rows per workgroup
-constexpr int WM = 2;         // waves along rows
-constexpr int BK = 32;        // K chunk per pipeline stage
-constexpr int LDP = BK + 4;   // LDS row pitch in floats (conflict-free b128 reads)
 
 // Workgroup -> (row tile, column tile).  Consecutive workgroup ids land on
 // different XCDs (round-robin dispatch), so the linear id is first regrouped
@@ -58,18 +55,19 @@ __device__ inline void tile_map(int b, int nblk, int n_mt, int n_ct, int &mt, in
     ct = in / gsz;
 }
 
-__device__ inline bool finite4(float a) { return __builtin_isfinite(a); }
+__device__ inline bool fin(float a) { return __builtin_isfinite(a); }
 
-template <int BN, int WN, bool CPLX, int MODE>
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE>
 __global__ void __launch_bounds__(64 * WM * WN)
 dense_step_f32(DenseStepArgs a) {
+    constexpr int LDP = BK + 4;     // LDS row pitch in floats
     constexpr int NT = 64 * WM * WN;
-    constexpr int TM = BM / WM;     // 32 rows per wave
+    constexpr int TM = BM / WM;     // rows per wave
     constexpr int TN = BN / WN;     // GEMM columns per wave
-    constexpr int MB = TM / 32;     // MFMA row blocks per wave
-    constexpr int NB = TN / 32;     // MFMA column blocks per wave
+    constexpr int MB = TM / 16;     // 16-row MFMA blocks per wave
+    constexpr int NB = TN / 16;     // 16-column MFMA blocks per wave
+    constexpr int NP = CPLX ? NB / 2 : NB;   // trajectory blocks per wave
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
-    static_assert(MB == 1, "two waves of 32 rows");
     static_assert(!CPLX || (NB % 2 == 0), "complex waves pair re/im blocks");
     constexpr int KQ = BK / 4;                 // float4 per row chunk
     constexpr int AL = BM * KQ / NT;           // A float4 loads per thread
@@ -126,72 +124,68 @@ dense_step_f32(DenseStepArgs a) {
             *reinterpret_cast<f32x4 *>(&lds[buf][(BM + col) * LDP + kq * 4]) = rb[u];
         }
     };
-    // LDS column of block nb for this wave
+    // LDS column (within the B tile) of column block nb of this wave
     auto bcol = [&](int nb) -> int {
         if (CPLX) {
-            constexpr int half = NB / 2;
-            const int p = nb / half, tb = nb % half;
-            return p * (BN / 2) + wn * (TN / 2) + tb * 32;
+            const int p = nb / NP, tb = nb % NP;
+            return p * (BN / 2) + wn * (TN / 2) + tb * 16;
         }
-        return wn * TN + nb * 32;
+        return wn * TN + nb * 16;
     };
+    // trajectory offset (within the tile) of trajectory block tb of this wave
+    auto tcol = [&](int tb) -> int { return CPLX ? wn * (TN / 2) + tb * 16 : wn * TN + tb * 16; };
 
-    f32x16 acc[NB];
+    f32x4 acc[MB][NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int nk = a.Np / BK;
+    const int l16 = lane & 15;
+    const int lq = lane >> 4;
     gload(0);
     lstore(0);
     __syncthreads();
-    const int lrow = lane & 31;
-    const int lh = lane >> 5;
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         if (kc + 1 < nk) gload((kc + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 16; ++kk) {
-            const float *pa = &lds[buf][(wm * TM + lrow) * LDP + kk * 16 + lh * 8];
-            const f32x4 a0 = *reinterpret_cast<const f32x4 *>(pa);
-            const f32x4 a1 = *reinterpret_cast<const f32x4 *>(pa + 4);
-            f32x4 b0[NB], b1[NB];
+            f32x4 av[MB], bv[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const float *pb = &lds[buf][(BM + bcol(nb) + lrow) * LDP + kk * 16 + lh * 8];
-                b0[nb] = *reinterpret_cast<const f32x4 *>(pb);
-                b1[nb] = *reinterpret_cast<const f32x4 *>(pb + 4);
-            }
+            for (int mb = 0; mb < MB; ++mb)
+                av[mb] = *reinterpret_cast<const f32x4 *>(
+                    &lds[buf][(wm * TM + mb * 16 + l16) * LDP + kk * 16 + lq * 4]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[t], b0[nb][t], acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb)
+                bv[nb] = *reinterpret_cast<const f32x4 *>(
+                    &lds[buf][(BM + bcol(nb) + l16) * LDP + kk * 16 + lq * 4]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[t], b1[nb][t], acc[nb], 0, 0, 0);
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][t], bv[nb][t],
+                                                                          acc[mb][nb], 0, 0, 0);
         }
         if (kc + 1 < nk) lstore(buf ^ 1);
         __syncthreads();
     }
 
     // ---------------------------------------------------------------- epilogue
-    // acc[nb][4q + e] holds row i = m0 + wm*32 + 8q + 4*lh + e, column lrow of block nb.
-    const int ibase = m0 + wm * TM + 4 * lh;
-    constexpr int NP = CPLX ? NB / 2 : NB;   // trajectory blocks per wave
+    // acc[mb][nb][e] holds row i = m0 + wm*TM + mb*16 + 4*lq + e, column l16 of block nb.
     if constexpr (MODE == MODE_ENERGY) {
-        // e_ir = -sum_p D_p(i,r) T_p(i,r) + g_i D_0(i,r); reduce over the 64 rows.
+        // e_ir = -sum_p D_p(i,r) T_p(i,r) + g_i D_0(i,r); reduce over the tile's rows.
         double esum[NP];
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
-            const int r = r0 + (CPLX ? wn * (TN / 2) + tb * 32 : bcol(tb)) + lrow;
+            const int r = r0 + tcol(tb) + l16;
             double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i0 = ibase + 8 * q;
+            for (int mb = 0; mb < MB; ++mb) {
+                const int i0 = m0 + wm * TM + mb * 16 + 4 * lq;
                 const long long idx = (long long)r * Np + i0;
                 const f32x4 d0 = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
                 const f32x4 gg = *reinterpret_cast<const f32x4 *>(a.g + i0);
@@ -199,27 +193,28 @@ dense_step_f32(DenseStepArgs a) {
                 if (CPLX) d1 = *reinterpret_cast<const f32x4 *>(a.psi_in + a.plane_stride + idx);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    double t = -(double)d0[e] * (double)acc[tb][4 * q + e] + (double)gg[e] * (double)d0[e];
-                    if (CPLX) t -= (double)d1[e] * (double)acc[NP + tb][4 * q + e];
+                    double t = -(double)d0[e] * (double)acc[mb][tb][e] + (double)gg[e] * (double)d0[e];
+                    if (CPLX) t -= (double)d1[e] * (double)acc[mb][NP + tb][e];
                     s += t;
                 }
             }
+            s += __shfl_xor(s, 16);
             s += __shfl_xor(s, 32);
             esum[tb] = s;
         }
-        // combine the two row waves through LDS (main loop is done with it)
-        __syncthreads();
+        // combine the row waves through LDS (the main loop is done with it)
         double *red = reinterpret_cast<double *>(&lds[0][0]);
-        if (wm == 1 && lh == 0) {
+        if (lq == 0) {
 #pragma unroll
-            for (int tb = 0; tb < NP; ++tb) red[(wn * NP + tb) * 32 + lrow] = esum[tb];
+            for (int tb = 0; tb < NP; ++tb) red[(wm * WN + wn) * (NP * 16) + tb * 16 + l16] = esum[tb];
         }
         __syncthreads();
-        if (wm == 0 && lh == 0) {
+        if (wm == 0 && lq == 0) {
 #pragma unroll
             for (int tb = 0; tb < NP; ++tb) {
-                const int r = r0 + (CPLX ? wn * (TN / 2) + tb * 32 : bcol(tb)) + lrow;
-                a.partial[(long long)mt * a.Rp + r] = esum[tb] + red[(wn * NP + tb) * 32 + lrow];
+                double s = 0.0;
+                for (int w = 0; w < WM; ++w) s += red[(w * WN + wn) * (NP * 16) + tb * 16 + l16];
+                a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l16] = s;
             }
         }
         return;
@@ -227,12 +222,12 @@ dense_step_f32(DenseStepArgs a) {
         const float inv_s = a.inv_s, dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
-            const int r = r0 + (CPLX ? wn * (TN / 2) + tb * 32 : bcol(tb)) + lrow;
+            const int r = r0 + tcol(tb) + l16;
             const bool rvalid = r < a.R;
             bool bad = false;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i0 = ibase + 8 * q;
+            for (int mb = 0; mb < MB; ++mb) {
+                const int i0 = m0 + wm * TM + mb * 16 + 4 * lq;
                 const long long idx = (long long)r * Np + i0;
                 const f32x4 ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
                 const f32x4 hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
@@ -245,11 +240,11 @@ dense_step_f32(DenseStepArgs a) {
                 for (int e = 0; e < 4; ++e) {
                     const float rho = CPLX ? xr[e] * xr[e] + xi[e] * xi[e] : xr[e] * xr[e];
                     const float lin = gm[e] - gc - rho;
-                    fr[e] = xr[e] * lin + acc[tb][4 * q + e] * inv_s + hh[e];
-                    if (CPLX) fi[e] = xi[e] * lin + acc[NP + tb][4 * q + e] * inv_s;
+                    fr[e] = xr[e] * lin + acc[mb][tb][e] * inv_s + hh[e];
+                    fi[e] = CPLX ? xi[e] * lin + acc[mb][NP + tb][e] * inv_s : 0.0f;
                     fg[e] = ep[e] * (rho_th - rho);
                 }
-                // rows beyond n keep their (zero) state and gain
+                // rows beyond n and padded trajectories keep their (zero) state and gain
                 bool rowv[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) rowv[e] = rvalid && (i0 + e < a.n);
@@ -259,27 +254,23 @@ dense_step_f32(DenseStepArgs a) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         nr[e] = rowv[e] ? xr[e] + dt * fr[e] : xr[e];
-                        if (CPLX) ni[e] = rowv[e] ? xi[e] + dt * fi[e] : xi[e];
+                        ni[e] = rowv[e] ? xi[e] + dt * fi[e] : xi[e];
                         ng[e] = rowv[e] ? gm[e] + dt * fg[e] : gm[e];
-                        bad |= !(finite4(nr[e]) && finite4(ng[e]) && (!CPLX || finite4(ni[e])));
+                        bad |= !(fin(nr[e]) && fin(ng[e]) && fin(ni[e]));
                     }
                     *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
                     if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + a.plane_stride + idx) = ni;
                     *reinterpret_cast<f32x4 *>(a.gam_out + idx) = ng;
                 } else {
                     // RK4 stage on y = (psi, gamma); psi_in/gam_in is the stage input
-                    f32x4 yr, yi, yg;
-                    if constexpr (MODE == MODE_RK1) {
-                        yr = xr; yi = xi; yg = gm;
-                    } else {
+                    f32x4 yr = xr, yi = xi, yg = gm;
+                    if constexpr (MODE != MODE_RK1) {
                         yr = *reinterpret_cast<const f32x4 *>(a.y_psi + idx);
                         if (CPLX) yi = *reinterpret_cast<const f32x4 *>(a.y_psi + a.plane_stride + idx);
                         yg = *reinterpret_cast<const f32x4 *>(a.y_gam + idx);
                     }
-                    f32x4 ar, ai, ag;
-                    if constexpr (MODE == MODE_RK1) {
-                        ar = fr; ai = fi; ag = fg;
-                    } else {
+                    f32x4 ar = fr, ai = fi, ag = fg;
+                    if constexpr (MODE != MODE_RK1) {
                         ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
                         if (CPLX) ai = *reinterpret_cast<const f32x4 *>(a.acc_psi + a.plane_stride + idx);
                         ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
@@ -290,9 +281,9 @@ dense_step_f32(DenseStepArgs a) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             nr[e] = rowv[e] ? yr[e] + c6 * (ar[e] + fr[e]) : yr[e];
-                            if (CPLX) ni[e] = rowv[e] ? yi[e] + c6 * (ai[e] + fi[e]) : yi[e];
+                            ni[e] = rowv[e] ? yi[e] + c6 * (ai[e] + fi[e]) : yi[e];
                             ng[e] = rowv[e] ? yg[e] + c6 * (ag[e] + fg[e]) : yg[e];
-                            bad |= !(finite4(nr[e]) && finite4(ng[e]) && (!CPLX || finite4(ni[e])));
+                            bad |= !(fin(nr[e]) && fin(ng[e]) && fin(ni[e]));
                         }
                         *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
                         if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + a.plane_stride + idx) = ni;
@@ -302,7 +293,7 @@ dense_step_f32(DenseStepArgs a) {
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 ar[e] += 2.0f * fr[e];
-                                if (CPLX) ai[e] += 2.0f * fi[e];
+                                ai[e] += 2.0f * fi[e];
                                 ag[e] += 2.0f * fg[e];
                             }
                         }
@@ -311,7 +302,7 @@ dense_step_f32(DenseStepArgs a) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             sr[e] = rowv[e] ? yr[e] + c * fr[e] : yr[e];
-                            if (CPLX) si[e] = rowv[e] ? yi[e] + c * fi[e] : yi[e];
+                            si[e] = rowv[e] ? yi[e] + c * fi[e] : yi[e];
                             sg[e] = rowv[e] ? yg[e] + c * fg[e] : yg[e];
                         }
                         *reinterpret_cast<f32x4 *>(a.acc_psi + idx) = ar;
@@ -328,63 +319,74 @@ dense_step_f32(DenseStepArgs a) {
     }
 }
 
-template <int BN, int WN, bool CPLX>
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX>
 hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    if (a.Np % BM || a.Np % BK || a.Rp % TRAJ) return hipErrorInvalidValue;
     const int nblk = (a.Np / BM) * (a.Rp / TRAJ);
     const dim3 grid(nblk), block(64 * WM * WN);
+#define GD_LAUNCH(M) dense_step_f32<BM, BN, BK, WM, WN, CPLX, M><<<grid, block, 0, st>>>(a)
     switch (mode) {
-    case MODE_EULER: dense_step_f32<BN, WN, CPLX, MODE_EULER><<<grid, block, 0, st>>>(a); break;
-    case MODE_RK1: dense_step_f32<BN, WN, CPLX, MODE_RK1><<<grid, block, 0, st>>>(a); break;
-    case MODE_RK2: dense_step_f32<BN, WN, CPLX, MODE_RK2><<<grid, block, 0, st>>>(a); break;
-    case MODE_RK3: dense_step_f32<BN, WN, CPLX, MODE_RK3><<<grid, block, 0, st>>>(a); break;
-    case MODE_RK4: dense_step_f32<BN, WN, CPLX, MODE_RK4><<<grid, block, 0, st>>>(a); break;
-    case MODE_ENERGY: dense_step_f32<BN, WN, CPLX, MODE_ENERGY><<<grid, block, 0, st>>>(a); break;
+    case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
+    case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
+    case MODE_RK2: GD_LAUNCH(MODE_RK2); break;
+    case MODE_RK3: GD_LAUNCH(MODE_RK3); break;
+    case MODE_RK4: GD_LAUNCH(MODE_RK4); break;
+    case MODE_ENERGY: GD_LAUNCH(MODE_ENERGY); break;
     default: return hipErrorInvalidValue;
     }
+#undef GD_LAUNCH
     return hipGetLastError();
 }
 
-// Variants: {GEMM columns per workgroup, waves along columns}.
-constexpr int kRealCfg[][2] = {{64, 2}, {128, 2}, {128, 4}};
-constexpr int kCplxCfg[][2] = {{64, 1}, {128, 2}, {256, 2}};
+// Variants {BM, BN (GEMM columns), BK, WM, WN}; identical for real and
+// complex amplitudes (complex tiles hold BN/2 trajectories).  The runtime
+// times the variants that tile a problem and keeps the fastest.
+#define GD_DENSE_VARIANTS(X)      \
+    X(0, 64, 64, 32, 2, 2)        \
+    X(1, 64, 128, 32, 2, 2)       \
+    X(2, 128, 128, 32, 2, 2)      \
+    X(3, 32, 64, 32, 1, 2)        \
+    X(4, 64, 64, 64, 2, 2)        \
+    X(5, 64, 128, 64, 2, 2)       \
+    X(6, 128, 64, 32, 4, 1)
+
+constexpr int kCfg[][5] = {
+#define GD_ROW(id, bm, bn, bk, wm, wn) {bm, bn, bk, wm, wn},
+    GD_DENSE_VARIANTS(GD_ROW)
+#undef GD_ROW
+};
 
 }  // namespace
 
-int dense_config_count(bool complex_mode) {
-    return complex_mode ? int(sizeof(kCplxCfg) / sizeof(kCplxCfg[0]))
-                        : int(sizeof(kRealCfg) / sizeof(kRealCfg[0]));
-}
+int dense_config_count(bool) { return int(sizeof(kCfg) / sizeof(kCfg[0])); }
 
 DenseConfig dense_config(bool complex_mode, int idx) {
-    const int(*t)[2] = complex_mode ? kCplxCfg : kRealCfg;
     DenseConfig c;
     c.id = idx;
-    c.bn = t[idx][0];
-    c.wn = t[idx][1];
+    c.bm = kCfg[idx][0];
+    c.bn = kCfg[idx][1];
+    c.bk = kCfg[idx][2];
+    c.wn = kCfg[idx][4];
     c.traj_tile = complex_mode ? c.bn / 2 : c.bn;
-    c.threads = 64 * WM * c.wn;
+    c.threads = 64 * kCfg[idx][3] * kCfg[idx][4];
     return c;
 }
 
 hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                              const DenseStepArgs &a, hipStream_t st) {
     if (op != OP_F32) return hipErrorInvalidValue;
-    if (a.Np % BM || a.Rp % cfg.traj_tile) return hipErrorInvalidValue;
-    if (complex_mode) {
-        switch (cfg.id) {
-        case 0: return launch_modes<64, 1, true>(mode, a, st);
-        case 1: return launch_modes<128, 2, true>(mode, a, st);
-        case 2: return launch_modes<256, 2, true>(mode, a, st);
-        }
-    } else {
-        switch (cfg.id) {
-        case 0: return launch_modes<64, 2, false>(mode, a, st);
-        case 1: return launch_modes<128, 2, false>(mode, a, st);
-        case 2: return launch_modes<128, 4, false>(mode, a, st);
-        }
-    }
+#define GD_CASE(id, bm, bn, bk, wm, wn)                                                  \
+    case id:                                                                             \
+        return complex_mode ? launch_modes<bm, bn, bk, wm, wn, true>(mode, a, st)        \
+                            : launch_modes<bm, bn, bk, wm, wn, false>(mode, a, st);
+    switch (cfg.id) { GD_DENSE_VARIANTS(GD_CASE) }
+#undef GD_CASE
     return hipErrorInvalidValue;
+}
+
+bool dense_config_fits(const DenseConfig &c, int Np, int Rp) {
+    return Np % c.bm == 0 && Np % c.bk == 0 && Rp % c.traj_tile == 0;
 }
 
 }  // namespace gd

@@ -50,14 +50,17 @@ struct DenseStepArgs {
 // Kernel variants of the dense path.  traj_tile = trajectories per workgroup.
 struct DenseConfig {
     int id;
+    int bm;        // rows per workgroup (the energy partials use row tiles of bm)
     int bn;        // GEMM columns per workgroup
-    int wn;        // waves along the column dimension (2 waves along rows)
+    int bk;        // K chunk per pipeline stage
+    int wn;        // waves along the column dimension
     int traj_tile; // trajectories per workgroup
     int threads;
 };
 
 int dense_config_count(bool complex_mode);
 DenseConfig dense_config(bool complex_mode, int idx);
+bool dense_config_fits(const DenseConfig &c, int Np, int Rp);
 
 hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                              const DenseStepArgs &a, hipStream_t st);

@@ -152,7 +152,7 @@ int alloc_state(gd_solver *s, int R) {
         if (rc == GD_OK) rc = dalloc(&s->acc_gam, pl);
     }
     if (rc == GD_OK) rc = dalloc(&s->D, pl * P);
-    if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / kRowTile) * s->Rp);
+    if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 32) * s->Rp);  // smallest row tile
     if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp);
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
     if (rc == GD_OK) rc = dalloc(&s->dBest, 1);
@@ -251,7 +251,8 @@ int choose_config(gd_solver *s) {
     const int nc = dense_config_count(cx);
     if (const char *env = std::getenv("GD_DENSE_CONFIG")) {
         int id = std::atoi(env);
-        if (id < 0 || id >= nc) return fail(GD_E_INVALID_ARG, "GD_DENSE_CONFIG out of range");
+        if (id < 0 || id >= nc || !dense_config_fits(dense_config(cx, id), s->Np, s->Rp))
+            return fail(GD_E_INVALID_ARG, "GD_DENSE_CONFIG out of range or does not tile the problem");
         s->cfg = dense_config(cx, id);
         return GD_OK;
     }
@@ -264,9 +265,9 @@ int choose_config(gd_solver *s) {
             return GD_OK;
         }
     }
-    // tiny problems: no point timing
+    // tiny problems: no point timing; take the variant with the most workgroups
     const long long work = (long long)s->Np * s->Np * s->Rp * s->P;
-    int best = 0;
+    int best = -1;
     if (work >= (1ll << 26)) {
         hipEvent_t e0, e1;
         GD_HIP(hipEventCreate(&e0));
@@ -275,6 +276,7 @@ int choose_config(gd_solver *s) {
         const int reps = 3;
         for (int id = 0; id < nc; ++id) {
             DenseConfig c = dense_config(cx, id);
+            if (!dense_config_fits(c, s->Np, s->Rp)) continue;
             int rc = enqueue_step(s, c, 0.0f, false);  // warm-up
             if (rc != GD_OK) return rc;
             GD_HIP(hipEventRecord(e0, s->stream));
@@ -290,9 +292,15 @@ int choose_config(gd_solver *s) {
         (void)hipEventDestroy(e1);
         GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
     } else {
-        // most workgroups while keeping >= 2 trajectory blocks of work per wave
-        best = cx ? 0 : 0;
+        long long most = -1;
+        for (int id = 0; id < nc; ++id) {
+            DenseConfig c = dense_config(cx, id);
+            if (!dense_config_fits(c, s->Np, s->Rp)) continue;
+            const long long nblk = (long long)(s->Np / c.bm) * (s->Rp / c.traj_tile) * (c.threads / 64);
+            if (nblk > most) { most = nblk; best = id; }
+        }
     }
+    if (best < 0) return fail(GD_E_UNSUPPORTED, "no dense kernel variant tiles this problem");
     s->cfg = dense_config(cx, best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
@@ -627,7 +635,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             a.B = s->D;
             a.psi_in = s->D;
             GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
-            GD_HIP(launch_energy_reduce(s->partial, s->Np / kRowTile, s->Rp, s->R, s->dE, s->dBest,
+            GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
                                         s->stream));
             double emin = 0.0;
             int bi = 0;
@@ -688,7 +696,8 @@ static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
         a.psi_in = s->D;
         GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
     }
-    GD_HIP(launch_energy_reduce(s->partial, s->Np / kRowTile, s->Rp, s->R, s->dE, s->dBest, s->stream));
+    GD_HIP(launch_energy_reduce(s->partial, fp64 ? s->Np / 64 : s->Np / s->cfg.bm, s->Rp, s->R, s->dE,
+                                s->dBest, s->stream));
     int bi = 0;
     if (s->prm.flags & GD_F_DEVICE_PTRS) {
         GD_HIP(hipMemcpyAsync(E, s->dE, sizeof(double) * s->R, hipMemcpyDeviceToDevice, s->stream));
