@@ -24,8 +24,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
     # name: (model, n, R, integrator, dt, steps, generator)
@@ -33,10 +31,15 @@ WORKLOADS = {
                    J="dense_gaussian", desc="XY, N=1024, J~N(0,1/N), R=1024, RK4 dt=0.02, FP32"),
     "ising64": dict(model="ising", n=64, R=100, integrator="euler", dt=0.05, steps=2000,
                     J="dense_pm1", desc="Ising, N=64, J iid {-1,+1}, R=100, Euler dt=0.05, FP32"),
-    "ising4096_fp32": dict(model="ising", n=4096, R=4096, integrator="euler", dt=0.05, steps=200,
+    "ising4096_fp32": dict(model="ising", n=4096, R=4096, integrator="euler", dt=0.05, steps=500,
                            J="sparse_pm1", desc="Ising, N=4096, J in {-1,0,1} density 0.5, "
                                                 "R=4096, Euler dt=0.05, FP32 operands"),
+    "ising4096_bf16": dict(model="ising", n=4096, R=4096, integrator="euler", dt=0.05, steps=10000,
+                           J="sparse_pm1", precision="bf16",
+                           desc="Ising, N=4096, J in {-1,0,1} density 0.5 stored FP8, R=4096, "
+                                "Euler dt=0.05, BF16 operand, FP32 accumulation/state"),
 }
+PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
 
 def parse():
@@ -117,7 +120,9 @@ def main():
     torch.cuda.init()
     # inputs resident in HBM before the timed region; HIP events around every
     # coupling launch on the solver's stream (GD_F_PROFILE)
-    S = gd.Solver(J, model=model, integrator=integ, dt=wl["dt"], eps=0.1,
+    prec_name = wl.get("precision", "fp32")
+    prec = {"fp32": gd.GD_PREC_FP32, "bf16": gd.GD_PREC_BF16, "fp16": gd.GD_PREC_FP16}[prec_name]
+    S = gd.Solver(J, model=model, integrator=integ, dt=wl["dt"], eps=0.1, precision=prec,
                   check_interval=args.check, flags=gd.GD_F_PROFILE)
     S.set_init(R, psi0)
     if args.warmup:
@@ -149,13 +154,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec_name == "fp32" else f"{prec_name}xf32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "R": R, "integrator": wl["integrator"],
                    "dt": wl["dt"], "energy_check_every": args.check, "kernel_config": st.kernel_config},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "dense_step_f32", "launches": int(launches),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[prec_name],
+                     "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS[prec_name], "traffic": None,
+                     "kernel": "dense_step_f32" if prec_name == "fp32" else "dense_step_lp",
+                     "launches": int(launches),
                      "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops_launch},
         "best_energy": float(E[best]),
     }

@@ -28,11 +28,9 @@
 // K order inside a 16-wide slice is permuted: lane group q = lane/16 feeds
 // k = 4q + t to MFMA number t (A and B use the same permutation), so each
 // lane fetches its 4 operands of a slice with one ds_read_b128.
-#include "gd_internal.h"
+#include "gd_epilogue.h"
 
 namespace gd {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -54,8 +52,6 @@ __device__ inline void tile_map(int b, int nblk, int n_mt, int n_ct, int &mt, in
     mt = first + in % gsz;
     ct = in / gsz;
 }
-
-__device__ inline bool fin(float a) { return __builtin_isfinite(a); }
 
 template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE>
 __global__ void __launch_bounds__(64 * WM * WN)
@@ -177,27 +173,15 @@ dense_step_f32(DenseStepArgs a) {
     // ---------------------------------------------------------------- epilogue
     // acc[mb][nb][e] holds row i = m0 + wm*TM + mb*16 + 4*lq + e, column l16 of block nb.
     if constexpr (MODE == MODE_ENERGY) {
-        // e_ir = -sum_p D_p(i,r) T_p(i,r) + g_i D_0(i,r); reduce over the tile's rows.
         double esum[NP];
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
             const int r = r0 + tcol(tb) + l16;
             double s = 0.0;
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int i0 = m0 + wm * TM + mb * 16 + 4 * lq;
-                const long long idx = (long long)r * Np + i0;
-                const f32x4 d0 = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
-                const f32x4 gg = *reinterpret_cast<const f32x4 *>(a.g + i0);
-                f32x4 d1 = {0.f, 0.f, 0.f, 0.f};
-                if (CPLX) d1 = *reinterpret_cast<const f32x4 *>(a.psi_in + a.plane_stride + idx);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    double t = -(double)d0[e] * (double)acc[mb][tb][e] + (double)gg[e] * (double)d0[e];
-                    if (CPLX) t -= (double)d1[e] * (double)acc[mb][NP + tb][e];
-                    s += t;
-                }
-            }
+            for (int mb = 0; mb < MB; ++mb)
+                s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, acc[mb][tb],
+                                         CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
             s += __shfl_xor(s, 16);
             s += __shfl_xor(s, 32);
             esum[tb] = s;
@@ -217,103 +201,16 @@ dense_step_f32(DenseStepArgs a) {
                 a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l16] = s;
             }
         }
-        return;
     } else {
-        const float inv_s = a.inv_s, dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
             const int r = r0 + tcol(tb) + l16;
             const bool rvalid = r < a.R;
             bool bad = false;
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int i0 = m0 + wm * TM + mb * 16 + 4 * lq;
-                const long long idx = (long long)r * Np + i0;
-                const f32x4 ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
-                const f32x4 hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
-                const f32x4 xr = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
-                f32x4 xi = {0.f, 0.f, 0.f, 0.f};
-                if (CPLX) xi = *reinterpret_cast<const f32x4 *>(a.psi_in + a.plane_stride + idx);
-                const f32x4 gm = *reinterpret_cast<const f32x4 *>(a.gam_in + idx);
-                f32x4 fr, fi, fg;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float rho = CPLX ? xr[e] * xr[e] + xi[e] * xi[e] : xr[e] * xr[e];
-                    const float lin = gm[e] - gc - rho;
-                    fr[e] = xr[e] * lin + acc[mb][tb][e] * inv_s + hh[e];
-                    fi[e] = CPLX ? xi[e] * lin + acc[mb][NP + tb][e] * inv_s : 0.0f;
-                    fg[e] = ep[e] * (rho_th - rho);
-                }
-                // rows beyond n and padded trajectories keep their (zero) state and gain
-                bool rowv[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) rowv[e] = rvalid && (i0 + e < a.n);
-
-                if constexpr (MODE == MODE_EULER) {
-                    f32x4 nr, ni, ng;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        nr[e] = rowv[e] ? xr[e] + dt * fr[e] : xr[e];
-                        ni[e] = rowv[e] ? xi[e] + dt * fi[e] : xi[e];
-                        ng[e] = rowv[e] ? gm[e] + dt * fg[e] : gm[e];
-                        bad |= !(fin(nr[e]) && fin(ng[e]) && fin(ni[e]));
-                    }
-                    *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
-                    if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + a.plane_stride + idx) = ni;
-                    *reinterpret_cast<f32x4 *>(a.gam_out + idx) = ng;
-                } else {
-                    // RK4 stage on y = (psi, gamma); psi_in/gam_in is the stage input
-                    f32x4 yr = xr, yi = xi, yg = gm;
-                    if constexpr (MODE != MODE_RK1) {
-                        yr = *reinterpret_cast<const f32x4 *>(a.y_psi + idx);
-                        if (CPLX) yi = *reinterpret_cast<const f32x4 *>(a.y_psi + a.plane_stride + idx);
-                        yg = *reinterpret_cast<const f32x4 *>(a.y_gam + idx);
-                    }
-                    f32x4 ar = fr, ai = fi, ag = fg;
-                    if constexpr (MODE != MODE_RK1) {
-                        ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
-                        if (CPLX) ai = *reinterpret_cast<const f32x4 *>(a.acc_psi + a.plane_stride + idx);
-                        ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
-                    }
-                    if constexpr (MODE == MODE_RK4) {
-                        const float c6 = dt * (1.0f / 6.0f);
-                        f32x4 nr, ni, ng;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            nr[e] = rowv[e] ? yr[e] + c6 * (ar[e] + fr[e]) : yr[e];
-                            ni[e] = rowv[e] ? yi[e] + c6 * (ai[e] + fi[e]) : yi[e];
-                            ng[e] = rowv[e] ? yg[e] + c6 * (ag[e] + fg[e]) : yg[e];
-                            bad |= !(fin(nr[e]) && fin(ng[e]) && fin(ni[e]));
-                        }
-                        *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
-                        if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + a.plane_stride + idx) = ni;
-                        *reinterpret_cast<f32x4 *>(a.gam_out + idx) = ng;
-                    } else {
-                        if constexpr (MODE != MODE_RK1) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                ar[e] += 2.0f * fr[e];
-                                ai[e] += 2.0f * fi[e];
-                                ag[e] += 2.0f * fg[e];
-                            }
-                        }
-                        const float c = (MODE == MODE_RK3) ? dt : 0.5f * dt;
-                        f32x4 sr, si, sg;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            sr[e] = rowv[e] ? yr[e] + c * fr[e] : yr[e];
-                            si[e] = rowv[e] ? yi[e] + c * fi[e] : yi[e];
-                            sg[e] = rowv[e] ? yg[e] + c * fg[e] : yg[e];
-                        }
-                        *reinterpret_cast<f32x4 *>(a.acc_psi + idx) = ar;
-                        if (CPLX) *reinterpret_cast<f32x4 *>(a.acc_psi + a.plane_stride + idx) = ai;
-                        *reinterpret_cast<f32x4 *>(a.acc_gam + idx) = ag;
-                        *reinterpret_cast<f32x4 *>(a.psi_out + idx) = sr;
-                        if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + a.plane_stride + idx) = si;
-                        *reinterpret_cast<f32x4 *>(a.gam_out + idx) = sg;
-                    }
-                }
-            }
+            for (int mb = 0; mb < MB; ++mb)
+                bad |= step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, rvalid,
+                                                          acc[mb][tb], CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
             if (bad && rvalid) a.flags[r] = 1;
         }
     }

@@ -1,0 +1,313 @@
+// Reduced-precision coupling step: the coupling product of Eq. (main) with
+// BF16 or FP16 operands and FP32 accumulation on the matrix cores
+// (v_mfma_f32_32x32x16_bf16 / _f16), the amplitude/gain update in FP32.
+//
+// J is stored either in the operand type or, when every coupling is exactly
+// representable there (e.g. couplings in {-1, 0, +1}), in FP8 (OCP E4M3,
+// one byte per coupling) and widened exactly to the operand type while it is
+// staged into LDS (v_cvt_pk_f32_fp8, then the top 16 bits: FP8 values have at
+// most four significant bits, so the truncation is exact).  The operand Psi
+// is a BF16/FP16 copy of the FP32 amplitudes that the epilogue of the
+// previous step writes next to them; the epilogue itself reads and writes the
+// FP32 state (gd_epilogue.h).
+//
+// Tiling: workgroup BM x BN (GEMM columns), WM x WN waves, each wave a grid of
+// 32x32 MFMA blocks.  LDS holds both tiles as [row][k] in the operand type
+// with an 8-element pad per row; each lane fetches the 8 operands of its
+// half-wave K slice with one ds_read_b128.  Complex tiles pair real and
+// imaginary column blocks inside a wave as in the FP32 kernel.
+#include "gd_epilogue.h"
+
+namespace gd {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void tile_map_lp(int b, int nblk, int n_mt, int n_ct, int &mt, int &ct) {
+    int t = b;
+    if ((nblk & 7) == 0) t = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int gm = 8;
+    const int width = gm * n_ct;
+    const int group = t / width;
+    const int first = group * gm;
+    const int gsz = min(gm, n_mt - first);
+    const int in = t - group * width;
+    mt = first + in % gsz;
+    ct = in / gsz;
+}
+
+// four FP8 (E4M3) bytes -> four 16-bit operands packed in two dwords
+template <int OPT>
+__device__ inline void widen_fp8x4(unsigned int w, unsigned int &lo, unsigned int &hi) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8(int(w), false);
+    const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8(int(w), true);
+    if constexpr (OPT == OP_BF16) {
+        lo = (__float_as_uint(a[0]) >> 16) | (__float_as_uint(a[1]) & 0xFFFF0000u);
+        hi = (__float_as_uint(b[0]) >> 16) | (__float_as_uint(b[1]) & 0xFFFF0000u);
+    } else {
+        const __half2 x = __floats2half2_rn(a[0], a[1]);
+        const __half2 y = __floats2half2_rn(b[0], b[1]);
+        lo = *reinterpret_cast<const unsigned int *>(&x);
+        hi = *reinterpret_cast<const unsigned int *>(&y);
+    }
+}
+
+template <int OPT>
+__device__ inline f32x16 mfma32(u32x4 a, u32x4 b, f32x16 c) {
+    if constexpr (OPT == OP_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE, int OPT, bool JFP8>
+__global__ void __launch_bounds__(64 * WM * WN)
+dense_step_lp(DenseStepArgs a) {
+    constexpr int LDP = BK + 8;            // LDS row pitch in 16-bit elements
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int MB = TM / 32, NB = TN / 32;
+    constexpr int NP = CPLX ? NB / 2 : NB;
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    static_assert(!CPLX || (NB % 2 == 0), "complex waves pair re/im blocks");
+    // global loads are 16 bytes: 16 FP8 couplings or 8 16-bit values
+    constexpr int AQ = JFP8 ? BK / 16 : BK / 8;     // 16-byte loads per A row chunk
+    constexpr int BQ = BK / 8;                      // 16-byte loads per B row chunk
+    constexpr int AL = BM * AQ / NT, BL = BN * BQ / NT;
+    static_assert(BM * AQ % NT == 0 && BN * BQ % NT == 0, "load split");
+
+    __shared__ __attribute__((aligned(16))) unsigned short lds[2][(BM + BN) * LDP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int n_mt = a.Np / BM, n_ct = a.Rp / TRAJ;
+    int mt, ct;
+    tile_map_lp(blockIdx.x, gridDim.x, n_mt, n_ct, mt, ct);
+    const int m0 = mt * BM, r0 = ct * TRAJ;
+    const long long Np = a.Np;
+    const unsigned char *J8 = static_cast<const unsigned char *>(a.J);
+    const unsigned short *J16 = static_cast<const unsigned short *>(a.J);
+    const unsigned short *Bop = static_cast<const unsigned short *>(a.B);
+
+    u32x4 ra[AL], rb[BL];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < AL; ++u) {
+            const int q = tid + u * NT;
+            const int row = q / AQ, kq = q % AQ;
+            if constexpr (JFP8)
+                ra[u] = *reinterpret_cast<const u32x4 *>(J8 + (m0 + row) * Np + k0 + kq * 16);
+            else
+                ra[u] = *reinterpret_cast<const u32x4 *>(J16 + (m0 + row) * Np + k0 + kq * 8);
+        }
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+            const int q = tid + u * NT;
+            const int col = q / BQ, kq = q % BQ;
+            const int plane = CPLX ? col / (BN / 2) : 0;
+            const int tr = CPLX ? col % (BN / 2) : col;
+            rb[u] = *reinterpret_cast<const u32x4 *>(Bop + plane * a.plane_stride + (r0 + tr) * Np +
+                                                     k0 + kq * 8);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < AL; ++u) {
+            const int q = tid + u * NT;
+            const int row = q / AQ, kq = q % AQ;
+            if constexpr (JFP8) {
+                unsigned int x0, x1, x2, x3, x4, x5, x6, x7;
+                widen_fp8x4<OPT>(ra[u][0], x0, x1);
+                widen_fp8x4<OPT>(ra[u][1], x2, x3);
+                widen_fp8x4<OPT>(ra[u][2], x4, x5);
+                widen_fp8x4<OPT>(ra[u][3], x6, x7);
+                const u32x4 w0 = {x0, x1, x2, x3}, w1 = {x4, x5, x6, x7};
+                *reinterpret_cast<u32x4 *>(&lds[buf][row * LDP + kq * 16]) = w0;
+                *reinterpret_cast<u32x4 *>(&lds[buf][row * LDP + kq * 16 + 8]) = w1;
+            } else {
+                *reinterpret_cast<u32x4 *>(&lds[buf][row * LDP + kq * 8]) = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+            const int q = tid + u * NT;
+            const int col = q / BQ, kq = q % BQ;
+            *reinterpret_cast<u32x4 *>(&lds[buf][(BM + col) * LDP + kq * 8]) = rb[u];
+        }
+    };
+    auto bcol = [&](int nb) -> int {
+        if (CPLX) {
+            const int p = nb / NP, tb = nb % NP;
+            return p * (BN / 2) + wn * (TN / 2) + tb * 32;
+        }
+        return wn * TN + nb * 32;
+    };
+    auto tcol = [&](int tb) -> int { return CPLX ? wn * (TN / 2) + tb * 32 : wn * TN + tb * 32; };
+
+    f32x16 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
+
+    const int nk = a.Np / BK;
+    const int l32 = lane & 31, lh = lane >> 5;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) gload((kc + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            u32x4 av[MB], bv[NB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                av[mb] = *reinterpret_cast<const u32x4 *>(
+                    &lds[buf][(wm * TM + mb * 32 + l32) * LDP + kk * 16 + lh * 8]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                bv[nb] = *reinterpret_cast<const u32x4 *>(
+                    &lds[buf][(BM + bcol(nb) + l32) * LDP + kk * 16 + lh * 8]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma32<OPT>(av[mb], bv[nb], acc[mb][nb]);
+        }
+        if (kc + 1 < nk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    // acc[mb][nb][4q + e]: row i = m0 + wm*TM + mb*32 + 8q + 4*lh + e, column l32 of block nb
+    auto sub4 = [](const f32x16 &v, int q) -> f32x4 {
+        return f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+    };
+    if constexpr (MODE == MODE_ENERGY) {
+        double esum[NP];
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int r = r0 + tcol(tb) + l32;
+            double s = 0.0;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 32 + 8 * q + 4 * lh, r,
+                                             sub4(acc[mb][tb], q),
+                                             CPLX ? sub4(acc[mb][NP + tb], q) : sub4(acc[mb][tb], q));
+            s += __shfl_xor(s, 32);
+            esum[tb] = s;
+        }
+        double *red = reinterpret_cast<double *>(&lds[0][0]);
+        if (lh == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) red[(wm * WN + wn) * (NP * 32) + tb * 32 + l32] = esum[tb];
+        }
+        __syncthreads();
+        if (wm == 0 && lh == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) {
+                double s = 0.0;
+                for (int w = 0; w < WM; ++w) s += red[(w * WN + wn) * (NP * 32) + tb * 32 + l32];
+                a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l32] = s;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int r = r0 + tcol(tb) + l32;
+            const bool rvalid = r < a.R;
+            bool bad = false;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    bad |= step_epilogue4<MODE, CPLX, OPT>(
+                        a, m0 + wm * TM + mb * 32 + 8 * q + 4 * lh, r, rvalid, sub4(acc[mb][tb], q),
+                        CPLX ? sub4(acc[mb][NP + tb], q) : sub4(acc[mb][tb], q));
+            if (bad && rvalid) a.flags[r] = 1;
+        }
+    }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int OPT, bool JFP8>
+hipError_t launch_lp_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    if (a.Np % BM || a.Np % BK || a.Rp % TRAJ) return hipErrorInvalidValue;
+    const dim3 grid((a.Np / BM) * (a.Rp / TRAJ)), block(64 * WM * WN);
+#define GD_LAUNCH(M) dense_step_lp<BM, BN, BK, WM, WN, CPLX, M, OPT, JFP8><<<grid, block, 0, st>>>(a)
+    switch (mode) {
+    case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
+    case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
+    case MODE_RK2: GD_LAUNCH(MODE_RK2); break;
+    case MODE_RK3: GD_LAUNCH(MODE_RK3); break;
+    case MODE_RK4: GD_LAUNCH(MODE_RK4); break;
+    case MODE_ENERGY: GD_LAUNCH(MODE_ENERGY); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef GD_LAUNCH
+    return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &a, hipStream_t st) {
+#define GD_SEL(C, O, F)                                                                    \
+    if (cx == C && op == O && jfp8 == F) return launch_lp_modes<BM, BN, BK, WM, WN, C, O, F>(mode, a, st);
+    GD_SEL(false, OP_BF16, true) GD_SEL(false, OP_BF16, false)
+    GD_SEL(false, OP_F16, true) GD_SEL(false, OP_F16, false)
+    GD_SEL(true, OP_BF16, true) GD_SEL(true, OP_BF16, false)
+    GD_SEL(true, OP_F16, true) GD_SEL(true, OP_F16, false)
+#undef GD_SEL
+    return hipErrorInvalidValue;
+}
+
+// Variants {BM, BN (GEMM columns), BK, WM, WN}
+#define GD_LP_VARIANTS(X)        \
+    X(0, 128, 128, 64, 2, 2)     \
+    X(1, 64, 128, 64, 2, 2)      \
+    X(2, 128, 256, 64, 2, 2)     \
+    X(3, 128, 128, 32, 2, 2)
+
+constexpr int kLpCfg[][5] = {
+#define GD_ROW(id, bm, bn, bk, wm, wn) {bm, bn, bk, wm, wn},
+    GD_LP_VARIANTS(GD_ROW)
+#undef GD_ROW
+};
+
+}  // namespace
+
+int dense_lp_config_count() { return int(sizeof(kLpCfg) / sizeof(kLpCfg[0])); }
+
+DenseConfig dense_lp_config(bool complex_mode, int idx) {
+    DenseConfig c;
+    c.id = idx;
+    c.bm = kLpCfg[idx][0];
+    c.bn = kLpCfg[idx][1];
+    c.bk = kLpCfg[idx][2];
+    c.wn = kLpCfg[idx][4];
+    c.traj_tile = complex_mode ? c.bn / 2 : c.bn;
+    c.threads = 64 * kLpCfg[idx][3] * kLpCfg[idx][4];
+    return c;
+}
+
+hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
+                                bool j_fp8, const DenseStepArgs &a, hipStream_t st) {
+    if (op != OP_BF16 && op != OP_F16) return hipErrorInvalidValue;
+#define GD_CASE(id, bm, bn, bk, wm, wn) \
+    case id: return launch_lp<bm, bn, bk, wm, wn>(complex_mode, op, j_fp8, mode, a, st);
+    switch (cfg.id) { GD_LP_VARIANTS(GD_CASE) }
+#undef GD_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gd

@@ -1,0 +1,149 @@
+// Pointwise part of one integration step, shared by every coupling kernel.
+//
+// Given the coupling sums C (already computed by a GEMM, before the 1/s
+// scale) for four consecutive spins i0..i0+3 of trajectory r, apply the rest
+// of Eq. (main) and Eq. (gamma):
+//   f   = Psi (gamma - gamma_c - |Psi|^2) + C / s + h_1
+//   phi = eps_i (rho_th - |Psi|^2)
+// and an Euler update or one stage of the classical RK4 scheme on the joint
+// state (Psi, gamma).  Optionally writes a BF16/FP16 copy of the new
+// amplitudes: the operand of the next coupling GEMM.
+#pragma once
+#include "gd_internal.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace gd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline bool gd_finite(float a) { return __builtin_isfinite(a); }
+
+// store four consecutive floats as BF16 / FP16 (round to nearest even)
+template <int OPT>
+__device__ inline void store_shadow4(void *base, long long idx, f32x4 v) {
+    if constexpr (OPT == OP_BF16) {
+        __hip_bfloat16 *p = static_cast<__hip_bfloat16 *>(base) + idx;
+        __hip_bfloat162 lo = __halves2bfloat162(__float2bfloat16(v[0]), __float2bfloat16(v[1]));
+        __hip_bfloat162 hi = __halves2bfloat162(__float2bfloat16(v[2]), __float2bfloat16(v[3]));
+        reinterpret_cast<__hip_bfloat162 *>(p)[0] = lo;
+        reinterpret_cast<__hip_bfloat162 *>(p)[1] = hi;
+    } else if constexpr (OPT == OP_F16) {
+        __half *p = static_cast<__half *>(base) + idx;
+        reinterpret_cast<__half2 *>(p)[0] = __floats2half2_rn(v[0], v[1]);
+        reinterpret_cast<__half2 *>(p)[1] = __floats2half2_rn(v[2], v[3]);
+    }
+}
+
+// Returns true if a written value is non-finite.  cr/ci: raw GEMM sums.
+template <int MODE, bool CPLX, int OPT>
+__device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, bool rvalid,
+                                      f32x4 cr, f32x4 ci) {
+    const long long Np = a.Np;
+    const long long idx = (long long)r * Np + i0;
+    const long long ps = a.plane_stride;
+    const float inv_s = a.inv_s, dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
+    const f32x4 ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
+    const f32x4 hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
+    const f32x4 xr = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
+    f32x4 xi = {0.f, 0.f, 0.f, 0.f};
+    if (CPLX) xi = *reinterpret_cast<const f32x4 *>(a.psi_in + ps + idx);
+    const f32x4 gm = *reinterpret_cast<const f32x4 *>(a.gam_in + idx);
+    f32x4 fr, fi, fg;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float rho = CPLX ? xr[e] * xr[e] + xi[e] * xi[e] : xr[e] * xr[e];
+        const float lin = gm[e] - gc - rho;
+        fr[e] = xr[e] * lin + cr[e] * inv_s + hh[e];
+        fi[e] = CPLX ? xi[e] * lin + ci[e] * inv_s : 0.0f;
+        fg[e] = ep[e] * (rho_th - rho);
+    }
+    // rows beyond n and padded trajectories keep their (zero) state and gain
+    bool rowv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rowv[e] = rvalid && (i0 + e < a.n);
+    bool bad = false;
+    f32x4 nr, ni, ng;   // values written to psi_out / gam_out
+    if constexpr (MODE == MODE_EULER) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            nr[e] = rowv[e] ? xr[e] + dt * fr[e] : xr[e];
+            ni[e] = rowv[e] ? xi[e] + dt * fi[e] : xi[e];
+            ng[e] = rowv[e] ? gm[e] + dt * fg[e] : gm[e];
+            bad |= !(gd_finite(nr[e]) && gd_finite(ng[e]) && gd_finite(ni[e]));
+        }
+    } else {
+        // RK4 stage on y = (psi, gamma); psi_in/gam_in is the stage input
+        f32x4 yr = xr, yi = xi, yg = gm;
+        if constexpr (MODE != MODE_RK1) {
+            yr = *reinterpret_cast<const f32x4 *>(a.y_psi + idx);
+            if (CPLX) yi = *reinterpret_cast<const f32x4 *>(a.y_psi + ps + idx);
+            yg = *reinterpret_cast<const f32x4 *>(a.y_gam + idx);
+        }
+        f32x4 ar = fr, ai = fi, ag = fg;
+        if constexpr (MODE != MODE_RK1) {
+            ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
+            if (CPLX) ai = *reinterpret_cast<const f32x4 *>(a.acc_psi + ps + idx);
+            ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
+        }
+        if constexpr (MODE == MODE_RK4) {
+            const float c6 = dt * (1.0f / 6.0f);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nr[e] = rowv[e] ? yr[e] + c6 * (ar[e] + fr[e]) : yr[e];
+                ni[e] = rowv[e] ? yi[e] + c6 * (ai[e] + fi[e]) : yi[e];
+                ng[e] = rowv[e] ? yg[e] + c6 * (ag[e] + fg[e]) : yg[e];
+                bad |= !(gd_finite(nr[e]) && gd_finite(ng[e]) && gd_finite(ni[e]));
+            }
+        } else {
+            if constexpr (MODE != MODE_RK1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ar[e] += 2.0f * fr[e];
+                    ai[e] += 2.0f * fi[e];
+                    ag[e] += 2.0f * fg[e];
+                }
+            }
+            const float c = (MODE == MODE_RK3) ? dt : 0.5f * dt;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nr[e] = rowv[e] ? yr[e] + c * fr[e] : yr[e];
+                ni[e] = rowv[e] ? yi[e] + c * fi[e] : yi[e];
+                ng[e] = rowv[e] ? yg[e] + c * fg[e] : yg[e];
+            }
+            *reinterpret_cast<f32x4 *>(a.acc_psi + idx) = ar;
+            if (CPLX) *reinterpret_cast<f32x4 *>(a.acc_psi + ps + idx) = ai;
+            *reinterpret_cast<f32x4 *>(a.acc_gam + idx) = ag;
+        }
+    }
+    *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
+    if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + ps + idx) = ni;
+    *reinterpret_cast<f32x4 *>(a.gam_out + idx) = ng;
+    if constexpr (OPT != OP_F32) {
+        store_shadow4<OPT>(a.shadow_out, idx, nr);
+        if (CPLX) store_shadow4<OPT>(a.shadow_out, ps + idx, ni);
+    }
+    return bad;
+}
+
+// Energy terms of Eq. (h) for four consecutive spins of trajectory r:
+// sum_e [ -sum_p D_p T_p + g_i D_0 ] in FP64 (T: raw GEMM sums of J D).
+template <bool CPLX>
+__device__ inline double energy_terms4(const DenseStepArgs &a, int i0, int r, f32x4 tr, f32x4 ti) {
+    const long long idx = (long long)r * a.Np + i0;
+    const f32x4 d0 = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
+    const f32x4 gg = *reinterpret_cast<const f32x4 *>(a.g + i0);
+    f32x4 d1 = {0.f, 0.f, 0.f, 0.f};
+    if (CPLX) d1 = *reinterpret_cast<const f32x4 *>(a.psi_in + a.plane_stride + idx);
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double t = -(double)d0[e] * (double)tr[e] + (double)gg[e] * (double)d0[e];
+        if (CPLX) t -= (double)d1[e] * (double)ti[e];
+        s += t;
+    }
+    return s;
+}
+
+}  // namespace gd

@@ -65,6 +65,13 @@ bool dense_config_fits(const DenseConfig &c, int Np, int Rp);
 hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                              const DenseStepArgs &a, hipStream_t st);
 
+// Reduced-precision variants (gd_dense_lp.hip): BF16/FP16 operands, FP32
+// accumulation; J either in the operand type or FP8 E4M3 (j_fp8).
+int dense_lp_config_count();
+DenseConfig dense_lp_config(bool complex_mode, int idx);
+hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
+                                bool j_fp8, const DenseStepArgs &a, hipStream_t st);
+
 // ---- auxiliary kernels (gd_aux.hip)
 // user [R][n] (or [R][n][2]) -> zero-padded planes [P][Rp][Np]
 hipError_t launch_pack_planes(const float *user, float *planes, int n, int R, int Np, int Rp,

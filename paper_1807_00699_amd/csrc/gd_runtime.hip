@@ -55,6 +55,40 @@ inline double uniform01(uint64_t seed, uint64_t ctr) {
     return double(splitmix64(seed ^ splitmix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
 }
 
+// OCP FP8 E4M3 (4 exponent bits, bias 7, 3 mantissa bits; S.1111.111 is NaN,
+// no infinities).  decode: value of a code; encode_exact: code whose value is
+// exactly v (normal numbers and zero only), if any.
+inline float e4m3_decode(uint8_t c) {
+    const int s = c >> 7, e = (c >> 3) & 15, m = c & 7;
+    float v;
+    if (e == 15 && m == 7) return std::nanf("");
+    if (e == 0) v = std::ldexp(float(m), -9);
+    else v = std::ldexp(1.0f + float(m) / 8.0f, e - 7);
+    return s ? -v : v;
+}
+inline bool e4m3_encode_exact(float v, uint8_t *out) {
+    if (v == 0.0f) { *out = std::signbit(v) ? 0x80 : 0x00; return true; }
+    for (int c = 0; c < 256; ++c) {
+        const int e = (c >> 3) & 15;
+        if (e == 0) continue;   // subnormals are not used for storage
+        if (e4m3_decode(uint8_t(c)) == v) { *out = uint8_t(c); return true; }
+    }
+    return false;
+}
+inline bool bf16_exact(float v, uint16_t *out) {
+    uint32_t b;
+    std::memcpy(&b, &v, 4);
+    if (b & 0xFFFFu) return false;
+    *out = uint16_t(b >> 16);
+    return true;
+}
+inline bool f16_exact(float v, uint16_t *out) {
+    const _Float16 h = (_Float16)v;
+    if (float(h) != v) return false;
+    std::memcpy(out, &h, 2);
+    return true;
+}
+
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (complex, Np, Rp, integrator) -> cfg
 
@@ -72,6 +106,11 @@ struct gd_solver {
     std::vector<float> hEps;   // per-spin eps actually in use (length n)
     // device constants
     float *dJ = nullptr, *dEps = nullptr, *dH1 = nullptr, *dG = nullptr;
+    int op = OP_F32;           // operand precision of the coupling GEMM
+    bool jfp8 = false;         // J stored as FP8 E4M3 (reduced-precision modes)
+    void *dJlp = nullptr;      // J in FP8 or in the operand type
+    void *shadow[3] = {nullptr, nullptr, nullptr};   // operand copies of psi[k]
+    void *shadowD = nullptr;   // operand copy of the discretised state
     // state
     int R = 0, Rp = 0;
     bool have_state = false;
@@ -102,6 +141,9 @@ void free_state(gd_solver *s) {
     for (float *&p : s->psi) { if (p) (void)hipFree(p); p = nullptr; }
     float **fl[] = {&s->gam, &s->gam_s, &s->acc_psi, &s->acc_gam, &s->D};
     for (float **p : fl) { if (*p) (void)hipFree(*p); *p = nullptr; }
+    for (void *&p : s->shadow) { if (p) (void)hipFree(p); p = nullptr; }
+    if (s->shadowD) (void)hipFree(s->shadowD);
+    s->shadowD = nullptr;
     if (s->partial) (void)hipFree(s->partial);
     if (s->dE) (void)hipFree(s->dE);
     if (s->flags) (void)hipFree(s->flags);
@@ -152,6 +194,11 @@ int alloc_state(gd_solver *s, int R) {
         if (rc == GD_OK) rc = dalloc(&s->acc_gam, pl);
     }
     if (rc == GD_OK) rc = dalloc(&s->D, pl * P);
+    if (s->op != OP_F32) {
+        for (int k = 0; k < npsi && rc == GD_OK; ++k)
+            rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadow[k]), pl * P);
+        if (rc == GD_OK) rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadowD), pl * P);
+    }
     if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 32) * s->Rp);  // smallest row tile
     if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp);
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
@@ -161,8 +208,10 @@ int alloc_state(gd_solver *s, int R) {
         free_state(s);
         return rc;
     }
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k) {
         if (s->psi[k]) GD_HIP(hipMemsetAsync(s->psi[k], 0, pl * P * sizeof(float), s->stream));
+        if (s->shadow[k]) GD_HIP(hipMemsetAsync(s->shadow[k], 0, pl * P * sizeof(uint16_t), s->stream));
+    }
     GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
     s->cur = 0;
     s->have_state = true;
@@ -189,6 +238,19 @@ DenseStepArgs base_args(gd_solver *s) {
     return a;
 }
 
+hipError_t launch_coupling(gd_solver *s, const DenseConfig &cfg, int mode, const DenseStepArgs &a) {
+    if (s->op == OP_F32) return launch_dense_step(cfg, s->complex_mode(), mode, OP_F32, a, s->stream);
+    DenseStepArgs b = a;
+    b.J = s->dJlp;
+    return launch_dense_step_lp(cfg, s->complex_mode(), mode, s->op, s->jfp8, b, s->stream);
+}
+
+// refresh the operand copy of psi[k] after the FP32 state was written by the host
+hipError_t refresh_shadow(gd_solver *s, int k) {
+    if (s->op == OP_F32) return hipSuccess;
+    return launch_make_shadow(s->psi[k], s->shadow[k], s->plane() * s->P, s->op, s->stream);
+}
+
 // Enqueue one integration step.  `dt_override` >= 0 replaces dt (used with
 // 0 by the tuner: the state is then left bit-for-bit unchanged).
 int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed) {
@@ -208,7 +270,7 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
             e1 = s->events[k + 1];
             GD_HIP(hipEventRecord(e0, s->stream));
         }
-        GD_HIP(launch_dense_step(cfg, cx, mode, OP_F32, x, s->stream));
+        GD_HIP(launch_coupling(s, cfg, mode, x));
         if (timed) {
             GD_HIP(hipEventRecord(e1, s->stream));
             s->ev_used++;
@@ -216,8 +278,10 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
         return GD_OK;
     };
     int rc;
+    const bool lp = s->op != OP_F32;
     if (s->integrator() == GD_EULER) {
-        a.B = s->psi[s->cur];
+        a.B = lp ? s->shadow[s->cur] : (const void *)s->psi[s->cur];
+        a.shadow_out = s->shadow[s->cur ^ 1];
         a.psi_in = s->psi[s->cur];
         a.psi_out = s->psi[s->cur ^ 1];
         a.gam_in = s->gam;
@@ -226,19 +290,25 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
         s->cur ^= 1;
         return GD_OK;
     }
-    float *Y = s->psi[s->cur], *Sa = s->psi[s->cur ^ 1], *Sb = s->psi[2];
+    const int iY = s->cur, iA = s->cur ^ 1, iB = 2;
+    float *Y = s->psi[iY], *Sa = s->psi[iA], *Sb = s->psi[iB];
+    auto op_of = [&](int k) -> const void * { return lp ? s->shadow[k] : (const void *)s->psi[k]; };
     a.y_psi = Y;
     a.y_gam = s->gam;
     a.acc_psi = s->acc_psi;
     a.acc_gam = s->acc_gam;
     // stage 1: input y
-    a.B = Y; a.psi_in = Y; a.gam_in = s->gam; a.psi_out = Sa; a.gam_out = s->gam_s;
+    a.B = op_of(iY); a.psi_in = Y; a.gam_in = s->gam; a.psi_out = Sa; a.gam_out = s->gam_s;
+    a.shadow_out = s->shadow[iA];
     if ((rc = launch(MODE_RK1, a)) != GD_OK) return rc;
-    a.B = Sa; a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Sb; a.gam_out = s->gam_s;
+    a.B = op_of(iA); a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Sb; a.gam_out = s->gam_s;
+    a.shadow_out = s->shadow[iB];
     if ((rc = launch(MODE_RK2, a)) != GD_OK) return rc;
-    a.B = Sb; a.psi_in = Sb; a.gam_in = s->gam_s; a.psi_out = Sa; a.gam_out = s->gam_s;
+    a.B = op_of(iB); a.psi_in = Sb; a.gam_in = s->gam_s; a.psi_out = Sa; a.gam_out = s->gam_s;
+    a.shadow_out = s->shadow[iA];
     if ((rc = launch(MODE_RK3, a)) != GD_OK) return rc;
-    a.B = Sa; a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Y; a.gam_out = s->gam;
+    a.B = op_of(iA); a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Y; a.gam_out = s->gam;
+    a.shadow_out = s->shadow[iY];
     if ((rc = launch(MODE_RK4, a)) != GD_OK) return rc;
     return GD_OK;
 }
@@ -248,20 +318,22 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
 // fastest is cached per (model, Np, Rp, integrator).
 int choose_config(gd_solver *s) {
     const bool cx = s->complex_mode();
-    const int nc = dense_config_count(cx);
+    const bool lp = s->op != OP_F32;
+    const int nc = lp ? dense_lp_config_count() : dense_config_count(cx);
+    auto cfg_of = [&](int id) { return lp ? dense_lp_config(cx, id) : dense_config(cx, id); };
     if (const char *env = std::getenv("GD_DENSE_CONFIG")) {
         int id = std::atoi(env);
-        if (id < 0 || id >= nc || !dense_config_fits(dense_config(cx, id), s->Np, s->Rp))
+        if (id < 0 || id >= nc || !dense_config_fits(cfg_of(id), s->Np, s->Rp))
             return fail(GD_E_INVALID_ARG, "GD_DENSE_CONFIG out of range or does not tile the problem");
-        s->cfg = dense_config(cx, id);
+        s->cfg = cfg_of(id);
         return GD_OK;
     }
-    auto key = std::make_tuple(int(cx), s->Np, s->Rp, s->integrator());
+    auto key = std::make_tuple(int(cx) + 2 * s->op + 8 * int(s->jfp8), s->Np, s->Rp, s->integrator());
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            s->cfg = dense_config(cx, it->second);
+            s->cfg = cfg_of(it->second);
             return GD_OK;
         }
     }
@@ -275,7 +347,7 @@ int choose_config(gd_solver *s) {
         float best_ms = 1e30f;
         const int reps = 3;
         for (int id = 0; id < nc; ++id) {
-            DenseConfig c = dense_config(cx, id);
+            DenseConfig c = cfg_of(id);
             if (!dense_config_fits(c, s->Np, s->Rp)) continue;
             int rc = enqueue_step(s, c, 0.0f, false);  // warm-up
             if (rc != GD_OK) return rc;
@@ -294,14 +366,14 @@ int choose_config(gd_solver *s) {
     } else {
         long long most = -1;
         for (int id = 0; id < nc; ++id) {
-            DenseConfig c = dense_config(cx, id);
+            DenseConfig c = cfg_of(id);
             if (!dense_config_fits(c, s->Np, s->Rp)) continue;
             const long long nblk = (long long)(s->Np / c.bm) * (s->Rp / c.traj_tile) * (c.threads / 64);
             if (nblk > most) { most = nblk; best = id; }
         }
     }
     if (best < 0) return fail(GD_E_UNSUPPORTED, "no dense kernel variant tiles this problem");
-    s->cfg = dense_config(cx, best);
+    s->cfg = cfg_of(best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
     return GD_OK;
@@ -474,8 +546,6 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
     else gd_default_params(&prm);
     int rc = check_params(&prm);
     if (rc != GD_OK) return rc;
-    if (prm.precision != GD_PREC_FP32)
-        return fail(GD_E_UNSUPPORTED, "only FP32 operands are implemented for dense solvers");
 
     gd_solver *s = new (std::nothrow) gd_solver();
     if (!s) return fail(GD_E_OOM, "host allocation failed");
@@ -535,7 +605,44 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
             return bail(fail(GD_E_DEVICE, "hipStreamCreate failed"));
         s->own_stream = true;
     }
+    // reduced precision: J must be exact in FP8 E4M3 (stored as one byte) or
+    // in the operand type itself
+    std::vector<uint8_t> j8;
+    std::vector<uint16_t> j16;
+    if (prm.precision != GD_PREC_FP32) {
+        s->op = prm.precision == GD_PREC_BF16 ? OP_BF16 : OP_F16;
+        bool fp8 = true;
+        j8.assign((size_t)Np * Np, 0);
+        for (int i = 0; i < n && fp8; ++i)
+            for (int j = 0; j < n && fp8; ++j)
+                if (i != j) fp8 = e4m3_encode_exact(hj[(size_t)i * n + j], &j8[(size_t)i * Np + j]);
+        s->jfp8 = fp8;
+        if (!fp8) {
+            j8.clear();
+            j16.assign((size_t)Np * Np, 0);
+            bool ok = true;
+            for (int i = 0; i < n && ok; ++i)
+                for (int j = 0; j < n && ok; ++j)
+                    if (i != j) {
+                        const float v = hj[(size_t)i * n + j];
+                        uint16_t *o = &j16[(size_t)i * Np + j];
+                        ok = s->op == OP_BF16 ? bf16_exact(v, o) : f16_exact(v, o);
+                    }
+            if (!ok)
+                return bail(fail(GD_E_UNSUPPORTED, "J is not exactly representable in the requested "
+                                                   "operand precision (nor in FP8)"));
+        }
+    }
     if ((rc = dalloc(&s->dJ, (size_t)Np * Np)) != GD_OK) return bail(rc);
+    if (s->jfp8) {
+        if ((rc = dalloc(reinterpret_cast<uint8_t **>(&s->dJlp), j8.size())) != GD_OK) return bail(rc);
+        if (hipMemcpy(s->dJlp, j8.data(), j8.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(GD_E_DEVICE, "upload of FP8 J failed"));
+    } else if (!j16.empty()) {
+        if ((rc = dalloc(reinterpret_cast<uint16_t **>(&s->dJlp), j16.size())) != GD_OK) return bail(rc);
+        if (hipMemcpy(s->dJlp, j16.data(), j16.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(GD_E_DEVICE, "upload of 16-bit J failed"));
+    }
     if ((rc = dalloc(&s->dEps, (size_t)Np)) != GD_OK) return bail(rc);
     if ((rc = dalloc(&s->dH1, (size_t)Np)) != GD_OK) return bail(rc);
     if ((rc = dalloc(&s->dG, (size_t)Np)) != GD_OK) return bail(rc);
@@ -556,6 +663,7 @@ void gd_destroy(gd_solver *s) {
     if (s->dEps) (void)hipFree(s->dEps);
     if (s->dH1) (void)hipFree(s->dH1);
     if (s->dG) (void)hipFree(s->dG);
+    if (s->dJlp) (void)hipFree(s->dJlp);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -598,6 +706,7 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
     } else {
         if ((rc = default_init(s, batch, gamma0)) != GD_OK) return rc;
     }
+    GD_HIP(refresh_shadow(s, 0));
     return choose_config(s);
 }
 
@@ -629,12 +738,12 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         if (ci > 0 && s->steps_done % ci == 0) {
             // device check: discretise, energy GEMM, deterministic reduction
             const float *cur = s->psi[s->cur];
-            GD_HIP(launch_discretise(cur, s->D, nullptr, OP_F32, nullptr, nullptr, s->flags, s->n,
+            GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, nullptr, nullptr, s->flags, s->n,
                                      s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
             DenseStepArgs a = base_args(s);
-            a.B = s->D;
+            a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
             a.psi_in = s->D;
-            GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
+            GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
             GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
                                         s->stream));
             double emin = 0.0;
@@ -685,16 +794,16 @@ static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
     if (!s->have_state) return fail(GD_E_STATE, "no state: call gd_set_init or gd_run first");
     if (!E) return fail(GD_E_INVALID_ARG, "E is NULL");
     const float *cur = s->psi[s->cur];
-    GD_HIP(launch_discretise(cur, s->D, nullptr, OP_F32, nullptr, nullptr, s->flags, s->n, s->R,
+    GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, nullptr, nullptr, s->flags, s->n, s->R,
                              s->Np, s->Rp, s->P, s->plane(), s->stream));
     if (fp64) {
         GD_HIP(launch_energy_fp64(s->dJ, cur, s->dG, s->partial, s->Np, s->Rp, s->n, s->R, s->P,
                                   s->plane(), s->stream));
     } else {
         DenseStepArgs a = base_args(s);
-        a.B = s->D;
+        a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
         a.psi_in = s->D;
-        GD_HIP(launch_dense_step(s->cfg, s->complex_mode(), MODE_ENERGY, OP_F32, a, s->stream));
+        GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
     }
     GD_HIP(launch_energy_reduce(s->partial, fp64 ? s->Np / 64 : s->Np / s->cfg.bm, s->Rp, s->R, s->dE,
                                 s->dBest, s->stream));
@@ -772,6 +881,7 @@ int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gam
     rc = upload_planes(s, gamma, s->gam, batch);
     s->P = savedP;
     if (rc != GD_OK) return rc;
+    GD_HIP(refresh_shadow(s, 0));
     GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
     GD_HIP(hipStreamSynchronize(s->stream));
     s->steps_done = step;
