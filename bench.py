@@ -38,6 +38,11 @@ WORKLOADS = {
                            J="sparse_pm1", precision="bf16",
                            desc="Ising, N=4096, J in {-1,0,1} density 0.5 stored FP8, R=4096, "
                                 "Euler dt=0.05, BF16 operand, FP32 accumulation/state"),
+    "batch256": dict(model="ising", n=None, R=64, integrator="euler", dt=0.05, steps=5000,
+                     J="regular3_maxcut", batch=256,
+                     desc="256 Ising instances, N_k even uniform in [50,2000], random 3-regular "
+                          "max-cut couplings (J=-1 on edges, gauged by a random s*), R=64, "
+                          "Euler dt=0.05, FP32, one persistent launch per chunk (hipGraph)"),
 }
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
@@ -95,6 +100,89 @@ def cpu_baseline(wl, J, psi0, target_s):
             "sample": f"{R_s} of {wl['R']} trajectories x {steps} steps, {el:.1f} s"}
 
 
+def batch_instances(K, seed=1):
+    from paper_1807_00699_amd import inputs as I
+    sizes = I.even_sizes(K, 50, 2000, seed)
+    insts = []
+    for k, n in enumerate(sizes):
+        e, w, _ = I.regular3_maxcut(int(n), 1000 * seed + k)
+        rows = np.concatenate([e, e[:, ::-1]])
+        vals = np.concatenate([w, w])
+        order = np.lexsort((rows[:, 1], rows[:, 0]))
+        rows, vals = rows[order], vals[order]
+        rp = np.zeros(n + 1, np.int64)
+        np.add.at(rp, rows[:, 0] + 1, 1)
+        insts.append(dict(n=int(n), row_ptr=np.cumsum(rp).astype(np.int32),
+                          col=rows[:, 1].astype(np.int32), val=vals.astype(np.float32)))
+    return sizes, insts
+
+
+# algorithmic FP32 flops of one spin-update of the sparse Euler step:
+# 2 per neighbour (multiply-add) + 12 for the pointwise update of Eq. (main, gamma)
+SPARSE_FLOPS_PER_UPDATE = lambda d: 2 * d + 12
+PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+def bench_batch(args, wl, steps):
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    K, R = wl["batch"], wl["R"]
+    sizes, insts = batch_instances(K)
+    x0 = np.concatenate([I.psi0_real(int(n), R, 5000 + k).ravel() for k, n in enumerate(sizes)])
+    torch.cuda.init()
+    B = gd.BatchSolver(insts, dt=wl["dt"], eps=0.1, check_interval=args.check)
+    B.set_init(R, x0)
+    if args.warmup:
+        B.run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = B.stats()
+    E, best = B.energy()
+    B.close()
+    total = int(np.sum(sizes))
+    upd = total * R * steps
+    flops = upd * SPARSE_FLOPS_PER_UPDATE(3)
+    out = {
+        "metric": "spin-updates/s (N*R*steps/s)", "value": upd / el, "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": el / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "instances": K, "sum_n": total, "R": R,
+                   "energy_check_every": args.check, "kernel_config": st.kernel_config},
+        "roofline": {"bound": "alu", "achieved": flops / el / 1e12, "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / el / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None, "kernel": "batch_ell_euler",
+                     "flops_per_update": SPARSE_FLOPS_PER_UPDATE(3)},
+        "best_energy_sum": float(E.min(1).sum()),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = min(16, os.cpu_count() or 1)
+        # sample: the first 16 instances, 16 trajectories each, a few hundred steps
+        t0 = time.perf_counter()
+        done = 0
+        nsteps = 100
+        for k in range(16):
+            n = int(sizes[k])
+            e, w, _ = I.regular3_maxcut(n, 1000 + k)
+            J = I.edges_to_dense(n, e, w)
+            O.run(J, x0[:n * 16].reshape(16, n) if k == 0 else I.psi0_real(n, 16, 5000 + k),
+                  model="ising", steps=nsteps, dt=wl["dt"], eps=0.1, nthreads=threads)
+            done += n * 16 * nsteps
+        elc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / elc, "unit": "spin-updates/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"16 instances x 16 trajectories x {nsteps} steps "
+                                         f"(dense FP64 oracle), {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -112,6 +200,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else wl["steps"]
+    if wl.get("batch"):
+        return bench_batch(args, wl, steps)
     n, R = wl["n"], wl["R"]
     J = getattr(I, wl["J"])(n, 1)
     psi0 = I.psi0_complex(n, R, 1) if wl["model"] == "xy" else I.psi0_real(n, R, 1)

@@ -204,8 +204,58 @@ int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gam
 /* gd_stats: copy the counters (out->struct_size must be set). */
 int gd_stats(gd_solver *s, gd_run_stats *out);
 
-/* gd_coupling_scale: the scale s in use. */
+/* gd_coupling_scale: the scale s in use (batch solvers: of instance 0). */
 int gd_coupling_scale(gd_solver *s, double *scale);
+
+/*
+ * Batches of instances of uneven size (the paper's workloads run many
+ * instances, Sec. 2 and 3).  One instance: n spins and either a dense
+ * coupling matrix J (n*n, row-major) or CSR arrays (row_ptr [n+1], col/val
+ * [nnz]; host memory), plus an optional field g [n].  The same validation
+ * as gd_create applies per instance; every instance gets its own coupling
+ * scale s_k.  The batched solver integrates the Ising model (real
+ * amplitudes) with explicit Euler steps in FP32; other combinations return
+ * GD_E_UNSUPPORTED.  All instances share params and the trajectory count R.
+ */
+typedef struct gd_instance {
+    int32_t n;
+    const float *J;          /* dense couplings or NULL */
+    const int32_t *row_ptr;  /* CSR, used when J is NULL */
+    const int32_t *col;
+    const float *val;
+    const float *g;          /* external field or NULL */
+} gd_instance;
+
+/*
+ * gd_create_batch: one handle for `count` instances.  The calls above then
+ * work on the whole batch with concatenated layouts: per-trajectory arrays are
+ * the instances' [R][n_k] blocks one after the other (sum_k R*n_k floats);
+ * eps of gd_set_init is [sum_k n_k]; gd_energy writes E [count][R] and best
+ * [count] (argmin per instance, ties -> lowest r); gd_spins writes int8
+ * spins in the state layout.  gd_run makes one persistent launch per chunk
+ * of steps (check_interval steps, or all), captured once in a hipGraph and
+ * replayed.
+ */
+int gd_create_batch(gd_solver **out, int32_t count, const gd_instance *inst, int32_t model,
+                    const gd_params *p);
+
+/*
+ * gd_set_targets: target energies of Eq. (h), [count] (one for a single-
+ * instance solver), or NULL to clear.  With check_interval > 0, gd_run
+ * records for each instance the wall time and step count of the first check
+ * where its best energy is <= its target; with has_target it stops once every
+ * instance has reached its target.  For a single-instance solver this sets
+ * params.target_energy and has_target.
+ */
+int gd_set_targets(gd_solver *s, const double *targets);
+
+/*
+ * gd_ttt: per instance [count]: seconds from the start of gd_run calls (summed
+ * over calls) to the check that met the target (-1 if not reached), the step
+ * count at that check (-1), and the best checked energy so far (+inf).  Any
+ * pointer may be NULL.
+ */
+int gd_ttt(gd_solver *s, double *seconds, int64_t *steps, double *best_energy);
 
 const char *gd_error_string(int code);
 const char *gd_last_error(void);

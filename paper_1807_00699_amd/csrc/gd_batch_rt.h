@@ -1,0 +1,26 @@
+// Host interface of the batched sparse solver (gd_batch_rt.hip); used by the
+// C ABI in gd_runtime.hip.  Not part of the public header.
+#pragma once
+#include "../../include/gd.h"
+
+#include <cstdint>
+
+namespace gd {
+
+struct BatchSolver;
+
+int batch_create(BatchSolver **out, int count, const gd_instance *inst, int model, const gd_params *p);
+void batch_destroy(BatchSolver *b);
+int batch_set_init(BatchSolver *b, int R, const float *psi0, const float *gamma0, const float *eps);
+int batch_run(BatchSolver *b, int R, int64_t steps);
+int batch_energy(BatchSolver *b, double *E, int32_t *best);
+int batch_spins(BatchSolver *b, void *out, int fmt);
+int batch_get_state(BatchSolver *b, float *psi, float *gamma, int64_t *step);
+int batch_set_state(BatchSolver *b, int R, const float *psi, const float *gamma, int64_t step);
+int batch_stats(BatchSolver *b, gd_run_stats *out);
+int batch_set_targets(BatchSolver *b, const double *targets);
+int batch_ttt(BatchSolver *b, double *seconds, int64_t *steps, double *best_energy);
+int batch_count(const BatchSolver *b);
+double batch_scale(const BatchSolver *b, int k);
+
+}  // namespace gd

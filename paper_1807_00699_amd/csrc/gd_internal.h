@@ -6,6 +6,9 @@
 
 namespace gd {
 
+// Records `msg` as the calling thread's last error and returns `code`.
+int gd_fail(int code, const char *msg);
+
 // Epilogue of the dense coupling kernel.
 enum StepMode : int {
     MODE_EULER = 0,   // psi_out = psi + dt f, gamma += dt phi
@@ -71,6 +74,37 @@ int dense_lp_config_count();
 DenseConfig dense_lp_config(bool complex_mode, int idx);
 hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                                 bool j_fp8, const DenseStepArgs &a, hipStream_t st);
+
+// ---- batched sparse solver (gd_batch.hip)
+struct BatchArgs {
+    const int *inst_n;            // [K] spins per instance
+    const long long *inst_spin;   // [K] offset of the instance's spins in per-spin arrays
+    const long long *inst_state;  // [K] offset of the instance's [R][n] state block
+    const float *inst_inv_s;      // [K] 1 / coupling scale
+    const int *ell_idx;           // [sum n][dmax] local neighbour indices (padding: 0)
+    const float *ell_w;           // [sum n][dmax] couplings (padding: 0)
+    const float *eps, *h1, *g;    // [sum n]
+    float *x, *gam;               // state [sum_k R n_k]
+    double *E;                    // [K][R] energies after the launch
+    int *flags;                   // [K][R] non-finite flags
+    const int *wg_off;            // [nwg + 1] item ranges per workgroup
+    const int *items;             // item = k * nslices + slice
+    int nslices, R, dmax, nmax, steps;
+    float dt, gamma_c, rho_th;
+};
+
+struct BatchConfig {
+    int id;
+    int traj;     // trajectories per work item
+    int threads;  // workgroup size
+    int slots;    // spins per thread (n_max <= slots * threads / traj)
+};
+
+int batch_config_count();
+BatchConfig batch_config(int idx);
+size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax);
+hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax);   // once per variant, outside capture
+hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipStream_t st);
 
 // ---- auxiliary kernels (gd_aux.hip)
 // user [R][n] (or [R][n][2]) -> zero-padded planes [P][Rp][Np]

@@ -5,6 +5,7 @@
 // Eq. (h) onto the q = 1 term h_1 = -g sqrt(rho_th)/s of Eq. (main), pad to
 // the row tile and upload.  Run: one dense coupling launch per Euler step or
 // per RK4 stage, with the amplitude/gain update fused in (gd_dense.hip).
+#include "gd_batch_rt.h"
 #include "gd_internal.h"
 #include "../../include/gd.h"
 
@@ -94,7 +95,10 @@ std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (complex, Np, Rp
 
 }  // namespace
 
+int gd::gd_fail(int code, const char *msg) { return fail(code, msg ? msg : ""); }
+
 struct gd_solver {
+    gd::BatchSolver *batch = nullptr;   // non-null: a batch of instances (gd_create_batch)
     int n = 0, Np = 0, model = 0, P = 1;
     gd_params prm{};
     double s = 1.0;
@@ -657,6 +661,11 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
 
 void gd_destroy(gd_solver *s) {
     if (!s) return;
+    if (s->batch) {
+        batch_destroy(s->batch);
+        delete s;
+        return;
+    }
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     free_state(s);
     if (s->dJ) (void)hipFree(s->dJ);
@@ -672,6 +681,7 @@ void gd_destroy(gd_solver *s) {
 int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gamma0,
                 const float *eps) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_set_init(s->batch, batch, psi0, gamma0, eps);
     if (batch < 1 || batch > (1 << 22)) return fail(GD_E_INVALID_ARG, "batch out of range");
     int rc;
     if ((rc = set_eps(s, eps)) != GD_OK) return rc;
@@ -712,6 +722,7 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
 
 int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_run(s->batch, batch, steps);
     if (steps < 0) return fail(GD_E_INVALID_ARG, "steps must be >= 0");
     int rc;
     if (!s->have_state) {
@@ -791,6 +802,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
 
 static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_energy(s->batch, E, best);
     if (!s->have_state) return fail(GD_E_STATE, "no state: call gd_set_init or gd_run first");
     if (!E) return fail(GD_E_INVALID_ARG, "E is NULL");
     const float *cur = s->psi[s->cur];
@@ -826,6 +838,10 @@ int gd_energy_device(gd_solver *s, double *E, int32_t *best) { return energies(s
 
 int gd_spins(gd_solver *s, void *out, int32_t fmt) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) {
+        if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+        return batch_spins(s->batch, out, fmt);
+    }
     if (!s->have_state) return fail(GD_E_STATE, "no state");
     if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
     if (fmt != GD_SPINS_I8 && fmt != GD_SPINS_ANGLE_F32) return fail(GD_E_INVALID_ARG, "unknown format");
@@ -851,6 +867,7 @@ int gd_spins(gd_solver *s, void *out, int32_t fmt) {
 
 int gd_get_state(gd_solver *s, float *psi, float *gamma, int64_t *step) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_get_state(s->batch, psi, gamma, step);
     if (!s->have_state) return fail(GD_E_STATE, "no state");
     int rc;
     if (psi && (rc = download_planes(s, s->psi[s->cur], psi, s->P)) != GD_OK) return rc;
@@ -861,6 +878,7 @@ int gd_get_state(gd_solver *s, float *psi, float *gamma, int64_t *step) {
 
 int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gamma, int64_t step) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_set_state(s->batch, batch, psi, gamma, step);
     if (!psi || !gamma) return fail(GD_E_INVALID_ARG, "psi and gamma are required");
     if (batch < 1 || batch > (1 << 22) || step < 0) return fail(GD_E_INVALID_ARG, "bad batch or step");
     std::vector<float> chk;
@@ -891,6 +909,7 @@ int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gam
 int gd_stats(gd_solver *s, gd_run_stats *out) {
     if (!s || !out) return fail(GD_E_INVALID_ARG, "NULL argument");
     if (out->struct_size != sizeof(gd_run_stats)) return fail(GD_E_INVALID_ARG, "gd_run_stats.struct_size mismatch");
+    if (s->batch) return batch_stats(s->batch, out);
     out->batch = s->R;
     out->steps_done = s->steps_done;
     out->spin_updates = s->spin_updates;
@@ -909,7 +928,56 @@ int gd_stats(gd_solver *s, gd_run_stats *out) {
 
 int gd_coupling_scale(gd_solver *s, double *scale) {
     if (!s || !scale) return fail(GD_E_INVALID_ARG, "NULL argument");
+    if (s->batch) {
+        *scale = batch_scale(s->batch, 0);
+        return GD_OK;
+    }
     *scale = s->s;
+    return GD_OK;
+}
+
+int gd_create_batch(gd_solver **out, int32_t count, const gd_instance *inst, int32_t model,
+                    const gd_params *p) {
+    if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    gd_params prm;
+    if (p) prm = *p;
+    else gd_default_params(&prm);
+    int rc = check_params(&prm);
+    if (rc != GD_OK) return rc;
+    gd::BatchSolver *b = nullptr;
+    if ((rc = batch_create(&b, count, inst, model, &prm)) != GD_OK) return rc;
+    gd_solver *s = new (std::nothrow) gd_solver();
+    if (!s) {
+        batch_destroy(b);
+        return fail(GD_E_OOM, "host allocation failed");
+    }
+    s->batch = b;
+    s->prm = prm;
+    s->model = model;
+    *out = s;
+    return GD_OK;
+}
+
+int gd_set_targets(gd_solver *s, const double *targets) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_set_targets(s->batch, targets);
+    if (targets) {
+        s->prm.target_energy = targets[0];
+        s->prm.has_target = 1;
+    } else {
+        s->prm.has_target = 0;
+    }
+    s->target_reached = 0;
+    return GD_OK;
+}
+
+int gd_ttt(gd_solver *s, double *seconds, int64_t *steps, double *best_energy) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return batch_ttt(s->batch, seconds, steps, best_energy);
+    if (seconds) *seconds = s->target_reached ? s->ttt_seconds : -1.0;
+    if (steps) *steps = s->target_reached ? s->ttt_steps : -1;
+    if (best_energy) *best_energy = s->best_energy;
     return GD_OK;
 }
 

@@ -30,7 +30,8 @@ GD_F_DEVICE_PTRS, GD_F_ASYNC, GD_F_PROFILE = 0x1, 0x2, 0x4
 EXPORTS = (
     "gd_default_params", "gd_create", "gd_destroy", "gd_set_init", "gd_run", "gd_energy",
     "gd_energy_device", "gd_spins", "gd_get_state", "gd_set_state", "gd_stats",
-    "gd_coupling_scale", "gd_error_string", "gd_last_error",
+    "gd_coupling_scale", "gd_error_string", "gd_last_error", "gd_create_batch", "gd_set_targets",
+    "gd_ttt",
 )
 
 
@@ -51,6 +52,13 @@ class gd_run_stats(C.Structure):
         ("kernel_launches", C.c_int64), ("diverged", C.c_int32), ("target_reached", C.c_int32),
         ("ttt_seconds", C.c_double), ("ttt_steps", C.c_int64), ("best_energy", C.c_double),
         ("best_index", C.c_int32), ("kernel_config", C.c_int32),
+    ]
+
+
+class gd_instance(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("J", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+        ("val", C.c_void_p), ("g", C.c_void_p),
     ]
 
 
@@ -93,6 +101,9 @@ def load(path: str = LIB_PATH):
     lib.gd_set_state.argtypes = [vp, i32, vp, vp, i64]
     lib.gd_stats.argtypes = [vp, C.POINTER(gd_run_stats)]
     lib.gd_coupling_scale.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.gd_create_batch.argtypes = [C.POINTER(vp), i32, vp, i32, C.POINTER(gd_params)]
+    lib.gd_set_targets.argtypes = [vp, vp]
+    lib.gd_ttt.argtypes = [vp, vp, vp, vp]
     lib.gd_error_string.argtypes = [C.c_int]
     lib.gd_error_string.restype = C.c_char_p
     lib.gd_last_error.argtypes = []
@@ -266,3 +277,119 @@ class Solver:
     @property
     def scale(self):
         return gd_coupling_scale(self.h)
+
+
+def gd_create_batch(instances, model=GD_ISING, params: gd_params | None = None):
+    """instances: list of dicts with 'n' and either 'J' (dense [n][n]) or CSR
+    'row_ptr', 'col', 'val', optional 'g' (host numpy).  Returns (handle, keep)
+    where keep holds the marshalled arrays alive for the call."""
+    lib = load()
+    arr = (gd_instance * len(instances))()
+    keep = []
+    for k, inst in enumerate(instances):
+        a = arr[k]
+        a.n = int(inst["n"])
+        for name, dt in (("J", np.float32), ("row_ptr", np.int32), ("col", np.int32),
+                         ("val", np.float32), ("g", np.float32)):
+            v = inst.get(name)
+            if v is not None:
+                v = np.ascontiguousarray(v, dtype=dt)
+                keep.append(v)
+                setattr(a, name, v.ctypes.data_as(C.c_void_p))
+    h = C.c_void_p()
+    _check(lib.gd_create_batch(C.byref(h), len(instances), C.cast(arr, C.c_void_p), int(model),
+                               C.byref(params) if params is not None else None), "gd_create_batch")
+    return h
+
+
+def gd_set_targets(h, targets):
+    t = None if targets is None else np.ascontiguousarray(targets, np.float64)
+    _check(load().gd_set_targets(h, None if t is None else t.ctypes.data_as(C.c_void_p)), "gd_set_targets")
+
+
+def gd_ttt(h, count):
+    sec = np.empty(count, np.float64)
+    st = np.empty(count, np.int64)
+    be = np.empty(count, np.float64)
+    _check(load().gd_ttt(h, sec.ctypes.data_as(C.c_void_p), st.ctypes.data_as(C.c_void_p),
+                         be.ctypes.data_as(C.c_void_p)), "gd_ttt")
+    return sec, st, be
+
+
+class BatchSolver:
+    """Owning wrapper of a gd_create_batch handle (host arrays, Ising, Euler)."""
+
+    def __init__(self, instances, **params):
+        self.ns = [int(i["n"]) for i in instances]
+        self.K = len(instances)
+        self.total = int(sum(self.ns))
+        self.params = default_params(**params)
+        self.h = gd_create_batch(instances, GD_ISING, self.params)
+        self.R = 0
+
+    def close(self):
+        if self.h is not None:
+            gd_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_init(self, R, psi0=None, gamma0=None, eps=None):
+        gd_set_init(self.h, R, psi0, gamma0, eps)
+        self.R = int(R)
+
+    def run(self, steps, R=None):
+        gd_run(self.h, self.R if R is None else R, steps)
+        if R is not None:
+            self.R = int(R)
+
+    def state(self):
+        psi = np.empty(self.total * self.R, np.float32)
+        gam = np.empty(self.total * self.R, np.float32)
+        step = C.c_int64()
+        _check(load().gd_get_state(self.h, psi.ctypes.data_as(C.c_void_p),
+                                   gam.ctypes.data_as(C.c_void_p), C.byref(step)), "gd_get_state")
+        return psi, gam, int(step.value)
+
+    def set_state(self, psi, gamma, R, step=0):
+        gd_set_state(self.h, R, np.ravel(psi), np.ravel(gamma), step)
+        self.R = int(R)
+
+    def split(self, flat):
+        """concatenated [sum_k R n_k] -> list of [R][n_k]"""
+        out, off = [], 0
+        for n in self.ns:
+            out.append(np.asarray(flat[off:off + self.R * n]).reshape(self.R, n))
+            off += self.R * n
+        return out
+
+    def energy(self):
+        E = np.empty(self.K * self.R, np.float64)
+        best = np.empty(self.K, np.int32)
+        _check(load().gd_energy(self.h, E.ctypes.data_as(C.c_void_p), best.ctypes.data_as(C.c_void_p)),
+               "gd_energy")
+        return E.reshape(self.K, self.R), best
+
+    def spins(self):
+        out = np.empty(self.total * self.R, np.int8)
+        _check(load().gd_spins(self.h, out.ctypes.data_as(C.c_void_p), GD_SPINS_I8), "gd_spins")
+        return out
+
+    def set_targets(self, targets):
+        gd_set_targets(self.h, targets)
+
+    def ttt(self):
+        return gd_ttt(self.h, self.K)
+
+    def stats(self):
+        return gd_stats(self.h)
