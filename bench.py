@@ -102,19 +102,7 @@ def cpu_baseline(wl, J, psi0, target_s):
 
 def batch_instances(K, seed=1):
     from paper_1807_00699_amd import inputs as I
-    sizes = I.even_sizes(K, 50, 2000, seed)
-    insts = []
-    for k, n in enumerate(sizes):
-        e, w, _ = I.regular3_maxcut(int(n), 1000 * seed + k)
-        rows = np.concatenate([e, e[:, ::-1]])
-        vals = np.concatenate([w, w])
-        order = np.lexsort((rows[:, 1], rows[:, 0]))
-        rows, vals = rows[order], vals[order]
-        rp = np.zeros(n + 1, np.int64)
-        np.add.at(rp, rows[:, 0] + 1, 1)
-        insts.append(dict(n=int(n), row_ptr=np.cumsum(rp).astype(np.int32),
-                          col=rows[:, 1].astype(np.int32), val=vals.astype(np.float32)))
-    return sizes, insts
+    return I.maxcut_batch(K, 50, 2000, seed)
 
 
 # algorithmic FP32 flops of one spin-update of the sparse Euler step:

@@ -260,6 +260,73 @@ int gd_ttt(gd_solver *s, double *seconds, int64_t *steps, double *best_energy);
 const char *gd_error_string(int code);
 const char *gd_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal.  The paper suggests site-dependent gain-adjustment rates
+ * eps_i(t) as an extension (Sec. 3); the sub-threshold phase of the dynamics
+ * amplifies the leading eigenvectors of J (Sec. 1).  A per-spin network reads
+ * GD_NFEAT features of J and proposes a sign for each spin (biasing the
+ * initial amplitudes) and a confidence (setting eps_i).  The random-start
+ * solver stays the fallback and judges the energies.
+ * ------------------------------------------------------------------------ */
+#define GD_NFEAT 20
+#define GD_MLP_NPARAM 5634
+
+/*
+ * gd_features (batch solvers): per spin, in the concatenated spin order,
+ * GD_NFEAT floats: [0] sum_j J_ij/s, [1] degree / mean degree, [2..9]
+ * sqrt(n) v_k[i], [10..17] n lambda_k v_k[i]^2, [18] sum_j |J_ij|/s, [19] 1,
+ * where (lambda_k, v_k), k < 8, are the Ritz pairs of J/s after `iters`
+ * steps of block power iteration on J/s + cI (c = max_i sum_j |J_ij|/s)
+ * from a SplitMix64 start block, with Cholesky-QR each step, each v_k
+ * sign-fixed so that its largest-magnitude entry is positive (ties: lowest
+ * index).  lambda [count][8] and vecs [sum n][8] are optional (NULL).
+ * Instances need n <= 2560.  Host output pointers.
+ */
+int gd_features(gd_solver *s, int32_t iters, float *feats, float *lambda, float *vecs);
+
+/* Network GD_NFEAT -> 64 -> 64 -> 2 (ReLU), parameters (GD_MLP_NPARAM floats):
+ * W1 [20][64], b1 [64], W2 [64][64], b2 [64], W3 [64][2], b3 [2].
+ * Outputs per spin: o0 (sign logit, m = tanh o0) and o1 (confidence logit,
+ * c = sigmoid o1). */
+typedef struct gd_mlp gd_mlp;
+
+/* params NULL: He-normal weights from SplitMix64 + Box-Muller keyed by seed,
+ * zero biases.  flags: GD_F_DEVICE_PTRS makes X/labels/out/params of the
+ * calls below device pointers (seg stays host memory). */
+int gd_mlp_create(gd_mlp **out, const float *params, uint64_t seed, uint32_t flags);
+void gd_mlp_destroy(gd_mlp *m);
+/* replace the parameters (NULL keeps them) and reset the Adam moments */
+int gd_mlp_set_params(gd_mlp *m, const float *params);
+int gd_mlp_get_params(gd_mlp *m, float *params);
+
+/* outputs [M][2] for features X [M][GD_NFEAT]; fp16 != 0 runs the FP16
+ * inference kernel (parameters and activations in half precision). */
+int gd_mlp_forward(gd_mlp *m, int32_t M, const float *X, float *out, int32_t fp16);
+
+/*
+ * gd_mlp_train_step: one FP32 step on M rows from K instances (rows
+ * seg[k]..seg[k+1]-1 belong to instance k; seg host memory) with labels +-1,
+ * a low-energy state of each instance.  Loss (per instance the label is
+ * aligned to the prediction by the global flip sigma_k of Eq. (h)):
+ *   L = (1/M) sum_i [(m_i - sigma_k s_i)^2 + 0.5 BCE(c_i, [m_i sigma_k s_i > 0])].
+ * lr > 0 applies Adam (0.9, 0.999, 1e-8, bias-corrected); lr = 0 only
+ * evaluates.  loss and grad [GD_MLP_NPARAM] (host, nullable) receive the
+ * loss and the gradient at the parameters before the update.
+ */
+int gd_mlp_train_step(gd_mlp *m, int32_t M, const float *X, const float *labels, int32_t K,
+                      const int32_t *seg, float lr, double *loss, float *grad);
+
+/*
+ * gd_propose (batch solvers): features (feat_iters iterations) -> FP16
+ * network -> initial state of R trajectories per instance:
+ *   psi0_ir = init_amp (alpha m_i + (1 - alpha) (2u - 1)),
+ *   u = SplitMix64 uniform of counter ((k 2^20 + r) 2^16 + i) and `seed`,
+ *   gamma_ir(0) = params.gamma0, eps_i = params.eps exp(beta (c_i - 1/2));
+ * then behaves as gd_set_init.
+ */
+int gd_propose(gd_solver *s, gd_mlp *m, int32_t R, int32_t feat_iters, double alpha, double beta,
+               uint64_t seed);
+
 #ifdef __cplusplus
 }
 #endif

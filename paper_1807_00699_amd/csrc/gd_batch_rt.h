@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+
 namespace gd {
 
 struct BatchSolver;
@@ -21,6 +23,25 @@ int batch_stats(BatchSolver *b, gd_run_stats *out);
 int batch_set_targets(BatchSolver *b, const double *targets);
 int batch_ttt(BatchSolver *b, double *seconds, int64_t *steps, double *best_energy);
 int batch_count(const BatchSolver *b);
+
+// Device view of a batch solver for the learned-proposal kernels.
+struct BatchView {
+    int K, dmax, nmax, R;
+    long long total;
+    const int *d_n;
+    const long long *d_spin, *d_state;
+    const float *d_inv_s;
+    const int *d_idx;
+    const float *d_w;
+    float *d_eps, *d_x, *d_gam;
+    hipStream_t stream;
+    double eps0, gamma0, amp;
+};
+int batch_view(BatchSolver *b, BatchView *v);
+// allocate the state for R trajectories (contents undefined), reset statistics
+int batch_prepare_state(BatchSolver *b, int R);
+// after x, gamma and eps were written on the device: pick the kernel variant
+int batch_finish_init(BatchSolver *b);
 double batch_scale(const BatchSolver *b, int k);
 
 }  // namespace gd

@@ -697,6 +697,42 @@ int batch_ttt(BatchSolver *b, double *seconds, int64_t *steps, double *best_ener
 }
 
 int batch_count(const BatchSolver *b) { return b->K; }
+
+int batch_view(BatchSolver *b, BatchView *v) {
+    v->K = b->K;
+    v->dmax = b->dmax;
+    v->nmax = b->nmax;
+    v->R = b->R;
+    v->total = b->total;
+    v->d_n = b->d_n;
+    v->d_spin = b->d_spin;
+    v->d_state = b->d_state;
+    v->d_inv_s = b->d_inv_s;
+    v->d_idx = b->d_idx;
+    v->d_w = b->d_w;
+    v->d_eps = b->d_eps;
+    v->d_x = b->d_x;
+    v->d_gam = b->d_gam;
+    v->stream = b->stream;
+    v->eps0 = b->prm.eps;
+    v->gamma0 = b->prm.gamma0;
+    v->amp = b->prm.init_amp;
+    return GD_OK;
+}
+
+int batch_prepare_state(BatchSolver *b, int R) {
+    if (R < 1 || R > (1 << 16)) return gd_fail(GD_E_INVALID_ARG, "batch out of range");
+    int rc = alloc_state(b, R);
+    if (rc != GD_OK) return rc;
+    reset_stats(b);
+    return GD_OK;
+}
+
+int batch_finish_init(BatchSolver *b) {
+    GD_TRY(hipStreamSynchronize(b->stream));
+    GD_TRY(hipMemcpy(b->eps_host.data(), b->d_eps, b->total * 4, hipMemcpyDeviceToHost));
+    return choose_config(b);
+}
 double batch_scale(const BatchSolver *b, int k) { return b->scale[k]; }
 
 }  // namespace gd

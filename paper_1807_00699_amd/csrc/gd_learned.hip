@@ -1,0 +1,612 @@
+// Learned proposal of initial amplitudes and per-spin gain rates.
+//
+// The paper suggests site-dependent gain-adjustment rates eps_i(t) as an
+// extension of the GD algorithm (Sec. 3); its sub-threshold phase amplifies
+// the leading eigenvectors of J (gain rising from below, Sec. 1).  Here a
+// small per-spin network reads spectral and local features of J and proposes
+// (i) a sign for each spin, used to bias the initial amplitudes, and (ii) a
+// confidence, used to set eps_i.  Kernels:
+//
+//  feat_k      one workgroup per instance: shifted block power iteration on
+//              A = J/s + cI (c = max row sum of |J|/s), Cholesky-QR each
+//              iteration, Rayleigh-Ritz (8x8 cyclic Jacobi in FP64), sign
+//              fix (largest-magnitude entry of each vector positive, ties to
+//              the lowest index), then 20 features per spin.
+//  mlp_*       20 -> 64 -> 64 -> 2 ReLU network: FP32 forward, per-instance
+//              flip-invariant loss, backward, weight-gradient partials over
+//              spin chunks, fixed-order reduction fused with Adam; FP16
+//              inference (packed half arithmetic).
+//  propose_k   writes psi0 = a (alpha m_i + (1 - alpha) xi) and eps_i into a
+//              batched solver's state, xi from SplitMix64.
+#include "gd_internal.h"
+#include "gd_learned.h"
+
+#include <hip/hip_fp16.h>
+
+namespace gd {
+
+namespace {
+
+constexpr int F = kMlpF, H = kMlpH, NO = kMlpOut;
+constexpr int OFF_W1 = 0, OFF_B1 = F * H, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
+              OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + H * NO, NPAR = OFF_B3 + NO;
+static_assert(NPAR == kMlpNParam, "parameter layout");
+constexpr float LAMBDA_C = 0.5f;
+
+__host__ __device__ inline unsigned long long splitmix64(unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ inline double uniform01(unsigned long long ctr, unsigned long long key) {
+    return double(splitmix64(key ^ splitmix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// block-wide sum of NV doubles per thread (256 threads); result in out[] of every thread
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *scratch /* [4][NV] */) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        v[q] = x;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) scratch[w * NV + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = scratch[q] + scratch[NV + q] + scratch[2 * NV + q] + scratch[3 * NV + q];
+    __syncthreads();
+}
+
+// 8x8 symmetric eigenproblem by cyclic Jacobi rotations (FP64); eigenvalues
+// descending in th, eigenvectors as columns of U.
+__device__ inline void jacobi8(double (&A)[8][8], double (&U)[8][8], double (&th)[8]) {
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) U[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < 8; ++p)
+            for (int q = p + 1; q < 8; ++q) off += A[p][q] * A[p][q];
+        if (off < 1e-30) break;
+        for (int p = 0; p < 8; ++p)
+            for (int q = p + 1; q < 8; ++q) {
+                if (fabs(A[p][q]) < 1e-300) continue;
+                const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < 8; ++k) {          // A <- A G  (columns p, q)
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 8; ++k) {          // A <- G^T A (rows p, q)
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < 8; ++k) {          // U <- U G
+                    const double ukp = U[k][p], ukq = U[k][q];
+                    U[k][p] = c * ukp - s * ukq;
+                    U[k][q] = s * ukp + c * ukq;
+                }
+            }
+    }
+    for (int i = 0; i < 8; ++i) th[i] = A[i][i];
+    // selection sort, descending (stable for equal values)
+    for (int i = 0; i < 8; ++i) {
+        int b = i;
+        for (int j = i + 1; j < 8; ++j)
+            if (th[j] > th[b]) b = j;
+        if (b != i) {
+            const double tt = th[i]; th[i] = th[b]; th[b] = tt;
+            for (int k = 0; k < 8; ++k) { const double u = U[k][i]; U[k][i] = U[k][b]; U[k][b] = u; }
+        }
+    }
+}
+
+constexpr int FT = 256;   // threads of the feature kernel
+
+__global__ void __launch_bounds__(FT) feat_k(FeatArgs a) {
+    extern __shared__ __attribute__((aligned(16))) float fsm[];
+    const int k = blockIdx.x;
+    const int n = a.inst_n[k];
+    const long long spin0 = a.inst_spin[k];
+    const int dmax = a.dmax;
+    const float inv_s = a.inst_inv_s[k];
+    float *V = fsm;                          // [nmax][8]
+    float *W = fsm + (size_t)a.nmax * 8;     // [nmax][8]
+    __shared__ double red[4 * 36];
+    __shared__ double mat[8][8];             // broadcast of L^-1 / U
+    __shared__ double shift;
+    const int tid = threadIdx.x;
+    // shift c = max_i sum_j |J_ij| / s, mean degree
+    double cmax = 0.0, degsum = 0.0;
+    for (int i = tid; i < n; i += FT) {
+        double r = 0.0;
+        for (int d = 0; d < dmax; ++d) {
+            const float w = a.ell_w[(spin0 + i) * dmax + d];
+            r += fabs((double)w) * inv_s;
+            degsum += (w != 0.0f);
+        }
+        cmax = fmax(cmax, r);
+    }
+    for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o));
+    {
+        double v[1] = {degsum};
+        if ((tid & 63) == 0) red[64 + (tid >> 6)] = cmax;
+        block_sum<1>(v, red);
+        degsum = v[0];
+    }
+    if (tid == 0) shift = fmax(fmax(red[64], red[65]), fmax(red[66], red[67]));
+    __syncthreads();
+    const double c = shift;
+    // V0 from SplitMix64
+    for (int i = tid; i < n; i += FT)
+        for (int q = 0; q < 8; ++q)
+            V[i * 8 + q] = float(2.0 * uniform01((unsigned long long)(8 * i + q), kFeatKey) - 1.0);
+    __syncthreads();
+    auto apply = [&]() {   // W = A V
+        for (int i = tid; i < n; i += FT) {
+            float acc[8];
+            for (int q = 0; q < 8; ++q) acc[q] = float(c) * V[i * 8 + q];
+            for (int d = 0; d < dmax; ++d) {
+                const float w = a.ell_w[(spin0 + i) * dmax + d] * inv_s;
+                const int j = a.ell_idx[(spin0 + i) * dmax + d];
+                for (int q = 0; q < 8; ++q) acc[q] += w * V[j * 8 + q];
+            }
+            for (int q = 0; q < 8; ++q) W[i * 8 + q] = acc[q];
+        }
+        __syncthreads();
+    };
+    for (int it = 0; it < a.iters; ++it) {
+        apply();
+        // G = W^T W (upper triangle, FP64)
+        double g[36];
+        for (int q = 0; q < 36; ++q) g[q] = 0.0;
+        for (int i = tid; i < n; i += FT) {
+            int q = 0;
+            for (int p = 0; p < 8; ++p)
+                for (int r = p; r < 8; ++r) g[q++] += (double)W[i * 8 + p] * (double)W[i * 8 + r];
+        }
+        block_sum<36>(g, red);
+        if (tid == 0) {
+            // Cholesky G = L L^T, then L^-1 (lower triangular)
+            double G[8][8], L[8][8], Li[8][8];
+            int q = 0;
+            for (int p = 0; p < 8; ++p)
+                for (int r = p; r < 8; ++r) { G[p][r] = g[q]; G[r][p] = g[q]; ++q; }
+            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) L[i][j] = Li[i][j] = 0.0;
+            for (int j = 0; j < 8; ++j) {
+                double d = G[j][j];
+                for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+                L[j][j] = sqrt(fmax(d, 1e-300));
+                for (int i = j + 1; i < 8; ++i) {
+                    double v = G[i][j];
+                    for (int p = 0; p < j; ++p) v -= L[i][p] * L[j][p];
+                    L[i][j] = v / L[j][j];
+                }
+            }
+            for (int j = 0; j < 8; ++j) {
+                Li[j][j] = 1.0 / L[j][j];
+                for (int i = j + 1; i < 8; ++i) {
+                    double v = 0.0;
+                    for (int p = j; p < i; ++p) v -= L[i][p] * Li[p][j];
+                    Li[i][j] = v / L[i][i];
+                }
+            }
+            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) mat[i][j] = Li[i][j];
+        }
+        __syncthreads();
+        // V = W L^-T: V_i[q] = sum_p W_i[p] Li[q][p]
+        for (int i = tid; i < n; i += FT)
+            for (int q = 0; q < 8; ++q) {
+                double v = 0.0;
+                for (int p = 0; p <= q; ++p) v += (double)W[i * 8 + p] * mat[q][p];
+                V[i * 8 + q] = float(v);
+            }
+        __syncthreads();
+    }
+    // Rayleigh-Ritz: H = V^T A V
+    apply();
+    {
+        double h[36];
+        for (int q = 0; q < 36; ++q) h[q] = 0.0;
+        for (int i = tid; i < n; i += FT) {
+            int q = 0;
+            for (int p = 0; p < 8; ++p)
+                for (int r = p; r < 8; ++r) h[q++] += (double)V[i * 8 + p] * (double)W[i * 8 + r];
+        }
+        block_sum<36>(h, red);
+        if (tid == 0) {
+            double Hm[8][8], U[8][8], th[8];
+            int q = 0;
+            for (int p = 0; p < 8; ++p)
+                for (int r = p; r < 8; ++r) { Hm[p][r] = h[q]; Hm[r][p] = h[q]; ++q; }
+            jacobi8(Hm, U, th);
+            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) mat[i][j] = U[i][j];
+            for (int j = 0; j < 8; ++j) {
+                red[j] = th[j] - c;
+                if (a.lambda) a.lambda[(long long)k * 8 + j] = float(th[j] - c);
+            }
+        }
+        __syncthreads();
+        double lam[8];
+        for (int j = 0; j < 8; ++j) lam[j] = red[j];
+        __syncthreads();
+        // V <- V U (into W)
+        for (int i = tid; i < n; i += FT)
+            for (int q = 0; q < 8; ++q) {
+                double v = 0.0;
+                for (int p = 0; p < 8; ++p) v += (double)V[i * 8 + p] * mat[p][q];
+                W[i * 8 + q] = float(v);
+            }
+        __syncthreads();
+        // sign fix: largest magnitude entry positive (ties: lowest index)
+        __shared__ float bestv[4][8];
+        __shared__ int besti[4][8];
+        __shared__ float sgn[8];
+        for (int q = 0; q < 8; ++q) {
+            float bv = -1.0f;
+            int bi = 0x7fffffff;
+            for (int i = tid; i < n; i += FT) {
+                const float v = fabsf(W[i * 8 + q]);
+                if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const float ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if ((tid & 63) == 0) { bestv[tid >> 6][q] = bv; besti[tid >> 6][q] = bi; }
+        }
+        __syncthreads();
+        if (tid < 8) {
+            float bv = bestv[0][tid];
+            int bi = besti[0][tid];
+            for (int w = 1; w < 4; ++w)
+                if (bestv[w][tid] > bv || (bestv[w][tid] == bv && besti[w][tid] < bi)) {
+                    bv = bestv[w][tid];
+                    bi = besti[w][tid];
+                }
+            sgn[tid] = W[bi * 8 + tid] < 0.0f ? -1.0f : 1.0f;
+            if (a.lambda) { /* eigenvalues already written */ }
+        }
+        __syncthreads();
+        const double meandeg = degsum / n;
+        const float sn = sqrtf(float(n));
+        for (int i = tid; i < n; i += FT) {
+            double rs = 0.0, ra = 0.0, deg = 0.0;
+            for (int d = 0; d < dmax; ++d) {
+                const float w = a.ell_w[(spin0 + i) * dmax + d];
+                rs += (double)w * inv_s;
+                ra += fabs((double)w) * inv_s;
+                deg += (w != 0.0f);
+            }
+            float *f = a.feats + (spin0 + i) * F;
+            f[0] = float(rs);
+            f[1] = float(deg / fmax(meandeg, 1e-300));
+            for (int q = 0; q < 8; ++q) {
+                const float v = sgn[q] * W[i * 8 + q];
+                f[2 + q] = sn * v;
+                f[10 + q] = float(n * lam[q] * (double)v * v);
+            }
+            f[18] = float(ra);
+            f[19] = 1.0f;
+            if (a.vecs)
+                for (int q = 0; q < 8; ++q) a.vecs[(spin0 + i) * 8 + q] = sgn[q] * W[i * 8 + q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- MLP
+
+constexpr int MT = 256;
+
+__device__ inline void mlp_load_params(const float *__restrict__ p, float *sp) {
+    for (int q = threadIdx.x; q < NPAR; q += blockDim.x) sp[q] = p[q];
+    __syncthreads();
+}
+
+// forward of one spin with parameters in LDS; z1/z2 pre-activations
+__device__ inline void mlp_fwd1(const float *sp, const float *x, float *z1, float *z2, float *o) {
+    for (int j = 0; j < H; ++j) {
+        float acc = sp[OFF_B1 + j];
+        for (int f = 0; f < F; ++f) acc += x[f] * sp[OFF_W1 + f * H + j];
+        z1[j] = acc;
+    }
+    for (int b = 0; b < H; ++b) {
+        float acc = sp[OFF_B2 + b];
+        for (int j = 0; j < H; ++j) acc += fmaxf(z1[j], 0.0f) * sp[OFF_W2 + j * H + b];
+        z2[b] = acc;
+    }
+    for (int q = 0; q < NO; ++q) {
+        float acc = sp[OFF_B3 + q];
+        for (int b = 0; b < H; ++b) acc += fmaxf(z2[b], 0.0f) * sp[OFF_W3 + b * NO + q];
+        o[q] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(MT) mlp_forward_k(const float *__restrict__ p, const float *__restrict__ X,
+                                                   float *__restrict__ out, int M) {
+    __shared__ float sp[NPAR];
+    mlp_load_params(p, sp);
+    const int m = blockIdx.x * MT + threadIdx.x;
+    if (m >= M) return;
+    float x[F], z1[H], z2[H], o[NO];
+    for (int f = 0; f < F; ++f) x[f] = X[(long long)m * F + f];
+    mlp_fwd1(sp, x, z1, z2, o);
+    out[(long long)m * NO] = o[0];
+    out[(long long)m * NO + 1] = o[1];
+}
+
+__device__ inline __half2 relu2(__half2 v) {
+    const __half z = __float2half(0.0f);
+    return __halves2half2(__hmax(__low2half(v), z), __hmax(__high2half(v), z));
+}
+
+// FP16 inference: parameters and activations in half precision (packed pairs)
+__global__ void __launch_bounds__(MT) mlp_forward_f16_k(const float *__restrict__ p, const float *__restrict__ X,
+                                                       float *__restrict__ out, int M) {
+    __shared__ __half2 w1[F][H / 2], w2[H][H / 2], w3[H];
+    __shared__ __half2 b1[H / 2], b2[H / 2];
+    __shared__ float b3[NO];
+    for (int q = threadIdx.x; q < F * H / 2; q += MT) {
+        const int f = q / (H / 2), j = q % (H / 2);
+        w1[f][j] = __floats2half2_rn(p[OFF_W1 + f * H + 2 * j], p[OFF_W1 + f * H + 2 * j + 1]);
+    }
+    for (int q = threadIdx.x; q < H * H / 2; q += MT) {
+        const int a0 = q / (H / 2), j = q % (H / 2);
+        w2[a0][j] = __floats2half2_rn(p[OFF_W2 + a0 * H + 2 * j], p[OFF_W2 + a0 * H + 2 * j + 1]);
+    }
+    for (int q = threadIdx.x; q < H; q += MT) w3[q] = __floats2half2_rn(p[OFF_W3 + q * NO], p[OFF_W3 + q * NO + 1]);
+    for (int q = threadIdx.x; q < H / 2; q += MT) {
+        b1[q] = __floats2half2_rn(p[OFF_B1 + 2 * q], p[OFF_B1 + 2 * q + 1]);
+        b2[q] = __floats2half2_rn(p[OFF_B2 + 2 * q], p[OFF_B2 + 2 * q + 1]);
+    }
+    if (threadIdx.x < NO) b3[threadIdx.x] = p[OFF_B3 + threadIdx.x];
+    __syncthreads();
+    const int m = blockIdx.x * MT + threadIdx.x;
+    if (m >= M) return;
+    __half2 h1[H / 2], h2[H / 2];
+    for (int j = 0; j < H / 2; ++j) h1[j] = b1[j];
+    for (int f = 0; f < F; ++f) {
+        const __half2 xf = __float2half2_rn(X[(long long)m * F + f]);
+        for (int j = 0; j < H / 2; ++j) h1[j] = __hfma2(xf, w1[f][j], h1[j]);
+    }
+    for (int j = 0; j < H / 2; ++j) h1[j] = relu2(h1[j]);
+    for (int j = 0; j < H / 2; ++j) h2[j] = b2[j];
+    for (int a0 = 0; a0 < H; ++a0) {
+        const __half ha = (a0 & 1) ? __high2half(h1[a0 / 2]) : __low2half(h1[a0 / 2]);
+        const __half2 hh = __half2half2(ha);
+        for (int j = 0; j < H / 2; ++j) h2[j] = __hfma2(hh, w2[a0][j], h2[j]);
+    }
+    __half2 acc = __float2half2_rn(0.0f);
+    for (int j = 0; j < H / 2; ++j) {
+        const __half2 r = relu2(h2[j]);
+        acc = __hfma2(__half2half2(__low2half(r)), w3[2 * j], acc);
+        acc = __hfma2(__half2half2(__high2half(r)), w3[2 * j + 1], acc);
+    }
+    out[(long long)m * NO] = __low2float(acc) + b3[0];
+    out[(long long)m * NO + 1] = __high2float(acc) + b3[1];
+}
+
+// per instance: sigma_k (flip alignment) and loss sums
+__global__ void __launch_bounds__(256) mlp_segment_k(const float *__restrict__ out, const float *__restrict__ lab,
+                                                    const int *__restrict__ seg, float *__restrict__ sigma,
+                                                    double *__restrict__ seg_loss) {
+    __shared__ double red[4 * 2];
+    const int k = blockIdx.x;
+    double v[2] = {0.0, 0.0};
+    for (int i = seg[k] + threadIdx.x; i < seg[k + 1]; i += 256) {
+        const double m = tanh((double)out[2 * i]);
+        const double s = lab[i];
+        v[0] += (m - s) * (m - s);
+        v[1] += (m + s) * (m + s);
+    }
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) sigma[k] = v[0] <= v[1] ? 1.0f : -1.0f;
+}
+
+// backward per spin: dO, dH2, dH1 and the activations needed for weight grads
+__global__ void __launch_bounds__(MT) mlp_backward_k(MlpTrainArgs a) {
+    __shared__ float sp[NPAR];
+    mlp_load_params(a.params, sp);
+    const int m = blockIdx.x * MT + threadIdx.x;
+    if (m >= a.M) return;
+    const int k = a.spin_inst[m];
+    float x[F], z1[H], z2[H], o[NO];
+    for (int f = 0; f < F; ++f) x[f] = a.X[(long long)m * F + f];
+    mlp_fwd1(sp, x, z1, z2, o);
+    const float mm = tanhf(o[0]);
+    const float cc = 1.0f / (1.0f + expf(-o[1]));
+    const float t = a.sigma[k] * a.labels[m];
+    const float y = (mm * t > 0.0f) ? 1.0f : 0.0f;
+    const float invM = 1.0f / float(a.M);
+    const float d0 = 2.0f * (mm - t) * (1.0f - mm * mm) * invM;
+    const float d1 = LAMBDA_C * (cc - y) * invM;
+    // BCE(sigmoid(o1), y) in the stable logit form softplus(o1) - y o1
+    const float bce = fmaxf(o[1], 0.0f) - y * o[1] + log1pf(expf(-fabsf(o[1])));
+    a.spin_loss[m] = ((mm - t) * (mm - t) + LAMBDA_C * bce) * invM;
+    a.dO[(long long)m * NO] = d0;
+    a.dO[(long long)m * NO + 1] = d1;
+    float dh2[H];
+    for (int b = 0; b < H; ++b) {
+        const float g = d0 * sp[OFF_W3 + b * NO] + d1 * sp[OFF_W3 + b * NO + 1];
+        dh2[b] = z2[b] > 0.0f ? g : 0.0f;
+        a.H2[(long long)m * H + b] = fmaxf(z2[b], 0.0f);
+        a.dH2[(long long)m * H + b] = dh2[b];
+    }
+    for (int j = 0; j < H; ++j) {
+        float g = 0.0f;
+        for (int b = 0; b < H; ++b) g += dh2[b] * sp[OFF_W2 + j * H + b];
+        a.H1[(long long)m * H + j] = fmaxf(z1[j], 0.0f);
+        a.dH1[(long long)m * H + j] = z1[j] > 0.0f ? g : 0.0f;
+    }
+}
+
+// weight-gradient partials: block p reduces spins [p*chunk, (p+1)*chunk) into
+// partial[p][NPAR].  Each thread owns parameters q = tid + MT * slot.
+constexpr int WG_TILE = 32;
+constexpr int WG_SLOTS = (NPAR + MT - 1) / MT;
+__global__ void __launch_bounds__(MT) mlp_wgrad_k(MlpTrainArgs a, int chunk) {
+    __shared__ float sX[WG_TILE][F], sH1[WG_TILE][H], sH2[WG_TILE][H];
+    __shared__ float sD1[WG_TILE][H], sD2[WG_TILE][H], sDO[WG_TILE][NO];
+    float acc[WG_SLOTS];
+    for (int q = 0; q < WG_SLOTS; ++q) acc[q] = 0.0f;
+    const int m0 = blockIdx.x * chunk;
+    const int m1 = min(a.M, m0 + chunk);
+    for (int t0 = m0; t0 < m1; t0 += WG_TILE) {
+        const int cnt = min(WG_TILE, m1 - t0);
+        for (int q = threadIdx.x; q < WG_TILE * H; q += MT) {
+            const int r = q / H, c = q % H;
+            const bool in = r < cnt;
+            const long long m = (long long)(t0 + r);
+            sH1[r][c] = in ? a.H1[m * H + c] : 0.0f;
+            sH2[r][c] = in ? a.H2[m * H + c] : 0.0f;
+            sD1[r][c] = in ? a.dH1[m * H + c] : 0.0f;
+            sD2[r][c] = in ? a.dH2[m * H + c] : 0.0f;
+            if (c < F) sX[r][c] = in ? a.X[m * F + c] : 0.0f;
+            if (c < NO) sDO[r][c] = in ? a.dO[m * NO + c] : 0.0f;
+        }
+        __syncthreads();
+        for (int s = 0; s < WG_SLOTS; ++s) {
+            const int q = threadIdx.x + MT * s;
+            if (q >= NPAR) break;
+            float v = 0.0f;
+            if (q < OFF_B1) {
+                const int f = q / H, j = q % H;
+                for (int r = 0; r < WG_TILE; ++r) v += sX[r][f] * sD1[r][j];
+            } else if (q < OFF_W2) {
+                const int j = q - OFF_B1;
+                for (int r = 0; r < WG_TILE; ++r) v += sD1[r][j];
+            } else if (q < OFF_B2) {
+                const int j = (q - OFF_W2) / H, b = (q - OFF_W2) % H;
+                for (int r = 0; r < WG_TILE; ++r) v += sH1[r][j] * sD2[r][b];
+            } else if (q < OFF_W3) {
+                const int b = q - OFF_B2;
+                for (int r = 0; r < WG_TILE; ++r) v += sD2[r][b];
+            } else if (q < OFF_B3) {
+                const int b = (q - OFF_W3) / NO, o = (q - OFF_W3) % NO;
+                for (int r = 0; r < WG_TILE; ++r) v += sH2[r][b] * sDO[r][o];
+            } else {
+                const int o = q - OFF_B3;
+                for (int r = 0; r < WG_TILE; ++r) v += sDO[r][o];
+            }
+            acc[s] += v;
+        }
+        __syncthreads();
+    }
+    for (int s = 0; s < WG_SLOTS; ++s) {
+        const int q = threadIdx.x + MT * s;
+        if (q < NPAR) a.partial[(long long)blockIdx.x * NPAR + q] = acc[s];
+    }
+}
+
+// fixed-order sum of the partials, then Adam; loss = fixed-order sum of spin losses
+__global__ void __launch_bounds__(MT) mlp_adam_k(MlpTrainArgs a, int nparts, float lr, int step) {
+    const int q = blockIdx.x * MT + threadIdx.x;
+    if (q < NPAR) {
+        float g = 0.0f;
+        for (int pp = 0; pp < nparts; ++pp) g += a.partial[(long long)pp * NPAR + q];
+        if (a.grad_out) a.grad_out[q] = g;
+        if (lr > 0.0f) {
+            const float b1 = 0.9f, b2 = 0.999f;
+            const float mo = b1 * a.mom[q] + (1.0f - b1) * g;
+            const float ve = b2 * a.vel[q] + (1.0f - b2) * g * g;
+            a.mom[q] = mo;
+            a.vel[q] = ve;
+            const float mh = mo / (1.0f - powf(b1, float(step)));
+            const float vh = ve / (1.0f - powf(b2, float(step)));
+            a.params[q] -= lr * mh / (sqrtf(vh) + 1e-8f);
+        }
+    }
+}
+
+// loss = sum of the per-spin terms, fixed order (strided per thread, then a tree)
+__global__ void __launch_bounds__(1024) mlp_loss_k(const float *__restrict__ spin_loss, int M,
+                                                  double *__restrict__ loss) {
+    __shared__ double s[1024];
+    double v = 0.0;
+    for (int m = threadIdx.x; m < M; m += 1024) v += spin_loss[m];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = s[0];
+}
+
+__global__ void propose_k(ProposeArgs a) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= a.total_state) return;
+    // locate instance: binary search over state offsets
+    int lo = 0, hi = a.K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (a.inst_state[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int k = lo;
+    const int n = a.inst_n[k];
+    const long long rel = t - a.inst_state[k];
+    const int r = int(rel / n), i = int(rel % n);
+    const long long sp = a.inst_spin[k] + i;
+    const float m = tanhf(a.out[sp * NO]);
+    const unsigned long long ctr = (((unsigned long long)k << 20) + (unsigned long long)r) * 65536ull + i;
+    const double u = uniform01(ctr, a.seed);
+    a.x[t] = float(a.amp * (a.alpha * m + (1.0 - a.alpha) * (2.0 * u - 1.0)));
+    a.gam[t] = a.gamma0;
+    if (r == 0) {
+        const float c = 1.0f / (1.0f + expf(-a.out[sp * NO + 1]));
+        a.eps[sp] = float(a.eps0 * exp(a.beta * (c - 0.5)));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_features(const FeatArgs &a, int K, hipStream_t st) {
+    const size_t lds = (size_t)a.nmax * 16 * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&feat_k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    feat_k<<<K, FT, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *params, const float *X, float *out, int M, bool fp16,
+                              hipStream_t st) {
+    if (M <= 0) return hipSuccess;
+    const int g = (M + MT - 1) / MT;
+    if (fp16) mlp_forward_f16_k<<<g, MT, 0, st>>>(params, X, out, M);
+    else mlp_forward_k<<<g, MT, 0, st>>>(params, X, out, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_train_step(const MlpTrainArgs &a, int K, int nparts, float lr, int step,
+                                 hipStream_t st) {
+    const int g = (a.M + MT - 1) / MT;
+    mlp_forward_k<<<g, MT, 0, st>>>(a.params, a.X, a.out, a.M);
+    mlp_segment_k<<<K, 256, 0, st>>>(a.out, a.labels, a.seg, a.sigma, nullptr);
+    mlp_backward_k<<<g, MT, 0, st>>>(a);
+    const int chunk = (a.M + nparts - 1) / nparts;
+    mlp_wgrad_k<<<nparts, MT, 0, st>>>(a, chunk);
+    mlp_adam_k<<<(NPAR + MT - 1) / MT, MT, 0, st>>>(a, nparts, lr, step);
+    mlp_loss_k<<<1, 1024, 0, st>>>(a.spin_loss, a.M, a.loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_propose(const ProposeArgs &a, hipStream_t st) {
+    const long long g = (a.total_state + 255) / 256;
+    propose_k<<<unsigned(g), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace gd

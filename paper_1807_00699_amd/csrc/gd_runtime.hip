@@ -97,6 +97,10 @@ std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (complex, Np, Rp
 
 int gd::gd_fail(int code, const char *msg) { return fail(code, msg ? msg : ""); }
 
+namespace gd {
+BatchSolver *solver_batch(gd_solver *s);
+}
+
 struct gd_solver {
     gd::BatchSolver *batch = nullptr;   // non-null: a batch of instances (gd_create_batch)
     int n = 0, Np = 0, model = 0, P = 1;
@@ -497,6 +501,8 @@ int default_init(gd_solver *s, int R, const float *gamma0) {
 }
 
 }  // namespace
+
+gd::BatchSolver *gd::solver_batch(gd_solver *s) { return s ? s->batch : nullptr; }
 
 extern "C" {
 

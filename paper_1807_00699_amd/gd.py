@@ -31,8 +31,11 @@ EXPORTS = (
     "gd_default_params", "gd_create", "gd_destroy", "gd_set_init", "gd_run", "gd_energy",
     "gd_energy_device", "gd_spins", "gd_get_state", "gd_set_state", "gd_stats",
     "gd_coupling_scale", "gd_error_string", "gd_last_error", "gd_create_batch", "gd_set_targets",
-    "gd_ttt",
+    "gd_ttt", "gd_features", "gd_mlp_create", "gd_mlp_destroy", "gd_mlp_set_params",
+    "gd_mlp_get_params", "gd_mlp_forward", "gd_mlp_train_step", "gd_propose",
 )
+GD_NFEAT = 20
+GD_MLP_NPARAM = 5634
 
 
 class gd_params(C.Structure):
@@ -104,12 +107,22 @@ def load(path: str = LIB_PATH):
     lib.gd_create_batch.argtypes = [C.POINTER(vp), i32, vp, i32, C.POINTER(gd_params)]
     lib.gd_set_targets.argtypes = [vp, vp]
     lib.gd_ttt.argtypes = [vp, vp, vp, vp]
+    lib.gd_features.argtypes = [vp, i32, vp, vp, vp]
+    lib.gd_mlp_create.argtypes = [C.POINTER(vp), vp, C.c_uint64, C.c_uint32]
+    lib.gd_mlp_destroy.argtypes = [vp]
+    lib.gd_mlp_destroy.restype = None
+    lib.gd_mlp_set_params.argtypes = [vp, vp]
+    lib.gd_mlp_get_params.argtypes = [vp, vp]
+    lib.gd_mlp_forward.argtypes = [vp, i32, vp, vp, i32]
+    lib.gd_mlp_train_step.argtypes = [vp, i32, vp, vp, i32, vp, C.c_float, C.POINTER(C.c_double), vp]
+    lib.gd_propose.argtypes = [vp, vp, i32, i32, C.c_double, C.c_double, C.c_uint64]
     lib.gd_error_string.argtypes = [C.c_int]
     lib.gd_error_string.restype = C.c_char_p
     lib.gd_last_error.argtypes = []
     lib.gd_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("gd_default_params", "gd_destroy", "gd_error_string", "gd_last_error"):
+        if name not in ("gd_default_params", "gd_destroy", "gd_error_string", "gd_last_error",
+                        "gd_mlp_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -393,3 +406,77 @@ class BatchSolver:
 
     def stats(self):
         return gd_stats(self.h)
+
+
+def gd_features(h, total, K, iters=30):
+    """features [total][GD_NFEAT], lambda [K][8], Ritz vectors [total][8]"""
+    f = np.empty((total, GD_NFEAT), np.float32)
+    lam = np.empty((K, 8), np.float32)
+    vec = np.empty((total, 8), np.float32)
+    _check(load().gd_features(h, int(iters), f.ctypes.data_as(C.c_void_p), lam.ctypes.data_as(C.c_void_p),
+                              vec.ctypes.data_as(C.c_void_p)), "gd_features")
+    return f, lam, vec
+
+
+class MLP:
+    """Owning wrapper of a gd_mlp handle (host arrays)."""
+
+    def __init__(self, params=None, seed=0):
+        lib = load()
+        self.h = C.c_void_p()
+        p = None if params is None else np.ascontiguousarray(params, np.float32)
+        _check(lib.gd_mlp_create(C.byref(self.h), None if p is None else p.ctypes.data_as(C.c_void_p),
+                                 int(seed), 0), "gd_mlp_create")
+
+    def close(self):
+        if self.h is not None:
+            load().gd_mlp_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self):
+        p = np.empty(GD_MLP_NPARAM, np.float32)
+        _check(load().gd_mlp_get_params(self.h, p.ctypes.data_as(C.c_void_p)), "gd_mlp_get_params")
+        return p
+
+    @params.setter
+    def params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        _check(load().gd_mlp_set_params(self.h, p.ctypes.data_as(C.c_void_p)), "gd_mlp_set_params")
+
+    def forward(self, X, fp16=False):
+        X = np.ascontiguousarray(X, np.float32)
+        out = np.empty((X.shape[0], 2), np.float32)
+        _check(load().gd_mlp_forward(self.h, X.shape[0], X.ctypes.data_as(C.c_void_p),
+                                     out.ctypes.data_as(C.c_void_p), int(bool(fp16))), "gd_mlp_forward")
+        return out
+
+    def train_step(self, X, labels, seg, lr, want_grad=False):
+        X = np.ascontiguousarray(X, np.float32)
+        lab = np.ascontiguousarray(labels, np.float32)
+        seg = np.ascontiguousarray(seg, np.int32)
+        loss = C.c_double()
+        g = np.empty(GD_MLP_NPARAM, np.float32) if want_grad else None
+        _check(load().gd_mlp_train_step(self.h, X.shape[0], X.ctypes.data_as(C.c_void_p),
+                                        lab.ctypes.data_as(C.c_void_p), len(seg) - 1,
+                                        seg.ctypes.data_as(C.c_void_p), float(lr), C.byref(loss),
+                                        None if g is None else g.ctypes.data_as(C.c_void_p)),
+               "gd_mlp_train_step")
+        return (float(loss.value), g) if want_grad else float(loss.value)
+
+
+def gd_propose(h, mlp, R, feat_iters=30, alpha=0.5, beta=0.0, seed=0):
+    _check(load().gd_propose(h, mlp.h, int(R), int(feat_iters), float(alpha), float(beta), int(seed)),
+           "gd_propose")

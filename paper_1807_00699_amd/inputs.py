@@ -25,7 +25,7 @@ __all__ = [
     "rng", "sym_from_upper", "dense_pm1", "dense_gaussian", "dense_uniform",
     "sparse_pm1", "regular3_edges", "regular3_maxcut", "regular3_uniform_bounds",
     "edges_to_dense", "even_sizes", "psi0_real", "psi0_complex",
-    "planted_signs", "gauge",
+    "planted_signs", "gauge", "edges_to_csr", "maxcut_batch",
 ]
 
 # stream ids keep independent draws independent when seeds collide
@@ -158,3 +158,28 @@ def psi0_complex(n: int, R: int, seed: int, amp: float = 0.1) -> np.ndarray:
     out[..., 0] = amp * np.cos(phi)
     out[..., 1] = amp * np.sin(phi)
     return out.astype(np.float32)
+
+
+def edges_to_csr(n: int, edges: np.ndarray, w: np.ndarray) -> dict:
+    """Symmetric CSR (both directions of every edge, columns sorted) as the
+    dict accepted by the batched solver: n, row_ptr, col, val."""
+    rows = np.concatenate([edges, edges[:, ::-1]]).astype(np.int64)
+    vals = np.concatenate([w, w]).astype(np.float32)
+    order = np.lexsort((rows[:, 1], rows[:, 0]))
+    rows, vals = rows[order], vals[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows[:, 0] + 1, 1)
+    return dict(n=int(n), row_ptr=np.cumsum(rp).astype(np.int32), col=rows[:, 1].astype(np.int32),
+                val=vals)
+
+
+def maxcut_batch(count: int, lo: int, hi: int, seed: int):
+    """`count` random 3-regular max-cut instances (J = -1 on edges, gauged by a
+    random s*) with even sizes uniform in [lo, hi].  Instance k uses graph seed
+    1000 * seed + k.  Returns (sizes, list of CSR dicts)."""
+    sizes = even_sizes(count, lo, hi, seed)
+    insts = []
+    for k, n in enumerate(sizes):
+        e, w, _ = regular3_maxcut(int(n), 1000 * seed + k)
+        insts.append(edges_to_csr(int(n), e, w))
+    return sizes, insts
