@@ -245,7 +245,8 @@ int gd_create_batch(gd_solver **out, int32_t count, const gd_instance *inst, int
  * records for each instance the wall time and step count of the first check
  * where its best energy is <= its target; with has_target it stops once every
  * instance has reached its target.  For a single-instance solver this sets
- * params.target_energy and has_target.
+ * params.target_energy; gd_run then records the time-to-target and stops
+ * there only if params.has_target was set at creation.
  */
 int gd_set_targets(gd_solver *s, const double *targets);
 

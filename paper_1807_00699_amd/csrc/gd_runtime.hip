@@ -103,6 +103,7 @@ BatchSolver *solver_batch(gd_solver *s);
 
 struct gd_solver {
     gd::BatchSolver *batch = nullptr;   // non-null: a batch of instances (gd_create_batch)
+    bool track_target = false;          // gd_set_targets was called: record time-to-target
     int n = 0, Np = 0, model = 0, P = 1;
     gd_params prm{};
     double s = 1.0;
@@ -772,12 +773,13 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 s->best_energy = emin;
                 s->best_index = bi;
             }
-            if (s->prm.has_target && !s->target_reached && emin <= s->prm.target_energy) {
+            if ((s->prm.has_target || s->track_target) && !s->target_reached &&
+                emin <= s->prm.target_energy) {
                 s->target_reached = 1;
                 s->ttt_steps = s->steps_done;
                 s->ttt_seconds = s->run_seconds +
                                  std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                break;
+                if (s->prm.has_target) break;
             }
         }
     }
@@ -968,12 +970,8 @@ int gd_create_batch(gd_solver **out, int32_t count, const gd_instance *inst, int
 int gd_set_targets(gd_solver *s, const double *targets) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
     if (s->batch) return batch_set_targets(s->batch, targets);
-    if (targets) {
-        s->prm.target_energy = targets[0];
-        s->prm.has_target = 1;
-    } else {
-        s->prm.has_target = 0;
-    }
+    s->track_target = targets != nullptr;
+    if (targets) s->prm.target_energy = targets[0];
     s->target_reached = 0;
     return GD_OK;
 }
