@@ -8,7 +8,8 @@ GEMM, best-of-R) every `check` steps.  Default workload: XY model, N = 1024,
 J_ij ~ N(0, 1/N), R = 1024 complex trajectories, RK4 dt = 0.02, FP32, 5000
 steps.  Prints one JSON line with spin-updates/s (N * R * steps / s), the
 roofline position of the dominant kernel (device time per launch from HIP
-events recorded around every coupling launch on the solver's stream) and the
+events recorded on the solver's stream around the coupling launches of every
+8th step of the timed run) and the
 FP64 oracle timed on the host CPU over a bounded sample of the same workload.
 """
 from __future__ import annotations

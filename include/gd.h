@@ -83,7 +83,7 @@ typedef enum gd_spin_fmt {
 
 #define GD_F_DEVICE_PTRS 0x1u  /* array arguments are device pointers */
 #define GD_F_ASYNC 0x2u        /* gd_run returns without synchronising the stream */
-#define GD_F_PROFILE 0x4u      /* time each coupling-step launch with HIP events */
+#define GD_F_PROFILE 0x4u      /* time the coupling launches of every 8th step with HIP events */
 
 /* Parameters of a solver.  Fill with gd_default_params(), then override.
  * struct_size must be sizeof(gd_params) of the caller's header. */
@@ -114,8 +114,8 @@ typedef struct gd_run_stats {
     int64_t steps_done;       /* integration steps of the current trajectories */
     int64_t spin_updates;     /* sum over gd_run calls of n * R * steps */
     double run_seconds;       /* host wall time inside gd_run (synchronous calls) */
-    double kernel_ms;         /* summed device time of coupling-step launches (GD_F_PROFILE) */
-    int64_t kernel_launches;  /* number of coupling-step launches timed in kernel_ms */
+    double kernel_ms;         /* summed device time of the sampled coupling launches (GD_F_PROFILE) */
+    int64_t kernel_launches;  /* number of coupling launches timed in kernel_ms */
     int32_t diverged;         /* trajectories whose state became non-finite */
     int32_t target_reached;   /* 1 once a check met the target */
     double ttt_seconds;       /* wall time from the start of gd_run to that check */

@@ -44,6 +44,7 @@ int fail(int code, const std::string &msg) {
 inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
 constexpr int kTrajAlign = 128;  // Rp granularity: every dense variant tiles it
+constexpr int kProfileEvery = 8;  // GD_F_PROFILE samples the launches of every 8th step
 
 // SplitMix64 (Steele, Lea, Flood 2014) -> uniform double in [0, 1).
 inline uint64_t splitmix64(uint64_t x) {
@@ -748,8 +749,12 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             const int64_t to_check = ci - (s->steps_done % ci);
             chunk = std::min<int64_t>(chunk, to_check);
         }
-        for (int64_t k = 0; k < chunk; ++k)
-            if ((rc = enqueue_step(s, s->cfg, -1.0f, timed)) != GD_OK) return rc;
+        for (int64_t k = 0; k < chunk; ++k) {
+            // GD_F_PROFILE: HIP events around the coupling launches of every
+            // kProfileEvery-th step only, so the events barely perturb the run
+            const bool sample = timed && ((s->steps_done + k) % kProfileEvery == 0);
+            if ((rc = enqueue_step(s, s->cfg, -1.0f, sample)) != GD_OK) return rc;
+        }
         done += chunk;
         s->steps_done += chunk;
         s->spin_updates += (int64_t)s->n * s->R * chunk;
