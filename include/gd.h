@@ -7,13 +7,16 @@
  * coupling matrix J, the rate equations
  *
  *   dPsi_i/dt   = Psi_i (gamma_i - gamma_c - |Psi_i|^2)
- *                 + (1/s) sum_{j != i} J_ij Psi_j  + h_1i            Eq. (main)
+ *                 + (1/s) sum_{j != i} J_ij Psi_j  + h_1i
+ *                 + h_q conj(Psi_i)^(q-1) + D xi_i(t)                Eq. (main)
  *   dgamma_i/dt = eps_i (rho_th - |Psi_i|^2)                         Eq. (gamma)
  *
- * (GD form: Delta_ij = 1, K_ij = J_ij; noise D = 0) for real amplitudes
- * (Ising, Sec. 3, on the real subspace where the q = 2 penalty is a shift of
- * gamma_c) or complex amplitudes (XY, Sec. 2), and scores the discretised
- * states with the Hamiltonian of Eq. (h):
+ * (GD form: Delta_ij = 1, K_ij = J_ij) for real amplitudes (Ising, Sec. 3,
+ * on the real subspace where the q = 2 penalty is a shift of gamma_c),
+ * complex amplitudes without resonant term (XY, Sec. 2), or complex
+ * amplitudes with one resonant term h_q (Ising through h_2, and the q-state
+ * clock (planar Potts) model, Eq. (hs)), and scores the discretised states
+ * with the Hamiltonian of Eq. (h):
  *
  *   H = - sum_{i != j} J_ij cos(theta_i - theta_j) + sum_i g_i cos(theta_i).
  *
@@ -43,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GD_ABI_VERSION 1
+#define GD_ABI_VERSION 2
 
 /* Error codes (all negative). */
 typedef enum gd_error {
@@ -58,9 +61,16 @@ typedef enum gd_error {
     GD_E_UNSUPPORTED = -8    /* valid request the library does not implement */
 } gd_error;
 
-/* Spin model.  GD_ISING integrates real amplitudes (theta in {0, pi});
- * GD_XY integrates complex amplitudes (theta in [0, 2pi)). */
-typedef enum gd_model { GD_ISING = 0, GD_XY = 1 } gd_model;
+/* Spin model.
+ *  GD_ISING          real amplitudes; readout sign(x) (theta in {0, pi}).
+ *  GD_XY             complex amplitudes, no resonant term; theta = arg Psi.
+ *  GD_ISING_COMPLEX  complex amplitudes with the q = 2 term h_2 conj(Psi)
+ *                    (Sec. 3); readout sign(Re Psi).
+ *  GD_POTTS          complex amplitudes with the q-th term h_q conj(Psi)^(q-1)
+ *                    (Eq. (hs)); readout k = floor(q theta / 2pi + 1/2) mod q
+ *                    (theta = arg Psi in [0, 2pi), Psi = 0 -> theta = 0),
+ *                    energy of Eq. (h) at theta_i = 2 pi k_i / q. */
+typedef enum gd_model { GD_ISING = 0, GD_XY = 1, GD_ISING_COMPLEX = 2, GD_POTTS = 3 } gd_model;
 
 /* Time integrator: explicit Euler, or the classical 4th-order Runge-Kutta
  * scheme on the joint state (Psi, gamma) (Sec. 2 uses RK4 for XY). */
@@ -77,8 +87,10 @@ typedef enum gd_precision {
 
 /* Output format of gd_spins. */
 typedef enum gd_spin_fmt {
-    GD_SPINS_I8 = 0,        /* Ising: int8 +-1, [batch][n] */
-    GD_SPINS_ANGLE_F32 = 1  /* XY (or Ising): float theta in [0, 2pi), [batch][n] */
+    GD_SPINS_I8 = 0,         /* Ising models: int8 +-1, [batch][n] */
+    GD_SPINS_ANGLE_F32 = 1,  /* float theta in [0, 2pi) of the discretised state, [batch][n]
+                                (XY: arg Psi; Ising: 0 or pi; Potts: 2 pi k / q) */
+    GD_SPINS_STATE_I32 = 2   /* Potts: int32 k in [0, q), [batch][n] */
 } gd_spin_fmt;
 
 #define GD_F_DEVICE_PTRS 0x1u  /* array arguments are device pointers */
@@ -104,6 +116,26 @@ typedef struct gd_params {
     int32_t has_target;      /* nonzero: gd_run stops at the first check with min_r E_r <= target */
     double target_energy;    /* target of Eq. (h) energy for time-to-target */
     void *stream;            /* hipStream_t or NULL */
+    /* noise D xi_i(t) of Eq. (main) (dense solvers; default D = 0).  Each step
+     * first takes the deterministic Euler or RK4 step, then adds
+     * D sqrt(dt) (eta_re + i eta_im) (real models: D sqrt(dt) eta_re) with
+     * eta_re, eta_im independent N(0, 1) drawn by Box-Muller from
+     * z = SplitMix64(k_t ^ SplitMix64(r 2^32 + i)), k_t = SplitMix64(noise_seed
+     * ^ SplitMix64(t)), t = index of the step since gd_set_init / the step of
+     * gd_set_state: u1 = ((z >> 40) + 1) 2^-24, u2 = ((z >> 16) mod 2^24) 2^-24,
+     * eta = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).  With D = 0 the
+     * dynamics are deterministic. */
+    double noise_D;
+    uint64_t noise_seed;
+    int32_t q;               /* GD_POTTS: number of states, 2 <= q <= 8 */
+    int32_t reserved;        /* must be 0 */
+    double h_q;              /* resonant strength of GD_ISING_COMPLEX and GD_POTTS.  For q = 2,
+                                0 selects 1.1 max_i sum_{j != i} |J_ij| / s (the bound of
+                                Sec. 1 for the penalty to pin the phases, with a 10% margin).
+                                For q > 2 it must be given (> 0): the paper states no value,
+                                and the term outgrows the cubic saturation for q > 4 (for
+                                q = 4 when h_4 > 1), so large values make the dynamics
+                                blow up. */
 } gd_params;
 
 /* Counters of a solver (cumulative over gd_run calls since the last
@@ -128,7 +160,8 @@ typedef struct gd_run_stats {
 typedef struct gd_solver gd_solver;
 
 /* Defaults: Euler, FP32, dt 0.05, eps 0.1, rho_th 1, gamma_c 0, gamma0 0,
- * automatic coupling scale, init_amp 0.1, seed 0, no checks, NULL stream. */
+ * automatic coupling scale, init_amp 0.1, seed 0, no checks, NULL stream,
+ * no noise, q = 2, automatic h_q. */
 void gd_default_params(gd_params *p);
 
 /*
@@ -142,7 +175,8 @@ void gd_default_params(gd_params *p);
  *   model  gd_model.  p: parameters (copied), NULL = defaults.
  * Errors: GD_E_INVALID_ARG, GD_E_NOT_SYMMETRIC, GD_E_NONFINITE, GD_E_OOM,
  * GD_E_DEVICE, GD_E_UNSUPPORTED (reduced precision with J not exactly
- * representable in it).  On error *out is set to NULL.
+ * representable in it).  GD_POTTS needs 2 <= params.q <= 8, and h_q > 0
+ * when q > 2.  On error *out is set to NULL.
  */
 int gd_create(gd_solver **out, int32_t n, const float *J, const float *g,
               int32_t model, const gd_params *p);
@@ -153,9 +187,10 @@ void gd_destroy(gd_solver *s);
 /*
  * gd_set_init: set the initial state of `batch` trajectories and reset the
  * step counter and statistics.
- *   psi0   Ising [batch][n], XY [batch][n][2]; NULL = default initial state
- *          (Ising U(-a, a); XY a*exp(i*phi), phi ~ U[0, 2pi); a = init_amp,
- *          drawn from SplitMix64 keyed by seed, trajectory and spin).
+ *   psi0   GD_ISING [batch][n], complex models [batch][n][2]; NULL = default
+ *          initial state (GD_ISING U(-a, a); complex models a*exp(i*phi),
+ *          phi ~ U[0, 2pi); a = init_amp (0 gives Psi(0) = 0, the start of
+ *          Sec. 2), drawn from SplitMix64 keyed by seed, trajectory and spin).
  *   gamma0 [batch][n] initial gains, or NULL for params.gamma0.
  *   eps    [n] per-spin gain rates eps_i (the site-dependent rates suggested
  *          in Sec. 3), or NULL for params.eps.
@@ -176,9 +211,10 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps);
 
 /*
  * gd_energy: Eq. (h) energies of the discretised current state (Ising:
- * s_i = sign(x_i) with sign(+-0) = +1; XY: theta_i = arg Psi_i, Psi_i = 0 ->
- * theta_i = 0), evaluated on the device in FP64 from the FP32 state (exact
- * for integer-valued J and g).
+ * s_i = sign(x_i) with sign(+-0) = +1 (complex Ising: of Re Psi_i); XY:
+ * theta_i = arg Psi_i, Psi_i = 0 -> theta_i = 0; Potts: the readout of
+ * gd_model), evaluated on the device in FP64 from the FP32 state (exact for
+ * integer-valued J and g; Potts: exact for q in {2, 3, 4, 6}).
  *   E     [batch] doubles.  best: argmin_r E_r (ties -> lowest r), nullable.
  */
 int gd_energy(gd_solver *s, double *E, int32_t *best);
@@ -191,7 +227,8 @@ int gd_energy(gd_solver *s, double *E, int32_t *best);
 int gd_energy_device(gd_solver *s, double *E, int32_t *best);
 
 /* gd_spins: discretised current state into caller memory, format gd_spin_fmt
- * (GD_SPINS_I8 needs model GD_ISING). */
+ * (GD_SPINS_I8 needs GD_ISING or GD_ISING_COMPLEX; GD_SPINS_STATE_I32 needs
+ * GD_POTTS). */
 int gd_spins(gd_solver *s, void *out, int32_t fmt);
 
 /* gd_get_state / gd_set_state: amplitudes ([batch][n] or [batch][n][2]),
@@ -214,8 +251,8 @@ int gd_coupling_scale(gd_solver *s, double *scale);
  * [nnz]; host memory), plus an optional field g [n].  The same validation
  * as gd_create applies per instance; every instance gets its own coupling
  * scale s_k.  The batched solver integrates the Ising model (real
- * amplitudes) with explicit Euler steps in FP32; other combinations return
- * GD_E_UNSUPPORTED.  All instances share params and the trajectory count R.
+ * amplitudes) with explicit Euler steps in FP32 and no noise; other
+ * combinations return GD_E_UNSUPPORTED.  All instances share params and the trajectory count R.
  */
 typedef struct gd_instance {
     int32_t n;

@@ -13,14 +13,20 @@
  * parallelism; it does not change any result).
  *
  * What it computes (paper notation):
- *   Eq. (main), GD form (Delta_ij = 1, K_ij = J_ij, Sec. 1), noise D = 0:
+ *   Eq. (main), GD form (Delta_ij = 1, K_ij = J_ij, Sec. 1):
  *     dPsi_i/dt = Psi_i (gamma_i - gamma_c - |Psi_i|^2)
  *                 + sum_{j != i} J_ij Psi_j / s
- *                 + sum_{q=1}^{nq} h_qi conj(Psi_i)^(q-1)
+ *                 + sum_{q=1}^{nq} h_qi conj(Psi_i)^(q-1) + D xi_i(t)
  *   Eq. (gamma): dgamma_i/dt = eps_i (rho_th - |Psi_i|^2)
  *   s is a coupling scale (s = 1 is the equation as printed).
  *   Integrators: explicit Euler, and the classical 4th-order Runge-Kutta
  *   scheme (Sec. 2) applied to the joint state (Psi, gamma).
+ *   Noise (D > 0): white noise xi_i with independent real and imaginary
+ *   parts of unit intensity; after each deterministic step the increment
+ *   D sqrt(dt) (eta_re + i eta_im) is added (real mode: D sqrt(dt) eta_re),
+ *   which for the Euler scheme is the Euler-Maruyama method.  eta_re, eta_im
+ *   are standard normals made by the Box-Muller transform from a
+ *   counter-based SplitMix64 stream (see orc_gauss_pair).
  *   Real-amplitude mode integrates the same equations for real Psi.
  *   Readout and energies follow Eq. (h); the diagonal of J is excluded as in
  *   Eq. (main) and Eq. (hs).
@@ -137,6 +143,50 @@ static void step_complex(int n, const double *J, double s, int nq, const double 
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Noise numbers                                                         */
+/* ------------------------------------------------------------------ */
+
+/* SplitMix64 (Steele, Lea, Flood 2014): the output for generator state x
+ * (the state first advances by the odd constant 0x9E3779B97F4A7C15, then a
+ * xor-shift-multiply finaliser mixes it). */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+/*
+ * Two independent standard normals for step t, trajectory r, spin i:
+ *   key = SplitMix64(seed ^ SplitMix64(t)),
+ *   z   = SplitMix64(key ^ SplitMix64(r * 2^32 + i)),
+ *   u1  = (bits 40..63 of z, plus 1) / 2^24   in (0, 1],
+ *   u2  = (bits 16..39 of z) / 2^24           in [0, 1),
+ *   (g0, g1) = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2)   (Box-Muller).
+ */
+void orc_gauss_pair(uint64_t seed, int64_t t, int64_t r, int64_t i, double *g0, double *g1)
+{
+    const uint64_t key = orc_splitmix64(seed ^ orc_splitmix64((uint64_t)t));
+    const uint64_t z = orc_splitmix64(key ^ orc_splitmix64(((uint64_t)r << 32) | (uint64_t)i));
+    const double u1 = ((double)(z >> 40) + 1.0) / 16777216.0;
+    const double u2 = (double)((z >> 16) & 0xFFFFFFull) / 16777216.0;
+    const double rad = sqrt(-2.0 * log(u1));
+    *g0 = rad * cos(2.0 * M_PI * u2);
+    *g1 = rad * sin(2.0 * M_PI * u2);
+}
+
+/* The pairs of orc_gauss_pair for step t, trajectories r0..r0+R-1 and spins
+ * 0..n-1, written to out [R][n][2]. */
+void orc_gauss_block(uint64_t seed, int64_t t, int64_t r0, int R, int n, double *out)
+{
+    for (int r = 0; r < R; ++r)
+        for (int i = 0; i < n; ++i)
+            orc_gauss_pair(seed, t, r0 + r, i, &out[((size_t)r * n + i) * 2],
+                           &out[((size_t)r * n + i) * 2 + 1]);
+}
+
 static int finite_vec(const double *v, size_t m)
 {
     for (size_t k = 0; k < m; ++k)
@@ -147,12 +197,15 @@ static int finite_vec(const double *v, size_t m)
 /*
  * orc_run_real: integrate R independent real-amplitude trajectories for
  * `steps` steps.  psi, gamma: [R][n] in/out.  h1: [n] or NULL.  eps: [n].
+ * Noise: amplitude D (0: none), seed, index t0 of the first step and index
+ * r0 of the first trajectory (the noise numbers depend on the global step
+ * and trajectory indices, so any sub-range is an exact sub-problem).
  * Returns ORC_E_NONFINITE if any trajectory's state became non-finite.
  */
 int orc_run_real(int n, const double *J, double s, const double *h1,
                  const double *eps, double rho_th, double gamma_c, double dt,
                  int integrator, int R, double *psi, double *gamma,
-                 long steps, int nthreads)
+                 long steps, int nthreads, double D, uint64_t seed, int64_t t0, int64_t r0)
 {
     if (n <= 0 || R < 0 || steps < 0 || !(s > 0.0) || !J || !eps || !psi || !gamma) return ORC_E_ARG;
     int bad = 0;
@@ -162,8 +215,15 @@ int orc_run_real(int n, const double *J, double s, const double *h1,
         double *w = malloc(sizeof(double) * 12 * (size_t)n);
         if (!w) { bad |= 2; continue; }
         double *p = psi + (size_t)r * n, *g = gamma + (size_t)r * n;
-        for (long t = 0; t < steps; ++t)
+        for (long t = 0; t < steps; ++t) {
             step_real(n, J, s, h1, eps, rho_th, gamma_c, dt, integrator, p, g, w);
+            if (D != 0.0)
+                for (int i = 0; i < n; ++i) {
+                    double g0, g1;
+                    orc_gauss_pair(seed, t0 + t, r0 + r, i, &g0, &g1);
+                    p[i] += D * sqrt(dt) * g0;
+                }
+        }
         if (!finite_vec(p, n) || !finite_vec(g, n)) bad |= 1;
         free(w);
     }
@@ -178,7 +238,7 @@ int orc_run_real(int n, const double *J, double s, const double *h1,
 int orc_run_complex(int n, const double *J, double s, int nq, const double *h,
                     const double *eps, double rho_th, double gamma_c, double dt,
                     int integrator, int R, double *psi, double *gamma,
-                    long steps, int nthreads)
+                    long steps, int nthreads, double D, uint64_t seed, int64_t t0, int64_t r0)
 {
     if (n <= 0 || R < 0 || steps < 0 || !(s > 0.0) || !J || !eps || !psi || !gamma) return ORC_E_ARG;
     if (nq < 0 || (nq > 0 && !h)) return ORC_E_ARG;
@@ -191,8 +251,15 @@ int orc_run_complex(int n, const double *J, double s, int nq, const double *h,
         double *pr = psi + (size_t)r * n * 2, *g = gamma + (size_t)r * n;
         double complex *p = z + 5 * (size_t)n;
         for (int i = 0; i < n; ++i) p[i] = pr[2 * i] + I * pr[2 * i + 1];
-        for (long t = 0; t < steps; ++t)
+        for (long t = 0; t < steps; ++t) {
             step_complex(n, J, s, nq, h, eps, rho_th, gamma_c, dt, integrator, p, g, z, wg);
+            if (D != 0.0)
+                for (int i = 0; i < n; ++i) {
+                    double g0, g1;
+                    orc_gauss_pair(seed, t0 + t, r0 + r, i, &g0, &g1);
+                    p[i] += D * sqrt(dt) * (g0 + I * g1);
+                }
+        }
         for (int i = 0; i < n; ++i) { pr[2 * i] = creal(p[i]); pr[2 * i + 1] = cimag(p[i]); }
         if (!finite_vec(pr, 2 * (size_t)n) || !finite_vec(g, n)) bad |= 1;
         free(z);

@@ -8,9 +8,12 @@ same seeded inputs from ``paper_1807_00699_amd.inputs`` as data.
 Thin numpy front-end over ``gd_oracle.c`` (built into ``liboracle.so`` by
 ``oracle/build.py``).  Notation follows the paper:
 
-* ``run`` integrates Eq. (main) (GD form, Delta_ij = 1, K_ij = J_ij, D = 0)
-  together with Eq. (gamma), by explicit Euler or the 4th-order Runge-Kutta
-  scheme of Sec. 2, for R independent trajectories.
+* ``run`` integrates Eq. (main) (GD form, Delta_ij = 1, K_ij = J_ij) together
+  with Eq. (gamma), by explicit Euler or the 4th-order Runge-Kutta scheme of
+  Sec. 2, for R independent trajectories; with noise_D > 0 the white-noise
+  term D xi_i(t) enters as an additive increment D sqrt(dt) eta after each
+  deterministic step (Euler-Maruyama for the Euler scheme), with eta drawn
+  from a counter-based SplitMix64 + Box-Muller stream (``gauss_pair``).
 * ``coupling_scale`` is the reading used for the coupling normalisation: the
   coupling enters Eq. (main) as (1/s) sum_j J_ij Psi_j with
   s = sqrt(sum_{i!=j} J_ij^2 / N) (the RMS row norm).  The paper leaves all
@@ -35,6 +38,8 @@ import subprocess
 import sys
 
 import numpy as np
+
+M64 = (1 << 64) - 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -61,8 +66,15 @@ def _load():
         build()
         lib = C.CDLL(_LIB_PATH)
         d, i, l_, p = C.c_double, C.c_int, C.c_long, C.c_void_p
-        lib.orc_run_real.argtypes = [i, p, d, p, p, d, d, d, i, i, p, p, l_, i]
-        lib.orc_run_complex.argtypes = [i, p, d, i, p, p, d, d, d, i, i, p, p, l_, i]
+        u64, i64 = C.c_uint64, C.c_int64
+        lib.orc_run_real.argtypes = [i, p, d, p, p, d, d, d, i, i, p, p, l_, i, d, u64, i64, i64]
+        lib.orc_run_complex.argtypes = [i, p, d, i, p, p, d, d, d, i, i, p, p, l_, i, d, u64, i64, i64]
+        lib.orc_splitmix64.argtypes = [u64]
+        lib.orc_splitmix64.restype = u64
+        lib.orc_gauss_pair.argtypes = [u64, i64, i64, i64, p, p]
+        lib.orc_gauss_pair.restype = None
+        lib.orc_gauss_block.argtypes = [u64, i64, i64, i, i, p]
+        lib.orc_gauss_block.restype = None
         lib.orc_ising_spins.argtypes = [l_, p, p]
         lib.orc_xy_phases.argtypes = [l_, p, p]
         lib.orc_potts_states.argtypes = [l_, p, i, p]
@@ -118,9 +130,30 @@ def field_h1(g, rho_th: float, s: float):
 
 # ---------------------------------------------------------------- dynamics
 
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for state x (the oracle's C routine)."""
+    return int(_load().orc_splitmix64(int(x) & M64))
+
+
+def gauss_pair(seed: int, t: int, r: int, i: int):
+    """The two standard normals of the noise term for (step t, trajectory r,
+    spin i), as drawn by run() with noise_D > 0."""
+    g0, g1 = C.c_double(), C.c_double()
+    _load().orc_gauss_pair(int(seed) & M64, int(t), int(r), int(i), C.byref(g0), C.byref(g1))
+    return g0.value, g1.value
+
+
+def gauss_block(seed: int, t: int, r0: int, R: int, n: int) -> np.ndarray:
+    """Noise numbers of step t for trajectories r0..r0+R-1: [R][n][2]."""
+    out = np.empty((int(R), int(n), 2))
+    _load().orc_gauss_block(int(seed) & M64, int(t), int(r0), int(R), int(n), _ptr(out))
+    return out
+
+
 def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
         rho_th: float = 1.0, gamma_c: float = 0.0, s: float | None = None,
-        g=None, h=None, integrator: int = EULER, nthreads: int | None = None):
+        g=None, h=None, integrator: int = EULER, nthreads: int | None = None,
+        noise_D: float = 0.0, noise_seed: int = 0, t0: int = 0, r0: int = 0):
     """Integrate R trajectories of Eqs. (main, gamma) for `steps` steps.
 
     model 'ising': real amplitudes, psi [R][n].
@@ -129,6 +162,9 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
     s: coupling scale (None -> coupling_scale(J)).  g: external field of
     Eq. (h) [n] (mapped to h_1).  h: complex mode only, extra resonant
     coefficients [nq][n] for q = 1..nq (added to the g mapping for q = 1).
+    noise_D, noise_seed: the noise term D xi_i(t) (Euler-Maruyama increment
+    after each deterministic step); t0 / r0: global index of the first step /
+    first trajectory, which key the noise numbers.
     Returns (psi, gamma) as float64 arrays of the input shapes.
     """
     lib = _load()
@@ -150,7 +186,8 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
             raise ValueError("resonant terms need model='xy' (complex amplitudes)")
         rc = lib.orc_run_real(n, _ptr(J), float(s), _ptr(_f64(h1)), _ptr(epsv), float(rho_th),
                               float(gamma_c), float(dt), int(integrator), R, _ptr(x), _ptr(gam),
-                              int(steps), int(nthreads))
+                              int(steps), int(nthreads), float(noise_D), int(noise_seed) & M64,
+                              int(t0), int(r0))
         _check(rc, "orc_run_real")
         return x, gam
     if model == "xy":
@@ -171,7 +208,8 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
         nq = 0 if hq is None else hq.shape[0]
         rc = lib.orc_run_complex(n, _ptr(J), float(s), nq, _ptr(hq), _ptr(epsv), float(rho_th),
                                  float(gamma_c), float(dt), int(integrator), R, _ptr(p), _ptr(gam),
-                                 int(steps), int(nthreads))
+                                 int(steps), int(nthreads), float(noise_D), int(noise_seed) & M64,
+                                 int(t0), int(r0))
         _check(rc, "orc_run_complex")
         if was_complex:
             p = p[..., 0] + 1j * p[..., 1]
@@ -181,11 +219,13 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
 
 def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
             rho_th: float = 1.0, gamma_c: float = 0.0, s: float | None = None, g=None,
-            integrator: int = EULER):
-    """The same integration as `run` carried out in float32 with numpy
-    (no resonant terms beyond the field).  Used only to measure the FP32
-    noise floor of a trajectory: |run_f32 - run| / |run| shows how far
-    rounding at single precision alone moves it, independent of any GPU."""
+            integrator: int = EULER, h=None, noise_D: float = 0.0, noise_seed: int = 0,
+            t0: int = 0, r0: int = 0):
+    """The same integration as `run` carried out in float32 with numpy (the
+    noise numbers are drawn in float64 as in `run` and rounded).  Used only
+    to measure the FP32 rounding floor of a trajectory: |run_f32 - run| /
+    |run| shows how far rounding at single precision alone moves it,
+    independent of any GPU."""
     f32 = np.float32
     J = np.asarray(J, np.float32).copy()
     np.fill_diagonal(J, 0.0)
@@ -201,15 +241,32 @@ def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
     gam = np.zeros(z.shape, f32) if gamma is None else np.asarray(gamma, f32).reshape(z.shape).copy()
     dt = f32(dt)
 
+    hq = None if h is None else np.asarray(h, f32).reshape(-1, n)
+
     def F(y, gm):
         c = (y @ J.T) * inv_s
         rho = (y.real * y.real + y.imag * y.imag) if cx else y * y
-        return y * (gm - f32(gamma_c) - rho) + c + h1, epsv * (f32(rho_th) - rho)
+        f = y * (gm - f32(gamma_c) - rho) + c + h1
+        if hq is not None:
+            pw = np.ones_like(y)
+            for q in range(hq.shape[0]):
+                f = f + hq[q] * pw
+                pw = pw * np.conj(y)
+        return f, epsv * (f32(rho_th) - rho)
 
-    for _ in range(int(steps)):
+    R = z.shape[0]
+    amp = f32(noise_D * np.sqrt(float(dt)))
+
+    def noise(k):
+        e = gauss_block(noise_seed, t0 + k, r0, R, n)
+        return (e[..., 0] + 1j * e[..., 1]).astype(np.complex64) if cx else e[..., 0].astype(f32)
+
+    for k in range(int(steps)):
         k1 = F(z, gam)
         if integrator == EULER:
             z, gam = z + dt * k1[0], gam + dt * k1[1]
+            if noise_D:
+                z = z + amp * noise(k)
             continue
         h = dt * f32(0.5)
         k2 = F(z + h * k1[0], gam + h * k1[1])
@@ -218,6 +275,8 @@ def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
         c6 = dt / f32(6.0)
         z = z + c6 * (k1[0] + f32(2) * k2[0] + f32(2) * k3[0] + k4[0])
         gam = gam + c6 * (k1[1] + f32(2) * k2[1] + f32(2) * k3[1] + k4[1])
+        if noise_D:
+            z = z + amp * noise(k)
     if cx:
         z = np.stack([z.real, z.imag], -1).astype(f32)
     return z, gam

@@ -44,9 +44,69 @@ __device__ inline void store_shadow(void *dst, long long k, float v, int op) {
     else if (op == OP_F16) static_cast<__half *>(dst)[k] = __float2half(v);
 }
 
+constexpr double kTwoPi = 6.283185307179586476925286766559;   // nearest double to 2 pi
+
+// q-state clock readout in FP64: theta = arg Psi in [0, 2pi) (Psi = 0 ->
+// theta = 0), k = floor(q theta / 2pi + 1/2) mod q.
+__device__ inline int clock_state(double x, double y, int q) {
+    double th = (x == 0.0 && y == 0.0) ? 0.0 : atan2(y, x);
+    if (th < 0.0) th += kTwoPi;
+    const long long c = (long long)floor((double)q * th / kTwoPi + 0.5);
+    return (int)(((c % q) + q) % q);
+}
+
+// Planes of clock state k: d0 = cos(2 pi k / q); d1 = sin(2 pi k / q), held
+// as sin / (sqrt(3)/2) in {0, +-1} for q = 3 and 6 so that both planes are
+// exact (their product then carries the weight 3/4).
+__device__ inline void clock_planes(int k, int q, double &d0, double &d1) {
+    switch (q) {
+    case 2: d0 = k ? -1.0 : 1.0; d1 = 0.0; return;
+    case 3: d0 = k ? -0.5 : 1.0; d1 = k == 0 ? 0.0 : (k == 1 ? 1.0 : -1.0); return;
+    case 4: d0 = k == 0 ? 1.0 : (k == 2 ? -1.0 : 0.0); d1 = k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); return;
+    case 6: {
+        const double c6[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+        const double s6[6] = {0.0, 1.0, 1.0, 0.0, -1.0, -1.0};
+        d0 = c6[k];
+        d1 = s6[k];
+        return;
+    }
+    default: sincospi(2.0 * k / q, &d1, &d0); return;
+    }
+}
+
+// Discretised planes (d0, d1) of one amplitude in FP64 for readout `ro`;
+// `k` receives the clock state (RO_CLOCK) or 0/1 for the sign readouts.
+__device__ inline void readout_planes(double x, double y, int ro, int q, double &d0, double &d1,
+                                      int &k) {
+    d1 = 0.0;
+    k = 0;
+    switch (ro) {
+    case RO_SIGN:
+    case RO_SIGN_RE:
+        d0 = (x < 0.0) ? -1.0 : 1.0;   // sign(+-0) = +1
+        k = x < 0.0;
+        return;
+    case RO_PHASOR: {
+        if (x == 0.0 && y == 0.0) {
+            d0 = 1.0;
+            return;
+        }
+        const double m = sqrt(x * x + y * y);
+        d0 = x / m;
+        d1 = y / m;
+        return;
+    }
+    default:
+        k = clock_state(x, y, q);
+        clock_planes(k, q, d0, d1);
+        return;
+    }
+}
+
 // Readout onto the spin domains of Eq. (h).
 __global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ D, void *shadowD,
-                             int op, int8_t *__restrict__ spins8, float *__restrict__ angle,
+                             int op, int ro, int q, int8_t *__restrict__ spins8,
+                             float *__restrict__ angle, int32_t *__restrict__ states,
                              int *__restrict__ flags, int n, int R, int Np, int Rp, int P,
                              long long ps) {
     const long long total = (long long)Rp * Np;
@@ -55,33 +115,30 @@ __global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ 
         const int r = int(t / Np), i = int(t % Np);
         const bool in = (r < R) && (i < n);
         float d0 = 0.0f, d1 = 0.0f, th = 0.0f;
-        bool nan = false;
         if (in) {
             const float x = psi[t];
-            if (P == 1) {
-                nan = __builtin_isnan(x);
-                d0 = (x < 0.0f) ? -1.0f : 1.0f;        // sign(+-0) = +1
-                th = (x < 0.0f) ? 3.14159265358979323846f : 0.0f;
-            } else {
-                const float y = psi[ps + t];
-                nan = __builtin_isnan(x) || __builtin_isnan(y);
-                if (x == 0.0f && y == 0.0f) {
-                    d0 = 1.0f; d1 = 0.0f; th = 0.0f;
-                } else {
-                    // unit phasor in double so that |D| = 1 to FP32 rounding
-                    const double xd = x, yd = y;
-                    const double m = sqrt(xd * xd + yd * yd);
-                    d0 = float(xd / m);
-                    d1 = float(yd / m);
-                    float a = atan2f(y, x);
-                    if (a < 0.0f) a += 6.28318530717958647692f;
-                    if (a >= 6.28318530717958647692f) a = 0.0f;
-                    th = a;
+            const float y = P == 2 ? psi[ps + t] : 0.0f;
+            double e0, e1;
+            int k;
+            readout_planes(x, y, ro, q, e0, e1, k);
+            d0 = float(e0);
+            d1 = float(e1);
+            if (ro == RO_PHASOR) {
+                if (!(x == 0.0f && y == 0.0f)) {
+                    th = atan2f(y, x);
+                    if (th < 0.0f) th += 6.28318530717958647692f;
+                    if (th >= 6.28318530717958647692f) th = 0.0f;
                 }
+            } else if (ro == RO_CLOCK) {
+                th = float(kTwoPi * k / q);
+            } else {
+                th = k ? 3.14159265358979323846f : 0.0f;
             }
-            if (spins8) spins8[(long long)r * n + i] = (d0 < 0.0f && P == 1) ? int8_t(-1) : int8_t(1);
-            if (angle) angle[(long long)r * n + i] = th;
-            if (nan) flags[r] = 1;
+            const long long o = (long long)r * n + i;
+            if (spins8) spins8[o] = k ? int8_t(-1) : int8_t(1);
+            if (angle) angle[o] = th;
+            if (states) states[o] = k;
+            if (__builtin_isnan(x) || __builtin_isnan(y)) flags[r] = 1;
         }
         D[t] = d0;
         if (P == 2) D[ps + t] = d1;
@@ -123,36 +180,26 @@ __global__ void energy_reduce_k(const double *__restrict__ partial, int ntiles, 
 }
 
 // FP64 re-score of Eq. (h) for the discretised state, formed in FP64 from
-// the FP32 amplitudes: Ising d = sign(x) (sign(+-0) = +1), XY d = psi/|psi|
-// (psi = 0 -> 1).  Workgroup (row tile t of 64 spins, column tile of 64
-// trajectories): T = J d over K through LDS in FP64, then
-// partial[t][r] = sum_{i in tile} [ -Re(conj(d_i) T_i) + g_i Re(d_i) ].
+// the FP32 amplitudes by the readout of the model.  Workgroup (row tile t of
+// 64 spins, column tile of 64 trajectories): T = J d over K through LDS in
+// FP64, then partial[t][r] = sum_{i in tile} [ -(d0_i T0_i + w d1_i T1_i)
+// + g_i d0_i ] (w: weight of the second plane).
 constexpr int E64_T = 64;
 constexpr int E64_K = 16;
 
-__device__ inline void unit_phasor(const float *psi, long long ps, int P, long long idx, bool in,
-                                   double &dr, double &di) {
+__device__ inline void planes_at(const float *psi, long long ps, int P, int ro, int q, long long idx,
+                                 bool in, double &dr, double &di) {
     dr = 0.0;
     di = 0.0;
     if (!in) return;
-    const double x = psi[idx];
-    if (P == 1) {
-        dr = (x < 0.0) ? -1.0 : 1.0;
-        return;
-    }
-    const double y = psi[ps + idx];
-    if (x == 0.0 && y == 0.0) {
-        dr = 1.0;
-        return;
-    }
-    const double m = sqrt(x * x + y * y);
-    dr = x / m;
-    di = y / m;
+    int k;
+    readout_planes(psi[idx], P == 2 ? psi[ps + idx] : 0.0f, ro, q, dr, di, k);
 }
 
 __global__ void __launch_bounds__(256)
 energy_fp64_k(const float *__restrict__ J, const float *__restrict__ psi, const float *__restrict__ g,
-              double *__restrict__ partial, int Np, int Rp, int n, int R, int P, long long ps) {
+              double *__restrict__ partial, int Np, int Rp, int n, int R, int P, long long ps, int ro,
+              int q, double w) {
     __shared__ double sJ[E64_K][E64_T + 1];
     __shared__ double sDr[E64_K][E64_T + 1];
     __shared__ double sDi[E64_K][E64_T + 1];
@@ -164,12 +211,12 @@ energy_fp64_k(const float *__restrict__ J, const float *__restrict__ psi, const 
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.0;
     for (int k0 = 0; k0 < Np; k0 += E64_K) {
-        for (int q = threadIdx.x; q < E64_K * E64_T; q += 256) {
-            const int row = q / E64_K, kk = q % E64_K;
+        for (int e = threadIdx.x; e < E64_K * E64_T; e += 256) {
+            const int row = e / E64_K, kk = e % E64_K;
             sJ[kk][row] = (double)J[(long long)(i0 + row) * Np + k0 + kk];
             const int r = r0 + row, j = k0 + kk;
             double dr, di;
-            unit_phasor(psi, ps, P, (long long)r * Np + j, r < R && j < n, dr, di);
+            planes_at(psi, ps, P, ro, q, (long long)r * Np + j, r < R && j < n, dr, di);
             sDr[kk][row] = dr;
             sDi[kk][row] = di;
         }
@@ -195,8 +242,8 @@ energy_fp64_k(const float *__restrict__ J, const float *__restrict__ psi, const 
         for (int b = 0; b < 4; ++b) {
             const int r = r0 + tx * 4 + b;
             double dr, di;
-            unit_phasor(psi, ps, P, (long long)r * Np + i, r < R && i < n, dr, di);
-            colsum[b] += -(dr * ar[a][b] + di * ai[a][b]) + (double)g[i] * dr;
+            planes_at(psi, ps, P, ro, q, (long long)r * Np + i, r < R && i < n, dr, di);
+            colsum[b] += -(dr * ar[a][b] + w * (di * ai[a][b])) + (double)g[i] * dr;
         }
     }
     for (int b = 0; b < 4; ++b) red[ty][tx * 4 + b] = colsum[b];
@@ -248,12 +295,15 @@ hipError_t launch_unpack_planes(const float *planes, float *user, int n, int R, 
     return hipGetLastError();
 }
 
-hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int8_t *spins8,
-                             float *angle, int *flags, int n, int R, int Np, int Rp, int nplanes,
-                             long long plane_stride, hipStream_t st) {
-    discretise_k<<<grid_for((long long)Rp * Np), 256, 0, st>>>(psi, D, shadowD, op, spins8, angle,
-                                                              flags, n, R, Np, Rp, nplanes,
-                                                              plane_stride);
+float clock_im_weight(int q) { return (q == 3 || q == 6) ? 0.75f : 1.0f; }
+
+hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int readout, int q,
+                             int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
+                             int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st) {
+    if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
+    discretise_k<<<grid_for((long long)Rp * Np), 256, 0, st>>>(psi, D, shadowD, op, readout, q, spins8,
+                                                              angle, states, flags, n, R, Np, Rp,
+                                                              nplanes, plane_stride);
     return hipGetLastError();
 }
 
@@ -265,10 +315,13 @@ hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R
 
 hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *partial,
                               int Np, int Rp, int n, int R, int nplanes, long long plane_stride,
-                              hipStream_t st) {
+                              int readout, int q, hipStream_t st) {
     if (Np % E64_T || Rp % E64_T) return hipErrorInvalidValue;
+    if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
+    const double w = readout == RO_CLOCK ? (double)clock_im_weight(q) : 1.0;
     dim3 grid(Np / E64_T, Rp / E64_T);
-    energy_fp64_k<<<grid, 256, 0, st>>>(J, psi, g, partial, Np, Rp, n, R, nplanes, plane_stride);
+    energy_fp64_k<<<grid, 256, 0, st>>>(J, psi, g, partial, Np, Rp, n, R, nplanes, plane_stride,
+                                        readout, q, w);
     return hipGetLastError();
 }
 

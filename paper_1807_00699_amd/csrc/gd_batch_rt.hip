@@ -330,6 +330,7 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
     if (model != GD_ISING) return gd_fail(GD_E_UNSUPPORTED, "batched solver integrates the Ising model");
     if (p->integrator != GD_EULER) return gd_fail(GD_E_UNSUPPORTED, "batched solver uses Euler steps");
     if (p->precision != GD_PREC_FP32) return gd_fail(GD_E_UNSUPPORTED, "batched solver is FP32");
+    if (p->noise_D != 0.0) return gd_fail(GD_E_UNSUPPORTED, "batched solver has no noise term");
     BatchSolver *b = new (std::nothrow) BatchSolver();
     if (!b) return gd_fail(GD_E_OOM, "host allocation failed");
     b->K = count;
@@ -601,8 +602,8 @@ int batch_spins(BatchSolver *b, void *out, int fmt) {
     int *d_flag = nullptr;
     int rc = dmalloc(&d_flag, 1);
     if (rc != GD_OK) return rc;
-    hipError_t e = launch_discretise(b->d_x, b->d_D, nullptr, OP_F32, b->d_spins, nullptr, d_flag,
-                                     int(st), 1, int(st), 1, 1, st, b->stream);
+    hipError_t e = launch_discretise(b->d_x, b->d_D, nullptr, OP_F32, RO_SIGN, 0, b->d_spins, nullptr,
+                                     nullptr, d_flag, int(st), 1, int(st), 1, 1, st, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, b->d_spins, st, (b->prm.flags & GD_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice
                                                                                  : hipMemcpyDeviceToHost,

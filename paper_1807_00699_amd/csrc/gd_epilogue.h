@@ -3,11 +3,13 @@
 // Given the coupling sums C (already computed by a GEMM, before the 1/s
 // scale) for four consecutive spins i0..i0+3 of trajectory r, apply the rest
 // of Eq. (main) and Eq. (gamma):
-//   f   = Psi (gamma - gamma_c - |Psi|^2) + C / s + h_1
+//   f   = Psi (gamma - gamma_c - |Psi|^2) + C / s + h_1 + h_q conj(Psi)^(q-1)
 //   phi = eps_i (rho_th - |Psi|^2)
 // and an Euler update or one stage of the classical RK4 scheme on the joint
-// state (Psi, gamma).  Optionally writes a BF16/FP16 copy of the new
-// amplitudes: the operand of the next coupling GEMM.
+// state (Psi, gamma).  The final stage of a step adds the noise increment
+// D sqrt(dt) eta (Euler-Maruyama for the Euler scheme; the same additive
+// increment after the deterministic RK4 step).  Optionally writes a BF16/FP16
+// copy of the new amplitudes: the operand of the next coupling GEMM.
 #pragma once
 #include "gd_internal.h"
 
@@ -19,6 +21,30 @@ namespace gd {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline bool gd_finite(float a) { return __builtin_isfinite(a); }
+
+// SplitMix64 (Steele, Lea, Flood 2014): one output of the generator whose
+// state was z before the output step.
+__device__ inline unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Two independent standard normal numbers for (trajectory r, spin i) of the
+// step keyed by `key`, by the Box-Muller transform of two 24-bit uniforms:
+// u1 = (m1 + 1) 2^-24 in (0, 1], u2 = m2 2^-24 in [0, 1) (both exact in FP32).
+__device__ inline void noise_pair(unsigned long long key, int r, int i, float &g0, float &g1) {
+    const unsigned long long ctr = ((unsigned long long)(unsigned)r << 32) | (unsigned)i;
+    const unsigned long long z = mix64(key ^ mix64(ctr));
+    const float u1 = float((z >> 40) + 1ull) * 5.9604644775390625e-8f;       // 2^-24
+    const float two_u2 = float((z >> 16) & 0xFFFFFFull) * 1.1920928955078125e-7f;  // 2^-23
+    const float rad = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(two_u2, &sn, &cs);   // angle 2 pi u2
+    g0 = rad * cs;
+    g1 = rad * sn;
+}
 
 // store four consecutive floats as BF16 / FP16 (round to nearest even)
 template <int OPT>
@@ -59,6 +85,21 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
         fi[e] = CPLX ? xi[e] * lin + ci[e] * inv_s : 0.0f;
         fg[e] = ep[e] * (rho_th - rho);
     }
+    if (CPLX && a.q >= 2) {
+        // resonant term h_q conj(Psi)^(q-1): repeated products with conj(Psi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float pr = xr[e], pi = -xi[e];
+            for (int k = 2; k < a.q; ++k) {
+                const float tr = pr * xr[e] + pi * xi[e];
+                const float ti = pi * xr[e] - pr * xi[e];
+                pr = tr;
+                pi = ti;
+            }
+            fr[e] += a.hq * pr;
+            fi[e] += a.hq * pi;
+        }
+    }
     // rows beyond n and padded trajectories keep their (zero) state and gain
     bool rowv[4];
 #pragma unroll
@@ -71,7 +112,6 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
             nr[e] = rowv[e] ? xr[e] + dt * fr[e] : xr[e];
             ni[e] = rowv[e] ? xi[e] + dt * fi[e] : xi[e];
             ng[e] = rowv[e] ? gm[e] + dt * fg[e] : gm[e];
-            bad |= !(gd_finite(nr[e]) && gd_finite(ng[e]) && gd_finite(ni[e]));
         }
     } else {
         // RK4 stage on y = (psi, gamma); psi_in/gam_in is the stage input
@@ -94,7 +134,6 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
                 nr[e] = rowv[e] ? yr[e] + c6 * (ar[e] + fr[e]) : yr[e];
                 ni[e] = rowv[e] ? yi[e] + c6 * (ai[e] + fi[e]) : yi[e];
                 ng[e] = rowv[e] ? yg[e] + c6 * (ag[e] + fg[e]) : yg[e];
-                bad |= !(gd_finite(nr[e]) && gd_finite(ng[e]) && gd_finite(ni[e]));
             }
         } else {
             if constexpr (MODE != MODE_RK1) {
@@ -117,6 +156,20 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
             *reinterpret_cast<f32x4 *>(a.acc_gam + idx) = ag;
         }
     }
+    if constexpr (MODE == MODE_EULER || MODE == MODE_RK4) {
+        if (a.noise_amp != 0.0f) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (rowv[e]) {
+                    float g0, g1;
+                    noise_pair(a.noise_key, r, i0 + e, g0, g1);
+                    nr[e] += a.noise_amp * g0;
+                    if (CPLX) ni[e] += a.noise_amp * g1;
+                }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bad |= !(gd_finite(nr[e]) && gd_finite(ng[e]) && gd_finite(ni[e]));
+    }
     *reinterpret_cast<f32x4 *>(a.psi_out + idx) = nr;
     if (CPLX) *reinterpret_cast<f32x4 *>(a.psi_out + ps + idx) = ni;
     *reinterpret_cast<f32x4 *>(a.gam_out + idx) = ng;
@@ -128,7 +181,8 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
 }
 
 // Energy terms of Eq. (h) for four consecutive spins of trajectory r:
-// sum_e [ -sum_p D_p T_p + g_i D_0 ] in FP64 (T: raw GEMM sums of J D).
+// sum_e [ -(D_0 T_0 + w D_1 T_1) + g_i D_0 ] in FP64 (T: raw GEMM sums of
+// J D; w = im_weight).
 template <bool CPLX>
 __device__ inline double energy_terms4(const DenseStepArgs &a, int i0, int r, f32x4 tr, f32x4 ti) {
     const long long idx = (long long)r * a.Np + i0;
@@ -140,7 +194,7 @@ __device__ inline double energy_terms4(const DenseStepArgs &a, int i0, int r, f3
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         double t = -(double)d0[e] * (double)tr[e] + (double)gg[e] * (double)d0[e];
-        if (CPLX) t -= (double)d1[e] * (double)ti[e];
+        if (CPLX) t -= (double)a.im_weight * ((double)d1[e] * (double)ti[e]);
         s += t;
     }
     return s;

@@ -48,6 +48,16 @@ struct DenseStepArgs {
     long long plane_stride;
     int Np, Rp, n, R;
     float inv_s, dt, gamma_c, rho_th;
+    // resonant term h_q conj(Psi)^(q-1) of the complex models (q = 0: none)
+    int q;
+    float hq;
+    // noise of the step's final stage: noise_amp = D sqrt(dt) (0: none),
+    // noise_key = SplitMix64 key of this step
+    float noise_amp;
+    unsigned long long noise_key;
+    // energy mode: weight of the second plane's product (3/4 for the q = 3, 6
+    // clock states, whose second plane holds sin(theta) / (sqrt(3)/2))
+    float im_weight;
 };
 
 // Kernel variants of the dense path.  traj_tile = trajectories per workgroup.
@@ -112,12 +122,25 @@ hipError_t launch_pack_planes(const float *user, float *planes, int n, int R, in
                               int nplanes, hipStream_t st);
 hipError_t launch_unpack_planes(const float *planes, float *user, int n, int R, int Np, int Rp,
                                 int nplanes, hipStream_t st);
-// discretised spins: Ising D = sign(x) (+-0 -> +1); XY D = (cos, sin) of arg psi
-// (psi = 0 -> (1, 0)); zero outside n x R.  Optional outputs (null to skip):
-// spins8 [R][n] int8, angle [R][n] float in [0, 2pi).  flags[r] set on NaN.
-hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int8_t *spins8,
-                             float *angle, int *flags, int n, int R, int Np, int Rp, int nplanes,
-                             long long plane_stride, hipStream_t st);
+// Readout of the amplitudes onto the spin domain of Eq. (h).
+enum Readout {
+    RO_SIGN = 0,     // real Ising: d = sign(x), sign(+-0) = +1
+    RO_PHASOR = 1,   // XY: d = Psi / |Psi| (Psi = 0 -> 1)
+    RO_SIGN_RE = 2,  // complex Ising: d = sign(Re Psi)
+    RO_CLOCK = 3     // q-state clock: k = floor(q arg(Psi) / 2pi + 1/2) mod q,
+                     // d = (cos 2pi k/q, sin 2pi k/q), second plane scaled as
+                     // clock_im_weight describes
+};
+// 3/4 for q = 3 and 6 (the second plane then holds sin / (sqrt(3)/2) in
+// {0, +-1}, exact), 1 otherwise
+float clock_im_weight(int q);
+// Discretised state planes D (and its operand copy), zero outside n x R.
+// Optional outputs (null to skip): spins8 [R][n] int8, angle [R][n] float in
+// [0, 2pi) of the discretised state, states [R][n] int32 (RO_CLOCK).
+// flags[r] set on NaN.
+hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int readout, int q,
+                             int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
+                             int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st);
 // E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r)
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
                                 int *best, hipStream_t st);
@@ -125,7 +148,7 @@ hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R
 // partial[t][r] = sum_{i in tile t} [-Re(conj(d_i) (J d)_i) + g_i Re(d_i)]
 hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *partial,
                               int Np, int Rp, int n, int R, int nplanes, long long plane_stride,
-                              hipStream_t st);
+                              int readout, int q, hipStream_t st);
 // shadow copy of FP32 planes in BF16 / FP16
 hipError_t launch_make_shadow(const float *src, void *dst, long long count, int op, hipStream_t st);
 // any_flag: out[0] = number of r < R with flags[r] != 0

@@ -106,6 +106,9 @@ struct gd_solver {
     gd::BatchSolver *batch = nullptr;   // non-null: a batch of instances (gd_create_batch)
     bool track_target = false;          // gd_set_targets was called: record time-to-target
     int n = 0, Np = 0, model = 0, P = 1;
+    int ro = RO_SIGN;          // readout of the model
+    int q_res = 0;             // order of the resonant term (0: none)
+    double hq = 0.0;           // its strength h_q
     gd_params prm{};
     double s = 1.0;
     bool j_integer = false, g_integer = true;
@@ -141,7 +144,7 @@ struct gd_solver {
     int64_t ev_used = 0;       // events recorded by the current gd_run call
 
     long long plane() const { return (long long)Rp * Np; }
-    bool complex_mode() const { return model == GD_XY; }
+    bool complex_mode() const { return P == 2; }
     int integrator() const { return prm.integrator; }
 };
 
@@ -245,6 +248,11 @@ DenseStepArgs base_args(gd_solver *s) {
     a.dt = float(s->prm.dt);
     a.gamma_c = float(s->prm.gamma_c);
     a.rho_th = float(s->prm.rho_th);
+    a.q = s->q_res;
+    a.hq = float(s->hq);
+    a.noise_amp = 0.0f;
+    a.noise_key = 0;
+    a.im_weight = s->ro == RO_CLOCK ? clock_im_weight(s->prm.q) : 1.0f;
     return a;
 }
 
@@ -261,11 +269,16 @@ hipError_t refresh_shadow(gd_solver *s, int k) {
     return launch_make_shadow(s->psi[k], s->shadow[k], s->plane() * s->P, s->op, s->stream);
 }
 
-// Enqueue one integration step.  `dt_override` >= 0 replaces dt (used with
-// 0 by the tuner: the state is then left bit-for-bit unchanged).
-int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed) {
+// Enqueue integration step number t.  `dt_override` >= 0 replaces dt (used
+// with 0 by the tuner: the state is then left bit-for-bit unchanged, noise
+// included, since its amplitude is D sqrt(dt)).
+int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed, int64_t t) {
     DenseStepArgs a = base_args(s);
     if (dt_override >= 0.0f) a.dt = dt_override;
+    if (s->prm.noise_D != 0.0) {
+        a.noise_amp = float(s->prm.noise_D * std::sqrt(double(a.dt)));
+        a.noise_key = splitmix64(s->prm.noise_seed ^ splitmix64((uint64_t)t));
+    }
     const bool cx = s->complex_mode();
     auto launch = [&](int mode, const DenseStepArgs &x) -> int {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -359,11 +372,11 @@ int choose_config(gd_solver *s) {
         for (int id = 0; id < nc; ++id) {
             DenseConfig c = cfg_of(id);
             if (!dense_config_fits(c, s->Np, s->Rp)) continue;
-            int rc = enqueue_step(s, c, 0.0f, false);  // warm-up
+            int rc = enqueue_step(s, c, 0.0f, false, 0);  // warm-up
             if (rc != GD_OK) return rc;
             GD_HIP(hipEventRecord(e0, s->stream));
             for (int k = 0; k < reps; ++k)
-                if ((rc = enqueue_step(s, c, 0.0f, false)) != GD_OK) return rc;
+                if ((rc = enqueue_step(s, c, 0.0f, false, 0)) != GD_OK) return rc;
             GD_HIP(hipEventRecord(e1, s->stream));
             GD_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -399,6 +412,9 @@ int check_params(const gd_params *p) {
         return fail(GD_E_INVALID_ARG, "non-finite parameter");
     if (!(std::isfinite(p->j_scale) && p->j_scale >= 0)) return fail(GD_E_INVALID_ARG, "j_scale must be >= 0");
     if (p->check_interval < 0) return fail(GD_E_INVALID_ARG, "check_interval must be >= 0");
+    if (!(std::isfinite(p->noise_D) && p->noise_D >= 0)) return fail(GD_E_INVALID_ARG, "noise_D must be >= 0");
+    if (!(std::isfinite(p->h_q) && p->h_q >= 0)) return fail(GD_E_INVALID_ARG, "h_q must be >= 0");
+    if (p->reserved != 0) return fail(GD_E_INVALID_ARG, "gd_params.reserved must be 0");
     return GD_OK;
 }
 
@@ -527,6 +543,11 @@ void gd_default_params(gd_params *p) {
     p->has_target = 0;
     p->target_energy = 0.0;
     p->stream = nullptr;
+    p->noise_D = 0.0;
+    p->noise_seed = 0;
+    p->q = 2;
+    p->reserved = 0;
+    p->h_q = 0.0;
 }
 
 const char *gd_error_string(int code) {
@@ -552,18 +573,26 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
     *out = nullptr;
     if (n < 1 || n > 65536) return fail(GD_E_INVALID_ARG, "n out of range [1, 65536]");
     if (!J) return fail(GD_E_INVALID_ARG, "J is NULL");
-    if (model != GD_ISING && model != GD_XY) return fail(GD_E_INVALID_ARG, "unknown model");
+    if (model < GD_ISING || model > GD_POTTS) return fail(GD_E_INVALID_ARG, "unknown model");
     gd_params prm;
     if (p) prm = *p;
     else gd_default_params(&prm);
     int rc = check_params(&prm);
     if (rc != GD_OK) return rc;
+    if (model == GD_POTTS && (prm.q < 2 || prm.q > 8))
+        return fail(GD_E_INVALID_ARG, "GD_POTTS needs 2 <= q <= 8");
+    if (model == GD_POTTS && prm.q > 2 && !(prm.h_q > 0))
+        return fail(GD_E_INVALID_ARG, "GD_POTTS with q > 2 needs h_q > 0");
 
     gd_solver *s = new (std::nothrow) gd_solver();
     if (!s) return fail(GD_E_OOM, "host allocation failed");
     s->n = n;
     s->model = model;
-    s->P = model == GD_XY ? 2 : 1;
+    s->P = model == GD_ISING ? 1 : 2;
+    s->ro = model == GD_ISING ? RO_SIGN : model == GD_XY ? RO_PHASOR
+          : model == GD_ISING_COMPLEX ? RO_SIGN_RE : RO_CLOCK;
+    s->q_res = model == GD_ISING_COMPLEX ? 2 : model == GD_POTTS ? prm.q : 0;
+    if (model == GD_ISING_COMPLEX) prm.q = 2;
     s->prm = prm;
     s->Np = (int)round_up(n, kRowTile);
     auto bail = [&](int code) {
@@ -596,6 +625,17 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
     for (float v : hg) s->g_integer = s->g_integer && (v == std::nearbyint(v));
     s->s = prm.j_scale > 0 ? prm.j_scale : std::sqrt(ss / n);
     if (!(s->s > 0)) s->s = 1.0;
+    if (s->q_res) {
+        // default h_2: 10% above max_i sum_{j != i} |J_ij| / s
+        double rowmax = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double a = 0.0;
+            for (int j = 0; j < n; ++j)
+                if (j != i) a += std::fabs(double(hj[(size_t)i * n + j]));
+            rowmax = std::max(rowmax, a);
+        }
+        s->hq = prm.h_q > 0 ? prm.h_q : 1.1 * rowmax / s->s;
+    }
 
     if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(GD_E_DEVICE, "no HIP device"));
     const int Np = s->Np;
@@ -753,7 +793,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             // GD_F_PROFILE: HIP events around the coupling launches of every
             // kProfileEvery-th step only, so the events barely perturb the run
             const bool sample = timed && ((s->steps_done + k) % kProfileEvery == 0);
-            if ((rc = enqueue_step(s, s->cfg, -1.0f, sample)) != GD_OK) return rc;
+            if ((rc = enqueue_step(s, s->cfg, -1.0f, sample, s->steps_done + k)) != GD_OK) return rc;
         }
         done += chunk;
         s->steps_done += chunk;
@@ -761,8 +801,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         if (ci > 0 && s->steps_done % ci == 0) {
             // device check: discretise, energy GEMM, deterministic reduction
             const float *cur = s->psi[s->cur];
-            GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, nullptr, nullptr, s->flags, s->n,
-                                     s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
+            GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr,
+                                     nullptr, s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(),
+                                     s->stream));
             DenseStepArgs a = base_args(s);
             a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
             a.psi_in = s->D;
@@ -819,11 +860,11 @@ static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
     if (!s->have_state) return fail(GD_E_STATE, "no state: call gd_set_init or gd_run first");
     if (!E) return fail(GD_E_INVALID_ARG, "E is NULL");
     const float *cur = s->psi[s->cur];
-    GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, nullptr, nullptr, s->flags, s->n, s->R,
-                             s->Np, s->Rp, s->P, s->plane(), s->stream));
+    GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr, nullptr,
+                             s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
     if (fp64) {
         GD_HIP(launch_energy_fp64(s->dJ, cur, s->dG, s->partial, s->Np, s->Rp, s->n, s->R, s->P,
-                                  s->plane(), s->stream));
+                                  s->plane(), s->ro, s->prm.q, s->stream));
     } else {
         DenseStepArgs a = base_args(s);
         a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
@@ -857,16 +898,20 @@ int gd_spins(gd_solver *s, void *out, int32_t fmt) {
     }
     if (!s->have_state) return fail(GD_E_STATE, "no state");
     if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
-    if (fmt != GD_SPINS_I8 && fmt != GD_SPINS_ANGLE_F32) return fail(GD_E_INVALID_ARG, "unknown format");
-    if (fmt == GD_SPINS_I8 && s->model != GD_ISING)
-        return fail(GD_E_INVALID_ARG, "int8 spins need the Ising model");
+    if (fmt != GD_SPINS_I8 && fmt != GD_SPINS_ANGLE_F32 && fmt != GD_SPINS_STATE_I32)
+        return fail(GD_E_INVALID_ARG, "unknown format");
+    if (fmt == GD_SPINS_I8 && s->ro != RO_SIGN && s->ro != RO_SIGN_RE)
+        return fail(GD_E_INVALID_ARG, "int8 spins need an Ising model");
+    if (fmt == GD_SPINS_STATE_I32 && s->ro != RO_CLOCK)
+        return fail(GD_E_INVALID_ARG, "int32 states need the Potts model");
     const size_t cnt = (size_t)s->R * s->n;
     const size_t bytes = cnt * (fmt == GD_SPINS_I8 ? 1 : 4);
     void *tmp = nullptr;
     GD_HIP(hipMalloc(&tmp, bytes));
-    hipError_t e = launch_discretise(s->psi[s->cur], s->D, nullptr, OP_F32,
+    hipError_t e = launch_discretise(s->psi[s->cur], s->D, nullptr, OP_F32, s->ro, s->prm.q,
                                      fmt == GD_SPINS_I8 ? static_cast<int8_t *>(tmp) : nullptr,
                                      fmt == GD_SPINS_ANGLE_F32 ? static_cast<float *>(tmp) : nullptr,
+                                     fmt == GD_SPINS_STATE_I32 ? static_cast<int32_t *>(tmp) : nullptr,
                                      s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(), s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, tmp, bytes,

@@ -20,10 +20,10 @@ LIB_PATH = os.path.join(_PKG, "libgd.so")
 GD_OK = 0
 GD_E_INVALID_ARG, GD_E_NOT_SYMMETRIC, GD_E_NONFINITE, GD_E_OOM = -1, -2, -3, -4
 GD_E_DEVICE, GD_E_STATE, GD_E_DIVERGED, GD_E_UNSUPPORTED = -5, -6, -7, -8
-GD_ISING, GD_XY = 0, 1
+GD_ISING, GD_XY, GD_ISING_COMPLEX, GD_POTTS = 0, 1, 2, 3
 GD_EULER, GD_RK4 = 0, 1
 GD_PREC_FP32, GD_PREC_BF16, GD_PREC_FP16 = 0, 1, 2
-GD_SPINS_I8, GD_SPINS_ANGLE_F32 = 0, 1
+GD_SPINS_I8, GD_SPINS_ANGLE_F32, GD_SPINS_STATE_I32 = 0, 1, 2
 GD_F_DEVICE_PTRS, GD_F_ASYNC, GD_F_PROFILE = 0x1, 0x2, 0x4
 
 # exported symbols of include/gd.h
@@ -45,6 +45,8 @@ class gd_params(C.Structure):
         ("gamma_c", C.c_double), ("gamma0", C.c_double), ("j_scale", C.c_double),
         ("init_amp", C.c_double), ("seed", C.c_uint64), ("check_interval", C.c_int32),
         ("has_target", C.c_int32), ("target_energy", C.c_double), ("stream", C.c_void_p),
+        ("noise_D", C.c_double), ("noise_seed", C.c_uint64), ("q", C.c_int32),
+        ("reserved", C.c_int32), ("h_q", C.c_double),
     ]
 
 
@@ -198,7 +200,8 @@ def gd_energy(h, batch, device_path=False):
 
 
 def gd_spins(h, batch, n, fmt=GD_SPINS_I8):
-    out = np.empty((int(batch), int(n)), np.int8 if fmt == GD_SPINS_I8 else np.float32)
+    dtype = {GD_SPINS_I8: np.int8, GD_SPINS_STATE_I32: np.int32}.get(fmt, np.float32)
+    out = np.empty((int(batch), int(n)), dtype)
     _check(load().gd_spins(h, out.ctypes.data_as(C.c_void_p), int(fmt)), "gd_spins")
     return out
 
@@ -269,7 +272,7 @@ class Solver:
             self.batch = int(batch)
 
     def state(self):
-        return gd_get_state(self.h, self.batch, self.n, self.model == GD_XY)
+        return gd_get_state(self.h, self.batch, self.n, self.model != GD_ISING)
 
     def set_state(self, psi, gamma, step=0):
         psi = np.asarray(psi, np.float32)
@@ -281,7 +284,8 @@ class Solver:
 
     def spins(self, fmt=None):
         if fmt is None:
-            fmt = GD_SPINS_I8 if self.model == GD_ISING else GD_SPINS_ANGLE_F32
+            fmt = {GD_ISING: GD_SPINS_I8, GD_ISING_COMPLEX: GD_SPINS_I8,
+                   GD_POTTS: GD_SPINS_STATE_I32}.get(self.model, GD_SPINS_ANGLE_F32)
         return gd_spins(self.h, self.batch, self.n, fmt)
 
     def stats(self):

@@ -48,8 +48,9 @@ def test_struct_layouts_match_header(lib):
 #include <stdio.h>
 #include <stddef.h>
 #include "gd.h"
-int main(void){printf("%zu %zu %zu %zu\n", sizeof(gd_params), offsetof(gd_params, stream),
- sizeof(gd_run_stats), offsetof(gd_run_stats, kernel_config));return 0;}
+int main(void){printf("%zu %zu %zu %zu %zu %zu\n", sizeof(gd_params), offsetof(gd_params, stream),
+ sizeof(gd_run_stats), offsetof(gd_run_stats, kernel_config), offsetof(gd_params, noise_seed),
+ offsetof(gd_params, h_q));return 0;}
 '''
     exe = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"gd_layout_{os.getpid()}")
     subprocess.run(["gcc", "-x", "c", "-I", os.path.join(ROOT, "include"), "-o", exe, "-"],
@@ -57,7 +58,8 @@ int main(void){printf("%zu %zu %zu %zu\n", sizeof(gd_params), offsetof(gd_params
     vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     os.remove(exe)
     assert vals == [C.sizeof(gd.gd_params), gd.gd_params.stream.offset,
-                    C.sizeof(gd.gd_run_stats), gd.gd_run_stats.kernel_config.offset]
+                    C.sizeof(gd.gd_run_stats), gd.gd_run_stats.kernel_config.offset,
+                    gd.gd_params.noise_seed.offset, gd.gd_params.h_q.offset]
 
 
 def test_defaults_and_error_strings(lib):
@@ -68,11 +70,11 @@ def test_defaults_and_error_strings(lib):
     assert lib.gd_error_string(12345) == b"unknown error"
 
 
-def _create(J, **kw):
+def _create(J, model=0, **kw):
     p = gd.default_params(**kw)
     h = C.c_void_p(123)
     Jc = np.ascontiguousarray(J, np.float32)
-    rc = gd.load().gd_create(C.byref(h), Jc.shape[0], Jc.ctypes.data_as(C.c_void_p), None, 0,
+    rc = gd.load().gd_create(C.byref(h), Jc.shape[0], Jc.ctypes.data_as(C.c_void_p), None, model,
                              C.byref(p))
     return rc, h
 
@@ -89,6 +91,12 @@ def test_host_validation_errors(lib):
     assert _create(np.zeros((4, 4)), dt=0.0)[0] == gd.GD_E_INVALID_ARG
     assert _create(np.zeros((4, 4)), integrator=7)[0] == gd.GD_E_INVALID_ARG
     assert _create(np.zeros((4, 4)), precision=9)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), noise_D=-1.0)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), h_q=float("nan"))[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), reserved=1)[0] == gd.GD_E_INVALID_ARG
+    for q in (0, 1, 9):
+        assert _create(np.zeros((4, 4)), model=gd.GD_POTTS, q=q, h_q=0.5)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), model=gd.GD_POTTS, q=3)[0] == gd.GD_E_INVALID_ARG
     bad = gd.default_params()
     bad.struct_size = 8
     h = C.c_void_p()

@@ -1,0 +1,280 @@
+"""GPU parity of the noise term (Sec. 2 regime: Psi(0) = 0, noise seeds, gain
+rising from below) and of the resonant complex models (Ising through h_2,
+q-state clock model through h_q, Eq. (hs)) against the FP64 oracle.
+
+Amplitude bar as for the plain dense path: per trajectory, max-norm relative
+error <= max(1e-4, 4 x the oracle's own FP32-vs-FP64 distance), with at least
+90% of the trajectories within 1e-4 itself, at steps {1, 10, 50, 100, 200}.
+The noise numbers are drawn in FP32 on the GPU (logf, sqrtf, sincospif of
+the same 24-bit uniforms) and in FP64 by the oracle: they agree to a few
+FP32 ulps, checked directly on the first increment.
+Integer results (readouts, integer-J energies) are compared exactly where
+both sides decide from amplitudes that are not within rounding of a
+decision boundary.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1807_00699_amd import gd
+from paper_1807_00699_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SNAP = (1, 10, 50, 100, 200)
+TOL = 1e-4
+ORACLE_MODEL = {gd.GD_ISING: "ising", gd.GD_XY: "xy", gd.GD_ISING_COMPLEX: "xy", gd.GD_POTTS: "xy"}
+
+
+def _rel(a, b):
+    R = a.shape[0]
+    a = a.reshape(R, -1).astype(np.float64)
+    b = b.reshape(R, -1).astype(np.float64)
+    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-30)
+
+
+def _hq_rows(model, q, hq, n):
+    """h of the oracle ([nq][n], h_1 row zero) for a resonant model."""
+    if model == gd.GD_ISING_COMPLEX:
+        q = 2
+    elif model != gd.GD_POTTS:
+        return None
+    h = np.zeros((q, n))
+    h[q - 1] = hq
+    return h
+
+
+def default_hq(J, s):
+    J = np.asarray(J, np.float64).copy()
+    np.fill_diagonal(J, 0.0)
+    return 1.1 * np.abs(J).sum(1).max() / s
+
+
+def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, **kw):
+    n = J.shape[0]
+    om = ORACLE_MODEL[model]
+    okw = {k: v for k, v in kw.items() if k in ("rho_th", "gamma_c", "noise_D", "noise_seed")}
+    if "eps" in kw:
+        okw["eps"] = kw["eps"]
+    S = gd.Solver(J, None, model=model, integrator=integrator, dt=dt, **kw)
+    try:
+        R = psi0.shape[0]
+        S.set_init(R, psi0)
+        q = kw.get("q", 2)
+        h = _hq_rows(model, q, kw.get("h_q") or default_hq(J, S.scale), n)
+        op = psi0.astype(np.float64)
+        og = np.zeros((R, n))
+        fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
+        prev = 0
+        worst = []
+        for st in steps_list:
+            S.run(st - prev)
+            op, og = O.run(J, op, og, model=om, steps=st - prev, dt=dt, integrator=integrator,
+                           s=S.scale, h=h, t0=prev, **okw)
+            fp, fg = O.run_f32(J, fp, fg, model=om, steps=st - prev, dt=dt, integrator=integrator,
+                               s=S.scale, h=h, t0=prev, **okw)
+            prev = st
+            p, gm, step = S.state()
+            assert step == st
+            ep, eg = _rel(p, op), _rel(gm, og)
+            bound = np.maximum(TOL, 4 * np.maximum(_rel(fp, op), _rel(fg, og)))
+            worst.append((st, float(ep.max()), float(eg.max())))
+            assert np.all(ep <= bound) and np.all(eg <= bound), (st, ep.max(), eg.max(), bound.max())
+            assert np.mean((ep <= TOL) & (eg <= TOL)) >= 0.9, st
+        print("worst per snapshot (step, psi, gamma):", worst)
+    except BaseException:
+        S.close()
+        raise
+    return S, op, worst
+
+
+# ------------------------------------------------------------------ noise (NEXT-1)
+
+@pytest.mark.parametrize("model", [gd.GD_ISING, gd.GD_XY])
+def test_noise_increment_matches_oracle_numbers(model):
+    """J = 0, Psi = 0, eps = 0: one step leaves exactly D sqrt(dt) eta; with
+    dt = 0.25 and D = 2, eta itself.  Checked at step 0 and, through
+    gd_set_state, at step 12345 (the step index keys the numbers)."""
+    n, R = 300, 70
+    J = np.zeros((n, n), np.float32)
+    cx = model != gd.GD_ISING
+    shape = (R, n, 2) if cx else (R, n)
+    for t0 in (0, 12345):
+        with gd.Solver(J, model=model, dt=0.25, eps=0.0, noise_D=2.0, noise_seed=77) as S:
+            S.set_state(np.zeros(shape, np.float32), np.zeros((R, n), np.float32), step=t0)
+            S.run(1)
+            p, gm, _ = S.state()
+        want = O.gauss_block(77, t0, 0, R, n)
+        if not cx:
+            want = want[..., 0]
+        assert np.all(gm == 0.0)
+        err = np.abs(p - want) / np.maximum(np.abs(want), 1.0)
+        assert err.max() < 2e-6, err.max()
+        assert abs(p.std() - 1.0) < 0.01
+
+
+def _below(J, s, margin):
+    return float(np.linalg.eigvalsh(np.asarray(J, np.float64) / s).max() + margin)
+
+
+def test_noise_euler_ising_paper_regime_parity():
+    """Ising N = 64 dense +-1, R = 100, Euler dt = 0.05, Psi(0) = 0, D = 0.01,
+    gamma_c above the top eigenvalue of J/s (gain from below)."""
+    n, R = 64, 100
+    J = I.dense_pm1(n, 1)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    parity_run(J, np.zeros((R, n), np.float32), gd.GD_ISING, gd.GD_EULER, 0.05,
+               gamma_c=_below(J, s, 0.2), noise_D=0.01, noise_seed=5)
+
+
+def test_noise_rk4_xy_paper_regime_parity():
+    """XY N = 130 with N(0, 1/N) couplings, R = 64, RK4 dt = 0.02, Psi(0) = 0,
+    D = 0.01, gain from below; plus random-start amplitudes with noise."""
+    n, R = 130, 64
+    J = I.dense_gaussian(n, 2)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    parity_run(J, np.zeros((R, n, 2), np.float32), gd.GD_XY, gd.GD_RK4, 0.02,
+               gamma_c=_below(J, s, 0.1), noise_D=0.01, noise_seed=6)
+    parity_run(J, I.psi0_complex(n, R, 7), gd.GD_XY, gd.GD_RK4, 0.02, noise_D=0.003,
+               noise_seed=8)
+
+
+def test_noise_bf16_path_runs_and_matches_fp32_statistics():
+    """The reduced-precision path shares the epilogue: same noise numbers.
+    One step from Psi = 0 with J = 0 equals the FP32 path exactly."""
+    n, R = 256, 128
+    J = np.zeros((n, n), np.float32)
+    out = []
+    for prec in (gd.GD_PREC_FP32, gd.GD_PREC_BF16):
+        with gd.Solver(J, model=gd.GD_ISING, dt=0.25, eps=0.0, noise_D=2.0, noise_seed=9,
+                       precision=prec) as S:
+            S.set_init(R, np.zeros((R, n), np.float32))
+            S.run(1)
+            out.append(S.state()[0])
+    assert np.array_equal(out[0], out[1])
+
+
+def test_paper_regime_reaches_ground_state_n20():
+    """Leading 20 x 20 block of the N = 64 instance: all 64 noise seeds from
+    Psi(0) = 0 with gain from below end in the brute-force ground state."""
+    J = I.dense_pm1(64, 1)[:20, :20].copy()
+    e_b, _ = O.brute_ising(J.astype(np.float64))
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / 20)
+    with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1, gamma_c=_below(J, s, 0.5),
+                   noise_D=0.01, noise_seed=1, init_amp=0.0) as S:
+        S.run(3000, batch=64)
+        E, _ = S.energy()
+    assert np.all(E == e_b), (E.min(), e_b)
+
+
+# ------------------------------------------------------------------ resonant models (NEXT-2)
+
+def test_complex_ising_parity_readout_and_exact_energies():
+    n, R = 60, 48
+    J = I.dense_pm1(n, 11)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    h2 = default_hq(J, s)
+    S, op, _ = parity_run(J, I.psi0_complex(n, R, 11), gd.GD_ISING_COMPLEX, gd.GD_RK4, 0.02,
+                          gamma_c=h2)
+    with S:
+        S.run(1800)      # to step 2000
+        p, _, _ = S.state()
+        sp = S.spins()
+        E, best = S.energy()
+        Ed, bd = S.energy(device_path=True)
+    want = np.where(p[..., 0] < 0, -1, 1).astype(np.int8)
+    assert np.array_equal(sp, want)
+    Eo = O.energy_ising(J.astype(np.float64), want).astype(np.float64)
+    assert np.array_equal(E, Eo) and np.array_equal(Ed, Eo)
+    assert best == bd == int(np.argmin(Eo))
+    # the phases have been pinned to 0 or pi by the h_2 penalty
+    assert np.abs(p[..., 1]).max() < 1e-3 * np.abs(p[..., 0]).min()
+
+
+@pytest.mark.parametrize("q,hq", [(3, 1.0), (4, 0.5), (5, 0.1)])
+def test_potts_parity(q, hq):
+    """q-state clock model, U[-10, 10] couplings, N = 70, R = 40, RK4 dt = 0.02;
+    h_q below the strength where the resonant term outgrows the saturation."""
+    n, R = 70, 40
+    J = I.dense_uniform(n, 20 + q)
+    parity_run(J, I.psi0_complex(n, R, q), gd.GD_POTTS, gd.GD_RK4, 0.02, q=q, h_q=hq)
+
+
+def _clock_state_psi(k, q, amp=0.9, jitter=None):
+    th = 2 * np.pi * k / q
+    if jitter is not None:
+        th = th + jitter
+    return np.stack([amp * np.cos(th), amp * np.sin(th)], -1).astype(np.float32)
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 6, 5, 8])
+def test_potts_readout_and_energies_on_given_states(q):
+    """States set through gd_set_state: the readout returns k (angles within
+    +-0.4 of a sector width of the clock direction), and the energies equal
+    the oracle's Eq. (h) clock energies: exactly for integer J with
+    q in {2, 3, 4, 6} (both the FP64 re-score and the FP32 device path),
+    to 1e-12 (FP64) / 1e-5 (device) relative otherwise."""
+    n, R = 150, 70
+    rng = I.rng(q, 99)
+    J = I.sparse_pm1(n, q)
+    g = rng.integers(-2, 3, n).astype(np.float32)
+    k = rng.integers(0, q, (R, n))
+    jit = rng.uniform(-0.4, 0.4, (R, n)) * (2 * np.pi / q)
+    psi = _clock_state_psi(k, q, 0.9, jit)
+    psi[0, :5] = 0.0                     # Psi = 0 reads as theta = 0, k = 0
+    k[0, :5] = 0
+    with gd.Solver(J, g, model=gd.GD_POTTS, q=q, h_q=0.5) as S:
+        S.set_state(psi, np.zeros((R, n), np.float32), step=0)
+        st = S.spins()
+        E, best = S.energy()
+        Ed, bd = S.energy(device_path=True)
+        ang = S.spins(gd.GD_SPINS_ANGLE_F32)
+    assert np.array_equal(st, k)
+    assert np.array_equal(O.potts_states(psi.astype(np.float64), q), k)
+    assert np.allclose(ang, (2 * np.pi * k / q).astype(np.float32))
+    Eo = O.energy_potts(J.astype(np.float64), k, q, g.astype(np.float64))
+    if q in (2, 3, 4, 6):
+        assert np.array_equal(E, Eo) and np.array_equal(Ed, Eo)
+    else:
+        scale = np.abs(J).sum() + np.abs(g).sum()
+        assert np.abs(E - Eo).max() <= 1e-12 * scale
+        assert np.abs(Ed - Eo).max() <= 1e-5 * scale
+    assert best == int(np.argmin(Eo))
+
+
+def test_potts_and_complex_ising_reach_brute_force_ground_states():
+    n = 12
+    J = I.dense_pm1(n, 5)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    with gd.Solver(J, model=gd.GD_ISING_COMPLEX, integrator=gd.GD_RK4, dt=0.02,
+                   gamma_c=default_hq(J, s)) as S:
+        S.set_init(32, I.psi0_complex(n, 32, 4))
+        S.run(4000)
+        E, _ = S.energy()
+    assert E.min() == O.brute_ising(J.astype(np.float64))[0]
+    n, q = 9, 3
+    J = I.dense_uniform(n, 7)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    with gd.Solver(J, model=gd.GD_POTTS, q=q, h_q=default_hq(J, s), integrator=gd.GD_RK4,
+                   dt=0.02) as S:
+        S.set_init(32, I.psi0_complex(n, 32, 8))
+        S.run(6000)
+        E, _ = S.energy()
+    assert np.isclose(E.min(), O.brute_potts(J.astype(np.float64), q)[0], rtol=1e-9)
+
+
+def test_resonant_model_argument_checks():
+    J = I.dense_pm1(16, 1)
+    for bad_q in (1, 9):
+        with pytest.raises(gd.GDError):
+            gd.Solver(J, model=gd.GD_POTTS, q=bad_q)
+    with pytest.raises(gd.GDError):
+        gd.Solver(J, model=gd.GD_POTTS, q=3)          # q > 2 needs an explicit h_q
+    with gd.Solver(J, model=gd.GD_POTTS, q=3, h_q=0.5) as S:
+        S.run(1, batch=4)
+        with pytest.raises(gd.GDError):
+            S.spins(gd.GD_SPINS_I8)
+    with gd.Solver(J, model=gd.GD_XY) as S:
+        S.run(1, batch=4)
+        with pytest.raises(gd.GDError):
+            S.spins(gd.GD_SPINS_STATE_I32)
