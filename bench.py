@@ -80,6 +80,10 @@ def parse():
                     help="time-to-target comparisons: FP32 vs BF16 (N=4096) and random vs learned start")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (reference for HBM counters)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="steps and time to a stationary state vs N (XY, U[-10,10], paper regime)")
+    ap.add_argument("--maxcut800", action="store_true",
+                    help="N=800 G(n,0.06) max-cut stand-ins: cut quality and time, 100 runs each")
     return ap.parse_args()
 
 
@@ -267,6 +271,173 @@ def compare_ttt(args):
     print(json.dumps(out), flush=True)
 
 
+def _lambda_max(J, s):
+    """largest algebraic eigenvalue of J/s (host, for gamma_c above it)"""
+    from scipy.sparse.linalg import eigsh
+    return float(eigsh(np.asarray(J, np.float64) / s, k=1, which="LA", tol=1e-8)[0][0])
+
+
+def _stationary_steps(S, R, max_steps, check, rho_th=1.0, tol=1e-3):
+    """Integrate in chunks of `check` steps; a trajectory is stationary at the
+    first check where max_i |rho_i - rho_th| < tol rho_th and no phase moved
+    by more than tol (radians) since the previous check.  Returns the step
+    count per trajectory (-1 if not reached)."""
+    first = np.full(R, -1, np.int64)
+    prev = None
+    done = 0
+    while done < max_steps and np.any(first < 0):
+        S.run(check)
+        done += check
+        p, _, _ = S.state()
+        z = p[..., 0].astype(np.float64) + 1j * p[..., 1]
+        rho = np.abs(z) ** 2
+        th = np.angle(z)
+        if prev is not None:
+            dth = np.abs(np.angle(np.exp(1j * (th - prev))))
+            ok = (np.abs(rho - rho_th).max(1) < tol * rho_th) & (dth.max(1) < tol)
+            first[(first < 0) & ok] = done
+        prev = th
+    return first
+
+
+def scaling(args):
+    """Time per instance to a stationary state vs N on one GPU (the paper
+    times 20 runs per size of its GD algorithm on XY problems up to N = 3000
+    and fits a power law).  Per N: dense U[-10,10] couplings, XY, RK4
+    dt = 0.02, eps = 0.5, Psi(0) = 0 with noise D = 1e-6 (it only seeds the
+    symmetry breaking) and gamma_c = lambda_max(J/s) + 0.1 (gain rising from
+    below); R = 128 runs in one batch (the trajectory
+    tile is 128 wide, so 20 runs would cost the same).  Pass 1 finds each
+    run's steps to stationarity (host checks every 100 steps); pass 2 times
+    200 steps without checks; time per run = steps x time per step of the
+    batch.  The FP64 oracle's time per RK4 step of one run (one core) is
+    measured beside it."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    torch.cuda.init()
+    sizes = [250, 500, 1000, 1500, 2000, 3000, 4000]
+    R, check, budget = 128, 100, 80000
+    rows = []
+    for n in sizes:
+        J = I.dense_uniform(n, 7000 + n)
+        s = float(np.sqrt((J.astype(np.float64) ** 2).sum() / n))
+        gc = _lambda_max(J, s) + 0.1
+        kw = dict(integrator=gd.GD_RK4, dt=0.02, eps=0.5, gamma_c=gc, noise_D=1e-6,
+                  noise_seed=n, init_amp=0.0)
+        with gd.Solver(J, model=gd.GD_XY, **kw) as S:
+            S.set_init(R)
+            first = _stationary_steps(S, R, budget, check)
+            S.set_init(R)
+            S.run(20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.run(200)
+            ms = (time.perf_counter() - t0) / 200 * 1e3
+            E, b = S.energy()
+        reached = first >= 0
+        mean_steps = float(first[reached].mean()) if reached.any() else None
+        # median over all runs, unreached ones counted as beyond the budget
+        med = float(np.median(np.where(reached, first, budget + 1)))
+        median_steps = med if med <= budget else None
+        psi = np.zeros((1, n, 2))
+        t0 = time.perf_counter()
+        O.run(J, psi + 0.1, model="xy", steps=2, dt=0.02, eps=0.5, integrator=O.RK4, nthreads=1)
+        oracle_ms = (time.perf_counter() - t0) / 2 * 1e3
+        rows.append({"n": n, "runs": R, "reached": int(reached.sum()), "mean_steps": mean_steps,
+                     "median_steps": median_steps,
+                     "seconds_per_run_median": None if median_steps is None else median_steps * ms / 1e3,
+                     "max_steps": int(first[reached].max()) if reached.any() else None,
+                     "ms_per_step_batch": ms,
+                     "seconds_per_run_mean": None if mean_steps is None else mean_steps * ms / 1e3,
+                     "seconds_all_runs": None if not reached.all() else float(first.max()) * ms / 1e3,
+                     "oracle_ms_per_step_one_run": oracle_ms})
+        print(json.dumps({"progress": rows[-1]}), file=sys.stderr, flush=True)
+    ok = [r for r in rows if r["median_steps"]]
+    ln = np.log([r["n"] for r in ok])
+
+    def slope(key):
+        if len(ok) < 2:
+            return None
+        return float(np.polyfit(ln, np.log([r[key] for r in ok]), 1)[0])
+
+    print(json.dumps({"scaling": "time to a stationary state vs N (XY, U[-10,10], RK4, eps 0.5, "
+                                 "paper regime)",
+                      "rows": rows,
+                      "fit_exponent": {"seconds_per_run_median": slope("seconds_per_run_median"),
+                                       "median_steps": slope("median_steps"),
+                                       "ms_per_step_batch": slope("ms_per_step_batch"),
+                                       "oracle_ms_per_step_one_run": slope("oracle_ms_per_step_one_run")},
+                      "criterion": "max_i |rho_i - 1| < 1e-3 and max_i |dtheta_i| < 1e-3 rad "
+                                   "between checks 100 steps apart",
+                      "budget_steps": budget}), flush=True)
+
+
+def maxcut800(args):
+    """Max-cut stand-ins shaped like the paper's N = 800 benchmarks (Sec. 3):
+    five G(800, 0.06) graphs with unit weights and five with +-1 weights, 100
+    runs each (one batch), Ising Euler dt = 0.05, budget 5000 steps, in two
+    regimes: random start (U(-0.1, 0.1), gamma_c = 0) and the paper's
+    Psi(0) = 0 with noise and gain from below.  Best-known cut per instance:
+    best over both regimes and a longer run (1000 runs, 20000 steps).
+    Reports mean and best cut, the mean's deviation from the best-known cut,
+    and the wall time of the 100-run batch."""
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    torch.cuda.init()
+    n, p, R, steps = 800, 0.06, 100, 5000
+    out = []
+    for k in range(10):
+        signed = k >= 5
+        e, w = I.gnp_maxcut(n, p, 800 + k, signed=signed)
+        J = I.edges_to_dense(n, e, -w)
+        W = float(w.astype(np.float64).sum())
+        s = float(np.sqrt((J.astype(np.float64) ** 2).sum() / n))
+        gc = _lambda_max(J, s) + 0.5
+        regimes = {"random_start": dict(init_amp=0.1, seed=k),
+                   "paper_regime": dict(init_amp=0.0, gamma_c=gc, noise_D=0.01, noise_seed=k)}
+        row = {"instance": k, "weights": "+-1" if signed else "1", "edges": int(e.shape[0])}
+        best_cut = -np.inf
+        for name, kw in regimes.items():
+            with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1, **kw) as S:
+                S.run(10, batch=R)
+                S.set_init(R)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.run(steps)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                E, b = S.energy()
+            cuts = W / 2 - E / 4
+            best_cut = max(best_cut, cuts.max())
+            row[name] = {"mean_cut": float(cuts.mean()), "best_cut": float(cuts.max()),
+                         "seconds_100_runs": el}
+            with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1,
+                           **{**kw, "seed": kw.get("seed", 0) + 100,
+                              "noise_seed": kw.get("noise_seed", 0) + 100}) as S:
+                S.run(20000, batch=1000)
+                E, b = S.energy()
+            best_cut = max(best_cut, float((W / 2 - E / 4).max()))
+        row["best_known_cut"] = float(best_cut)
+        for name in regimes:
+            row[name]["mean_deviation_pct"] = 100 * (best_cut - row[name]["mean_cut"]) / best_cut
+        out.append(row)
+        print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+    summ = {}
+    for name in ("random_start", "paper_regime"):
+        for grp, sl in (("unit", slice(0, 5)), ("signed", slice(5, 10))):
+            devs = [r[name]["mean_deviation_pct"] for r in out[sl]]
+            summ[f"{name}_{grp}_mean_deviation_pct"] = [float(min(devs)), float(max(devs))]
+    print(json.dumps({"maxcut800": "G(800,0.06) stand-ins, 100 runs x 5000 Euler steps",
+                      "summary": summ, "rows": out}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,6 +447,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.scaling:
+        scaling(args)
+        return
+    if args.maxcut800:
+        maxcut800(args)
         return
     if args.compare_ttt:
         compare_ttt(args)

@@ -25,11 +25,11 @@ __all__ = [
     "rng", "sym_from_upper", "dense_pm1", "dense_gaussian", "dense_uniform",
     "sparse_pm1", "regular3_edges", "regular3_maxcut", "regular3_uniform_bounds",
     "edges_to_dense", "even_sizes", "psi0_real", "psi0_complex",
-    "planted_signs", "gauge", "edges_to_csr", "maxcut_batch",
+    "planted_signs", "gauge", "edges_to_csr", "maxcut_batch", "gnp_edges", "gnp_maxcut",
 ]
 
 # stream ids keep independent draws independent when seeds collide
-_S_J, _S_PSI, _S_GRAPH, _S_SIZES, _S_PLANT, _S_W = 11, 12, 13, 14, 15, 16
+_S_J, _S_PSI, _S_GRAPH, _S_SIZES, _S_PLANT, _S_W, _S_GNP = 11, 12, 13, 14, 15, 16, 17
 
 
 def rng(seed: int, *stream: int) -> np.random.Generator:
@@ -183,3 +183,27 @@ def maxcut_batch(count: int, lo: int, hi: int, seed: int):
         e, w, _ = regular3_maxcut(int(n), 1000 * seed + k)
         insts.append(edges_to_csr(int(n), e, w))
     return sizes, insts
+
+
+def gnp_edges(n: int, p: float, seed: int) -> np.ndarray:
+    """Erdos-Renyi G(n, p): each pair i < j is an edge independently with
+    probability p.  Returns int32 edges [m, 2] with i < j, sorted."""
+    g = rng(seed, _S_GNP, n)
+    iu, ju = np.triu_indices(n, 1)
+    keep = g.random(iu.size) < p
+    return np.stack([iu[keep], ju[keep]], 1).astype(np.int32)
+
+
+def gnp_maxcut(n: int, p: float, seed: int, signed: bool = False):
+    """Max-cut instance on G(n, p) with weights w = 1 (or +-1 equiprobable when
+    `signed`), in Ising form J_ij = -w_ij (minimising Eq. (h) maximises the
+    cut: cut = W/2 - E/4 with W = sum_{i<j} w_ij).  Returns (edges, w) with w
+    float32; a synthetic stand-in shaped like the paper's N = 800 Max-Cut
+    benchmarks (Sec. 3), not any published instance."""
+    e = gnp_edges(n, p, seed)
+    if signed:
+        g = rng(seed, _S_GNP, n, 1)
+        w = np.where(g.random(e.shape[0]) < 0.5, -1.0, 1.0)
+    else:
+        w = np.ones(e.shape[0])
+    return e, w.astype(np.float32)

@@ -115,6 +115,16 @@ def test_xy1024_full_size_sampled_parity():
     _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=sub, steps_list=(1, 50, 200))
 
 
+def test_xy3000_dense_uniform_sampled_parity():
+    """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
+    U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
+    dt = 0.02: the size range of the paper's scaling study, sampled."""
+    n, R = 3000, 20
+    J = I.dense_uniform(n, 3000)
+    psi0 = I.psi0_complex(n, R, 3000)
+    _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=[0, 11, 19], steps_list=(1, 50, 200))
+
+
 def test_ising64_full_run_spins_and_energies_exact():
     """N = 64, R = 100, 2000 Euler steps: discretised spins and integer-J
     energies bit-exact; oracle and GPU agree on every well-separated trajectory."""

@@ -62,3 +62,21 @@ def test_even_sizes():
     n = I.even_sizes(256, 50, 2000, 1)
     assert n.shape == (256,) and np.all(n % 2 == 0) and n.min() >= 50 and n.max() <= 2000
     assert n.min() < 300 and n.max() > 1700
+
+
+def test_gnp_maxcut_shape_density_and_cut_identity():
+    n, p = 800, 0.06
+    e, w = I.gnp_maxcut(n, p, 3)
+    m = e.shape[0]
+    pairs = n * (n - 1) // 2
+    assert abs(m / pairs - p) < 5 * np.sqrt(p * (1 - p) / pairs)
+    assert np.all(e[:, 0] < e[:, 1]) and np.unique(e[:, 0] * n + e[:, 1]).size == m
+    assert np.all(w == 1.0)
+    es, ws = I.gnp_maxcut(n, p, 3, signed=True)
+    assert np.array_equal(es, e) and set(np.unique(ws)) == {-1.0, 1.0}
+    # Ising form J = -w: cut(s) = W/2 - E(s)/4 for a random partition
+    J = I.edges_to_dense(n, es, -ws).astype(np.float64)
+    s = np.where(np.random.default_rng(0).random(n) < 0.5, -1.0, 1.0)
+    E = -s @ J @ s
+    cut = sum(ws[k] for k in range(m) if s[es[k, 0]] != s[es[k, 1]])
+    assert np.isclose(cut, ws.sum() / 2 - E / 4)
