@@ -137,36 +137,65 @@ dense_step_f32(DenseStepArgs a) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // The epilogue's state operands are loaded into registers two K chunks
+    // before the end of the main loop (when they fit the register budget), so
+    // their HBM latency overlaps the last matrix iterations.
+    constexpr bool PREF = (MODE != MODE_ENERGY) && (MB * NP * (CPLX ? 44 : 32) <= 96);
+    EpiIn pre[PREF ? MB : 1][PREF ? NP : 1];
+    auto prefetch = [&]() {
+        if constexpr (PREF) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    epi_load<MODE, CPLX>(a, m0 + wm * TM + mb * 16 + 4 * (lane >> 4),
+                                         r0 + tcol(tb) + (lane & 15), pre[mb][tb]);
+        }
+    };
+
     const int nk = a.Np / BK;
+    const int kpf = nk >= 2 ? nk - 2 : 0;
     const int l16 = lane & 15;
     const int lq = lane >> 4;
+    constexpr int NS = BK / 16;   // 16-wide K slices per chunk
     gload(0);
     lstore(0);
     __syncthreads();
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
-        if (kc + 1 < nk) gload((kc + 1) * BK);
-#pragma unroll
-        for (int kk = 0; kk < BK / 16; ++kk) {
-            f32x4 av[MB], bv[NB];
+        const bool more = kc + 1 < nk;
+        if (more) gload((kc + 1) * BK);
+        if (kc == kpf) prefetch();   // issued after the chunk load, so that load is not held up
+        // operands of slice kk+1 are read from LDS while slice kk multiplies
+        f32x4 av[2][MB], bv[2][NB];
+        auto lread = [&](int kk, int set) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                av[mb] = *reinterpret_cast<const f32x4 *>(
+                av[set][mb] = *reinterpret_cast<const f32x4 *>(
                     &lds[buf][(wm * TM + mb * 16 + l16) * LDP + kk * 16 + lq * 4]);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                bv[nb] = *reinterpret_cast<const f32x4 *>(
+                bv[set][nb] = *reinterpret_cast<const f32x4 *>(
                     &lds[buf][(BM + bcol(nb) + l16) * LDP + kk * 16 + lq * 4]);
+        };
+        lread(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) {
+            const int set = kk & 1;
+            if (kk + 1 < NS) lread(kk + 1, set ^ 1);
+            // the next chunk goes to the other buffer half-way through this one
+            // (that buffer was last read before the previous barrier)
+            if (kk == NS / 2 && more) lstore(buf ^ 1);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][t], bv[nb][t],
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][mb][t], bv[set][nb][t],
                                                                           acc[mb][nb], 0, 0, 0);
         }
-        if (kc + 1 < nk) lstore(buf ^ 1);
+        if (NS == 1 && more) lstore(buf ^ 1);
         __syncthreads();
     }
 
@@ -208,9 +237,14 @@ dense_step_f32(DenseStepArgs a) {
             const bool rvalid = r < a.R;
             bool bad = false;
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                bad |= step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, rvalid,
-                                                          acc[mb][tb], CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
+            for (int mb = 0; mb < MB; ++mb) {
+                const int i0 = m0 + wm * TM + mb * 16 + 4 * lq;
+                const f32x4 ci = CPLX ? acc[mb][NP + tb] : acc[mb][tb];
+                if constexpr (PREF)
+                    bad |= epi_apply<MODE, CPLX, OP_F32>(a, i0, r, rvalid, pre[mb][tb], acc[mb][tb], ci);
+                else
+                    bad |= step_epilogue4<MODE, CPLX, OP_F32>(a, i0, r, rvalid, acc[mb][tb], ci);
+            }
             if (bad && rvalid) a.flags[r] = 1;
         }
     }

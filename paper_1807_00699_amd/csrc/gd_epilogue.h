@@ -62,20 +62,41 @@ __device__ inline void store_shadow4(void *base, long long idx, f32x4 v) {
     }
 }
 
+// Operands of the pointwise update of four consecutive spins of one
+// trajectory, loaded ahead of the update (the dense kernel issues these loads
+// during its last GEMM iterations so their latency overlaps the matrix work).
+struct EpiIn {
+    f32x4 ep, hh, xr, xi, gm, yr, yi, yg, ar, ai, ag;
+};
+
+template <int MODE, bool CPLX>
+__device__ inline void epi_load(const DenseStepArgs &a, int i0, int r, EpiIn &in) {
+    const long long idx = (long long)r * a.Np + i0;
+    const long long ps = a.plane_stride;
+    in.ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
+    in.hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
+    in.xr = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
+    in.xi = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (CPLX) in.xi = *reinterpret_cast<const f32x4 *>(a.psi_in + ps + idx);
+    in.gm = *reinterpret_cast<const f32x4 *>(a.gam_in + idx);
+    if constexpr (MODE == MODE_RK2 || MODE == MODE_RK3 || MODE == MODE_RK4) {
+        in.yr = *reinterpret_cast<const f32x4 *>(a.y_psi + idx);
+        in.yi = CPLX ? *reinterpret_cast<const f32x4 *>(a.y_psi + ps + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+        in.yg = *reinterpret_cast<const f32x4 *>(a.y_gam + idx);
+        in.ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
+        in.ai = CPLX ? *reinterpret_cast<const f32x4 *>(a.acc_psi + ps + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+        in.ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
+    }
+}
+
 // Returns true if a written value is non-finite.  cr/ci: raw GEMM sums.
 template <int MODE, bool CPLX, int OPT>
-__device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, bool rvalid,
-                                      f32x4 cr, f32x4 ci) {
-    const long long Np = a.Np;
-    const long long idx = (long long)r * Np + i0;
+__device__ inline bool epi_apply(const DenseStepArgs &a, int i0, int r, bool rvalid, const EpiIn &in,
+                                 f32x4 cr, f32x4 ci) {
+    const long long idx = (long long)r * a.Np + i0;
     const long long ps = a.plane_stride;
     const float inv_s = a.inv_s, dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
-    const f32x4 ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
-    const f32x4 hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
-    const f32x4 xr = *reinterpret_cast<const f32x4 *>(a.psi_in + idx);
-    f32x4 xi = {0.f, 0.f, 0.f, 0.f};
-    if (CPLX) xi = *reinterpret_cast<const f32x4 *>(a.psi_in + ps + idx);
-    const f32x4 gm = *reinterpret_cast<const f32x4 *>(a.gam_in + idx);
+    const f32x4 ep = in.ep, hh = in.hh, xr = in.xr, xi = in.xi, gm = in.gm;
     f32x4 fr, fi, fg;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -116,16 +137,14 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
     } else {
         // RK4 stage on y = (psi, gamma); psi_in/gam_in is the stage input
         f32x4 yr = xr, yi = xi, yg = gm;
-        if constexpr (MODE != MODE_RK1) {
-            yr = *reinterpret_cast<const f32x4 *>(a.y_psi + idx);
-            if (CPLX) yi = *reinterpret_cast<const f32x4 *>(a.y_psi + ps + idx);
-            yg = *reinterpret_cast<const f32x4 *>(a.y_gam + idx);
-        }
         f32x4 ar = fr, ai = fi, ag = fg;
         if constexpr (MODE != MODE_RK1) {
-            ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
-            if (CPLX) ai = *reinterpret_cast<const f32x4 *>(a.acc_psi + ps + idx);
-            ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
+            yr = in.yr;
+            yi = in.yi;
+            yg = in.yg;
+            ar = in.ar;
+            ai = in.ai;
+            ag = in.ag;
         }
         if constexpr (MODE == MODE_RK4) {
             const float c6 = dt * (1.0f / 6.0f);
@@ -178,6 +197,14 @@ __device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, boo
         if (CPLX) store_shadow4<OPT>(a.shadow_out, ps + idx, ni);
     }
     return bad;
+}
+
+template <int MODE, bool CPLX, int OPT>
+__device__ inline bool step_epilogue4(const DenseStepArgs &a, int i0, int r, bool rvalid,
+                                      f32x4 cr, f32x4 ci) {
+    EpiIn in;
+    epi_load<MODE, CPLX>(a, i0, r, in);
+    return epi_apply<MODE, CPLX, OPT>(a, i0, r, rvalid, in, cr, ci);
 }
 
 // Energy terms of Eq. (h) for four consecutive spins of trajectory r:
