@@ -30,6 +30,8 @@
  *   Real-amplitude mode integrates the same equations for real Psi.
  *   Readout and energies follow Eq. (h); the diagonal of J is excluded as in
  *   Eq. (main) and Eq. (hs).
+ *   GD-mod (Delta_ij = gamma_i + gamma_j, couplings adapted by Eq. (gamma2)):
+ *   orc_run_mod, explicit Euler.
  *   Brute-force ground states: Ising by Gray-code enumeration, q-state clock
  *   (planar Potts) model by odometer enumeration.
  */
@@ -264,6 +266,82 @@ int orc_run_complex(int n, const double *J, double s, int nq, const double *h,
         if (!finite_vec(pr, 2 * (size_t)n) || !finite_vec(g, n)) bad |= 1;
         free(z);
         free(wg);
+    }
+    if (bad & 2) return ORC_E_OOM;
+    return bad ? ORC_E_NONFINITE : ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* GD-mod: Delta_ij = gamma_i + gamma_j with adapted couplings K_ij      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * orc_run_mod: the GD-mod algorithm (Sec. 1): Eq. (main) with
+ * Delta_ij = gamma_i + gamma_j and per-trajectory couplings K_ij that follow
+ * Eq. (gamma2), dK_ij/dt = eps_hat (J_ij - Delta_ij K_ij), together with
+ * Eq. (gamma); explicit Euler, every right-hand side at the old state:
+ *   c_i     = sum_{j != i} (gamma_i + gamma_j) K_ij Psi_j / s
+ *   Psi_i  += dt [Psi_i (gamma_i - gamma_c - |Psi_i|^2) + c_i + h1_i]
+ *   gamma_i += dt eps_i (rho_th - |Psi_i|^2)
+ *   K_ij   += dt eps_hat (J_ij - (gamma_i + gamma_j) K_ij)
+ * then the noise increment (as in orc_run_real / orc_run_complex).
+ * cplx: 0 real amplitudes psi [R][n], 1 complex psi [R][n][2].
+ * K: [R][n][n] in/out (the caller sets K(0)).
+ */
+int orc_run_mod(int n, int cplx, const double *J, double s, const double *h1,
+                const double *eps, double rho_th, double gamma_c, double eps_hat, double dt,
+                int R, double *psi, double *gamma, double *K, long steps, int nthreads,
+                double D, uint64_t seed, int64_t t0, int64_t r0)
+{
+    if (n <= 0 || R < 0 || steps < 0 || !(s > 0.0) || !J || !eps || !psi || !gamma || !K)
+        return ORC_E_ARG;
+    const int P = cplx ? 2 : 1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) reduction(| : bad)
+    for (int r = 0; r < R; ++r) {
+        double *x = psi + (size_t)r * n * P, *g = gamma + (size_t)r * n;
+        double *Kr = K + (size_t)r * n * n;
+        double *nx = malloc(sizeof(double) * (size_t)n * P);
+        double *ng = malloc(sizeof(double) * (size_t)n);
+        if (!nx || !ng) { free(nx); free(ng); bad |= 2; continue; }
+        for (long t = 0; t < steps; ++t) {
+            for (int i = 0; i < n; ++i) {
+                double cr = 0.0, ci = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    if (j == i) continue;
+                    const double w = (g[i] + g[j]) * Kr[(size_t)i * n + j];
+                    cr += w * x[(size_t)j * P];
+                    if (cplx) ci += w * x[(size_t)j * P + 1];
+                }
+                const double xr = x[(size_t)i * P], xi = cplx ? x[(size_t)i * P + 1] : 0.0;
+                const double rho = xr * xr + xi * xi;
+                const double lin = g[i] - gamma_c - rho;
+                nx[(size_t)i * P] = xr + dt * (xr * lin + cr / s + (h1 ? h1[i] : 0.0));
+                if (cplx) nx[(size_t)i * P + 1] = xi + dt * (xi * lin + ci / s);
+                ng[i] = g[i] + dt * eps[i] * (rho_th - rho);
+            }
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    if (j == i) continue;
+                    double *k = &Kr[(size_t)i * n + j];
+                    *k += dt * eps_hat * (J[(size_t)i * n + j] - (g[i] + g[j]) * *k);
+                }
+            for (int i = 0; i < n; ++i) {
+                x[(size_t)i * P] = nx[(size_t)i * P];
+                if (cplx) x[(size_t)i * P + 1] = nx[(size_t)i * P + 1];
+                g[i] = ng[i];
+            }
+            if (D != 0.0)
+                for (int i = 0; i < n; ++i) {
+                    double g0, g1;
+                    orc_gauss_pair(seed, t0 + t, r0 + r, i, &g0, &g1);
+                    x[(size_t)i * P] += D * sqrt(dt) * g0;
+                    if (cplx) x[(size_t)i * P + 1] += D * sqrt(dt) * g1;
+                }
+        }
+        if (!finite_vec(x, (size_t)n * P) || !finite_vec(g, n)) bad |= 1;
+        free(nx);
+        free(ng);
     }
     if (bad & 2) return ORC_E_OOM;
     return bad ? ORC_E_NONFINITE : ORC_OK;

@@ -74,6 +74,7 @@ def _load():
         lib.orc_gauss_pair.argtypes = [u64, i64, i64, i64, p, p]
         lib.orc_gauss_pair.restype = None
         lib.orc_gauss_block.argtypes = [u64, i64, i64, i, i, p]
+        lib.orc_run_mod.argtypes = [i, i, p, d, p, p, d, d, d, d, i, p, p, p, l_, i, d, u64, i64, i64]
         lib.orc_gauss_block.restype = None
         lib.orc_ising_spins.argtypes = [l_, p, p]
         lib.orc_xy_phases.argtypes = [l_, p, p]
@@ -215,6 +216,38 @@ def run(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
             p = p[..., 0] + 1j * p[..., 1]
         return p, gam
     raise ValueError(f"unknown model {model!r}")
+
+
+def run_mod(J, psi, gamma=None, K=None, *, model: str, steps: int, dt: float, eps=0.1,
+            eps_hat: float = 0.1, rho_th: float = 1.0, gamma_c: float = 0.0, s: float | None = None,
+            g=None, nthreads: int | None = None, noise_D: float = 0.0, noise_seed: int = 0,
+            t0: int = 0, r0: int = 0):
+    """GD-mod (Sec. 1): Eq. (main) with Delta_ij = gamma_i + gamma_j and the
+    couplings K_ij adapted by Eq. (gamma2), explicit Euler.  K: [R][n][n]
+    (None -> K_ij(0) = J_ij with zero diagonal).  Returns (psi, gamma, K)."""
+    lib = _load()
+    J = _f64(J).copy()
+    np.fill_diagonal(J, 0.0)
+    n = J.shape[0]
+    if s is None:
+        s = coupling_scale(J)
+    if nthreads is None:
+        nthreads = threads_default()
+    epsv = np.full(n, float(eps)) if np.isscalar(eps) else _f64(eps).reshape(n)
+    h1 = field_h1(g, rho_th, s)
+    cplx = model != "ising"
+    x = _f64(psi).copy()
+    if x.ndim == (2 if cplx else 1):
+        x = x[None]
+    R = x.shape[0]
+    gam = np.zeros((R, n)) if gamma is None else _f64(gamma).reshape(R, n).copy()
+    Km = np.repeat(J[None], R, 0) if K is None else _f64(K).reshape(R, n, n).copy()
+    rc = lib.orc_run_mod(n, int(cplx), _ptr(J), float(s), _ptr(None if h1 is None else _f64(h1)),
+                         _ptr(epsv), float(rho_th), float(gamma_c), float(eps_hat), float(dt), R,
+                         _ptr(x), _ptr(gam), _ptr(Km), int(steps), int(nthreads), float(noise_D),
+                         int(noise_seed) & M64, int(t0), int(r0))
+    _check(rc, "orc_run_mod")
+    return x, gam, Km
 
 
 def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
