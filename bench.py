@@ -44,8 +44,13 @@ WORKLOADS = {
                      desc="256 Ising instances, N_k even uniform in [50,2000], random 3-regular "
                           "max-cut couplings (J=-1 on edges, gauged by a random s*), R=64, "
                           "Euler dt=0.05, FP32, one persistent launch per chunk (hipGraph)"),
+    "gdmod1024": dict(model="xy", n=1024, R=256, integrator="euler", dt=0.02, steps=2000,
+                      J="dense_gaussian", gdmod=True,
+                      desc="GD-mod (Delta_ij = gamma_i + gamma_j, couplings adapted by Eq. (gamma2)), "
+                           "XY, N=1024, J~N(0,1/N), R=256, Euler dt=0.02, eps_hat=0.2, FP32"),
 }
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
+PEAK_HBM_GBS = 8000.0
 
 
 def kernel_traffic(config_id):
@@ -194,6 +199,76 @@ def bench_batch(args, wl, steps):
                                "kind": "oracle",
                                "sample": f"16 instances x 16 trajectories x {nsteps} steps "
                                          f"(dense FP64 oracle), {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_gdmod(args, wl, steps):
+    """GD-mod throughput: every step streams each trajectory's N x N coupling
+    matrix K through HBM once (read and write), so the roofline is HBM
+    bandwidth; algorithmic bytes per launch = R Np^2 8 (K) + R Np (2 P + 2) 4
+    (amplitudes and gains, read and written).  J rows are shared by all
+    trajectories and served from L2 (not counted)."""
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    n, R = wl["n"], wl["R"]
+    J = getattr(I, wl["J"])(n, 1)
+    Jd = J.astype(np.float64)
+    np.fill_diagonal(Jd, 0.0)
+    gc = float(np.abs(Jd).sum(1).max() / np.sqrt((Jd**2).sum() / n))
+    psi0 = I.psi0_complex(n, R, 1)
+    torch.cuda.init()
+    S = gd.Solver(J, model=gd.GD_XY, dt=wl["dt"], eps=0.1, variant=gd.GD_VARIANT_MOD, eps_hat=0.2,
+                  gamma_c=gc, check_interval=args.check, flags=gd.GD_F_PROFILE)
+    S.set_init(R, psi0)
+    if args.warmup:
+        S.run(args.warmup)
+    S.set_init(R, psi0)
+    torch.cuda.synchronize()
+    st0 = S.stats()
+    t0 = time.perf_counter()
+    S.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = S.stats()
+    E, best = S.energy()
+    S.close()
+    Np = -(-n // 64) * 64
+    launches = st.kernel_launches - st0.kernel_launches
+    avg_s = (st.kernel_ms - st0.kernel_ms) / 1e3 / max(launches, 1)
+    bytes_launch = R * Np * Np * 8.0 + R * Np * (2 * 2 + 2) * 4.0
+    achieved = bytes_launch / avg_s / 1e9
+    out = {
+        "metric": "spin-updates/s (N*R*steps/s)", "value": n * R * steps / el, "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": el / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "R": R, "integrator": "euler", "dt": wl["dt"],
+                   "gamma_c": gc, "energy_check_every": args.check},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "gdmod_euler_k",
+                     "launches": int(launches), "avg_launch_us": avg_s * 1e6,
+                     "bytes_per_launch": bytes_launch},
+        "best_energy": float(E[best]),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = min(16, os.cpu_count() or 1)
+        Rs = threads
+        t0 = time.perf_counter()
+        O.run_mod(J, psi0[:Rs], model="xy", steps=20, dt=wl["dt"], eps=0.1, eps_hat=0.2, gamma_c=gc,
+                  nthreads=threads)
+        pilot = time.perf_counter() - t0
+        ns = max(1, min(10 * steps, int(args.cpu_seconds * 20 / max(pilot, 1e-6))))
+        t0 = time.perf_counter()
+        O.run_mod(J, psi0[:Rs], model="xy", steps=ns, dt=wl["dt"], eps=0.1, eps_hat=0.2, gamma_c=gc,
+                  nthreads=threads)
+        elc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * Rs * ns / elc, "unit": "spin-updates/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{Rs} of {R} trajectories x {ns} steps, {elc:.1f} s"}
     print(json.dumps(out), flush=True)
 
 
@@ -466,6 +541,8 @@ def main():
     steps = args.steps if args.steps is not None else wl["steps"]
     if wl.get("batch"):
         return bench_batch(args, wl, steps)
+    if wl.get("gdmod"):
+        return bench_gdmod(args, wl, steps)
     n, R = wl["n"], wl["R"]
     J = getattr(I, wl["J"])(n, 1)
     psi0 = I.psi0_complex(n, R, 1) if wl["model"] == "xy" else I.psi0_real(n, R, 1)

@@ -93,6 +93,15 @@ typedef enum gd_spin_fmt {
     GD_SPINS_STATE_I32 = 2   /* Potts: int32 k in [0, q), [batch][n] */
 } gd_spin_fmt;
 
+/* Algorithm (Sec. 1).  GD: Delta_ij = 1, K_ij = J_ij.  GD-mod: Delta_ij =
+ * gamma_i + gamma_j with per-trajectory couplings K_ij adapted by Eq. (gamma2),
+ *   dK_ij/dt = eps_hat (J_ij - Delta_ij K_ij),  K_ij(0) = J_ij,
+ * integrated with explicit Euler (FP32, n <= 4096, dense solvers only).  Every
+ * trajectory holds an n x n K (R n^2 floats of device memory).  GD-mod needs
+ * positive gains (Delta_ij <= 0 makes Eq. (gamma2) unstable): gamma_c at or
+ * above max_i sum_j |J_ij| / s keeps every fixed-point gain >= rho_th. */
+typedef enum gd_variant { GD_VARIANT_GD = 0, GD_VARIANT_MOD = 1 } gd_variant;
+
 #define GD_F_DEVICE_PTRS 0x1u  /* array arguments are device pointers */
 #define GD_F_ASYNC 0x2u        /* gd_run returns without synchronising the stream */
 #define GD_F_PROFILE 0x4u      /* time the coupling launches of every 8th step with HIP events */
@@ -128,7 +137,7 @@ typedef struct gd_params {
     double noise_D;
     uint64_t noise_seed;
     int32_t q;               /* GD_POTTS: number of states, 2 <= q <= 8 */
-    int32_t reserved;        /* must be 0 */
+    int32_t variant;         /* gd_variant: GD (default) or GD-mod */
     double h_q;              /* resonant strength of GD_ISING_COMPLEX and GD_POTTS.  For q = 2,
                                 0 selects 1.1 max_i sum_{j != i} |J_ij| / s (the bound of
                                 Sec. 1 for the penalty to pin the phases, with a 10% margin).
@@ -136,6 +145,7 @@ typedef struct gd_params {
                                 and the term outgrows the cubic saturation for q > 4 (for
                                 q = 4 when h_4 > 1), so large values make the dynamics
                                 blow up. */
+    double eps_hat;          /* GD-mod: rate eps_hat of Eq. (gamma2) (default 0.1) */
 } gd_params;
 
 /* Counters of a solver (cumulative over gd_run calls since the last
@@ -176,7 +186,8 @@ void gd_default_params(gd_params *p);
  * Errors: GD_E_INVALID_ARG, GD_E_NOT_SYMMETRIC, GD_E_NONFINITE, GD_E_OOM,
  * GD_E_DEVICE, GD_E_UNSUPPORTED (reduced precision with J not exactly
  * representable in it).  GD_POTTS needs 2 <= params.q <= 8, and h_q > 0
- * when q > 2.  On error *out is set to NULL.
+ * when q > 2.  GD-mod needs Euler steps, FP32 and n <= 4096
+ * (GD_E_UNSUPPORTED otherwise).  On error *out is set to NULL.
  */
 int gd_create(gd_solver **out, int32_t n, const float *J, const float *g,
               int32_t model, const gd_params *p);
@@ -237,6 +248,11 @@ int gd_spins(gd_solver *s, void *out, int32_t fmt);
 int gd_get_state(gd_solver *s, float *psi, float *gamma, int64_t *step);
 int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gamma,
                  int64_t step);
+
+/* gd_mod_couplings (GD-mod): the current coupling matrix K (n*n, row-major)
+ * of trajectory `traj` into caller memory.  gd_set_init and gd_set_state
+ * reset every K to J. */
+int gd_mod_couplings(gd_solver *s, int32_t traj, float *K);
 
 /* gd_stats: copy the counters (out->struct_size must be set). */
 int gd_stats(gd_solver *s, gd_run_stats *out);

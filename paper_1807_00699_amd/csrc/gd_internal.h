@@ -85,6 +85,13 @@ DenseConfig dense_lp_config(bool complex_mode, int idx);
 hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                                 bool j_fp8, const DenseStepArgs &a, hipStream_t st);
 
+// ---- GD-mod (gd_mod.hip): one Euler step with per-trajectory couplings K
+// [R][Np][Np] (updated in place); c_hat = dt * eps_hat.  Needs Np % 16 == 0
+// and gdmod_lds_bytes <= 64 KiB.
+size_t gdmod_lds_bytes(bool complex_mode, int Np);
+hipError_t launch_gdmod(bool complex_mode, const DenseStepArgs &a, const float *J, float *K, float c_hat,
+                        hipStream_t st);
+
 // ---- batched sparse solver (gd_batch.hip)
 struct BatchArgs {
     const int *inst_n;            // [K] spins per instance

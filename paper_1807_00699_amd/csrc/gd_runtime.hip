@@ -131,6 +131,7 @@ struct gd_solver {
     float *psi[3] = {nullptr, nullptr, nullptr};
     float *gam = nullptr, *gam_s = nullptr, *acc_psi = nullptr, *acc_gam = nullptr;
     float *D = nullptr;
+    float *K = nullptr;        // GD-mod couplings [R][Np][Np]
     double *partial = nullptr, *dE = nullptr;
     int *flags = nullptr, *dBest = nullptr, *dCount = nullptr;
     int cur = 0;
@@ -144,6 +145,7 @@ struct gd_solver {
     int64_t ev_used = 0;       // events recorded by the current gd_run call
 
     long long plane() const { return (long long)Rp * Np; }
+    bool mod() const { return prm.variant == GD_VARIANT_MOD; }
     bool complex_mode() const { return P == 2; }
     int integrator() const { return prm.integrator; }
 };
@@ -152,7 +154,7 @@ namespace {
 
 void free_state(gd_solver *s) {
     for (float *&p : s->psi) { if (p) (void)hipFree(p); p = nullptr; }
-    float **fl[] = {&s->gam, &s->gam_s, &s->acc_psi, &s->acc_gam, &s->D};
+    float **fl[] = {&s->gam, &s->gam_s, &s->acc_psi, &s->acc_gam, &s->D, &s->K};
     for (float **p : fl) { if (*p) (void)hipFree(*p); *p = nullptr; }
     for (void *&p : s->shadow) { if (p) (void)hipFree(p); p = nullptr; }
     if (s->shadowD) (void)hipFree(s->shadowD);
@@ -206,6 +208,10 @@ int alloc_state(gd_solver *s, int R) {
         if (rc == GD_OK) rc = dalloc(&s->acc_psi, pl * P);
         if (rc == GD_OK) rc = dalloc(&s->acc_gam, pl);
     }
+    if (rc == GD_OK && s->mod()) {
+        rc = dalloc(&s->gam_s, pl);   // gains ping-pong: every row block reads all gains
+        if (rc == GD_OK) rc = dalloc(&s->K, (size_t)R * s->Np * s->Np);
+    }
     if (rc == GD_OK) rc = dalloc(&s->D, pl * P);
     if (s->op != OP_F32) {
         for (int k = 0; k < npsi && rc == GD_OK; ++k)
@@ -226,8 +232,19 @@ int alloc_state(gd_solver *s, int R) {
         if (s->shadow[k]) GD_HIP(hipMemsetAsync(s->shadow[k], 0, pl * P * sizeof(uint16_t), s->stream));
     }
     GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
+    if (s->gam_s) GD_HIP(hipMemsetAsync(s->gam_s, 0, pl * sizeof(float), s->stream));
     s->cur = 0;
     s->have_state = true;
+    return GD_OK;
+}
+
+// GD-mod: K_ij(0) = J_ij for every trajectory
+int reset_mod_couplings(gd_solver *s) {
+    if (!s->mod() || !s->K) return GD_OK;
+    const size_t m = (size_t)s->Np * s->Np;
+    for (int r = 0; r < s->R; ++r)
+        GD_HIP(hipMemcpyAsync(s->K + (size_t)r * m, s->dJ, m * sizeof(float), hipMemcpyDeviceToDevice,
+                              s->stream));
     return GD_OK;
 }
 
@@ -278,6 +295,34 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
     if (s->prm.noise_D != 0.0) {
         a.noise_amp = float(s->prm.noise_D * std::sqrt(double(a.dt)));
         a.noise_key = splitmix64(s->prm.noise_seed ^ splitmix64((uint64_t)t));
+    }
+    if (s->mod()) {
+        // GD-mod: HBM-bound batched product with per-trajectory couplings
+        a.psi_in = s->psi[s->cur];
+        a.psi_out = s->psi[s->cur ^ 1];
+        a.gam_in = s->gam;
+        a.gam_out = s->gam_s;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            const size_t k = (size_t)s->ev_used * 2;
+            while (s->events.size() < k + 2) {
+                hipEvent_t e;
+                GD_HIP(hipEventCreate(&e));
+                s->events.push_back(e);
+            }
+            e0 = s->events[k];
+            e1 = s->events[k + 1];
+            GD_HIP(hipEventRecord(e0, s->stream));
+        }
+        GD_HIP(launch_gdmod(s->complex_mode(), a, s->dJ, s->K, float(double(a.dt) * s->prm.eps_hat),
+                            s->stream));
+        if (timed) {
+            GD_HIP(hipEventRecord(e1, s->stream));
+            s->ev_used++;
+        }
+        std::swap(s->gam, s->gam_s);
+        s->cur ^= 1;
+        return GD_OK;
     }
     const bool cx = s->complex_mode();
     auto launch = [&](int mode, const DenseStepArgs &x) -> int {
@@ -360,10 +405,11 @@ int choose_config(gd_solver *s) {
             return GD_OK;
         }
     }
-    // tiny problems: no point timing; take the variant with the most workgroups
+    // tiny problems: no point timing; take the variant with the most workgroups.
+    // GD-mod steps do not use the variants (only its energy checks do).
     const long long work = (long long)s->Np * s->Np * s->Rp * s->P;
     int best = -1;
-    if (work >= (1ll << 26)) {
+    if (work >= (1ll << 26) && !s->mod()) {
         hipEvent_t e0, e1;
         GD_HIP(hipEventCreate(&e0));
         GD_HIP(hipEventCreate(&e1));
@@ -414,7 +460,9 @@ int check_params(const gd_params *p) {
     if (p->check_interval < 0) return fail(GD_E_INVALID_ARG, "check_interval must be >= 0");
     if (!(std::isfinite(p->noise_D) && p->noise_D >= 0)) return fail(GD_E_INVALID_ARG, "noise_D must be >= 0");
     if (!(std::isfinite(p->h_q) && p->h_q >= 0)) return fail(GD_E_INVALID_ARG, "h_q must be >= 0");
-    if (p->reserved != 0) return fail(GD_E_INVALID_ARG, "gd_params.reserved must be 0");
+    if (p->variant != GD_VARIANT_GD && p->variant != GD_VARIANT_MOD)
+        return fail(GD_E_INVALID_ARG, "unknown variant");
+    if (!(std::isfinite(p->eps_hat) && p->eps_hat >= 0)) return fail(GD_E_INVALID_ARG, "eps_hat must be >= 0");
     return GD_OK;
 }
 
@@ -546,8 +594,9 @@ void gd_default_params(gd_params *p) {
     p->noise_D = 0.0;
     p->noise_seed = 0;
     p->q = 2;
-    p->reserved = 0;
+    p->variant = GD_VARIANT_GD;
     p->h_q = 0.0;
+    p->eps_hat = 0.1;
 }
 
 const char *gd_error_string(int code) {
@@ -583,6 +632,9 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
         return fail(GD_E_INVALID_ARG, "GD_POTTS needs 2 <= q <= 8");
     if (model == GD_POTTS && prm.q > 2 && !(prm.h_q > 0))
         return fail(GD_E_INVALID_ARG, "GD_POTTS with q > 2 needs h_q > 0");
+    if (prm.variant == GD_VARIANT_MOD &&
+        (prm.integrator != GD_EULER || prm.precision != GD_PREC_FP32 || n > 4096))
+        return fail(GD_E_UNSUPPORTED, "GD-mod runs Euler steps in FP32 with n <= 4096");
 
     gd_solver *s = new (std::nothrow) gd_solver();
     if (!s) return fail(GD_E_OOM, "host allocation failed");
@@ -765,6 +817,7 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
         if ((rc = default_init(s, batch, gamma0)) != GD_OK) return rc;
     }
     GD_HIP(refresh_shadow(s, 0));
+    if ((rc = reset_mod_couplings(s)) != GD_OK) return rc;
     return choose_config(s);
 }
 
@@ -958,9 +1011,24 @@ int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gam
     s->P = savedP;
     if (rc != GD_OK) return rc;
     GD_HIP(refresh_shadow(s, 0));
+    if ((rc = reset_mod_couplings(s)) != GD_OK) return rc;
     GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
     GD_HIP(hipStreamSynchronize(s->stream));
     s->steps_done = step;
+    return GD_OK;
+}
+
+int gd_mod_couplings(gd_solver *s, int32_t traj, float *K) {
+    if (!s || !K) return fail(GD_E_INVALID_ARG, "NULL argument");
+    if (s->batch || !s->mod()) return fail(GD_E_INVALID_ARG, "not a GD-mod solver");
+    if (!s->have_state || !s->K) return fail(GD_E_STATE, "no state");
+    if (traj < 0 || traj >= s->R) return fail(GD_E_INVALID_ARG, "trajectory out of range");
+    const hipMemcpyKind kind =
+        (s->prm.flags & GD_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const float *src = s->K + (size_t)traj * s->Np * s->Np;
+    GD_HIP(hipMemcpy2DAsync(K, (size_t)s->n * sizeof(float), src, (size_t)s->Np * sizeof(float),
+                            (size_t)s->n * sizeof(float), (size_t)s->n, kind, s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
     return GD_OK;
 }
 

@@ -24,6 +24,7 @@ GD_ISING, GD_XY, GD_ISING_COMPLEX, GD_POTTS = 0, 1, 2, 3
 GD_EULER, GD_RK4 = 0, 1
 GD_PREC_FP32, GD_PREC_BF16, GD_PREC_FP16 = 0, 1, 2
 GD_SPINS_I8, GD_SPINS_ANGLE_F32, GD_SPINS_STATE_I32 = 0, 1, 2
+GD_VARIANT_GD, GD_VARIANT_MOD = 0, 1
 GD_F_DEVICE_PTRS, GD_F_ASYNC, GD_F_PROFILE = 0x1, 0x2, 0x4
 
 # exported symbols of include/gd.h
@@ -32,7 +33,7 @@ EXPORTS = (
     "gd_energy_device", "gd_spins", "gd_get_state", "gd_set_state", "gd_stats",
     "gd_coupling_scale", "gd_error_string", "gd_last_error", "gd_create_batch", "gd_set_targets",
     "gd_ttt", "gd_features", "gd_mlp_create", "gd_mlp_destroy", "gd_mlp_set_params",
-    "gd_mlp_get_params", "gd_mlp_forward", "gd_mlp_train_step", "gd_propose",
+    "gd_mlp_get_params", "gd_mlp_forward", "gd_mlp_train_step", "gd_propose", "gd_mod_couplings",
 )
 GD_NFEAT = 20
 GD_MLP_NPARAM = 5634
@@ -46,7 +47,7 @@ class gd_params(C.Structure):
         ("init_amp", C.c_double), ("seed", C.c_uint64), ("check_interval", C.c_int32),
         ("has_target", C.c_int32), ("target_energy", C.c_double), ("stream", C.c_void_p),
         ("noise_D", C.c_double), ("noise_seed", C.c_uint64), ("q", C.c_int32),
-        ("reserved", C.c_int32), ("h_q", C.c_double),
+        ("variant", C.c_int32), ("h_q", C.c_double), ("eps_hat", C.c_double),
     ]
 
 
@@ -290,6 +291,13 @@ class Solver:
 
     def stats(self):
         return gd_stats(self.h)
+
+    def mod_couplings(self, traj):
+        """GD-mod: K [n][n] of trajectory `traj`."""
+        K = np.empty((self.n, self.n), np.float32)
+        _check(load().gd_mod_couplings(self.h, int(traj), K.ctypes.data_as(C.c_void_p)),
+               "gd_mod_couplings")
+        return K
 
     @property
     def scale(self):

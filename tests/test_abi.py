@@ -93,7 +93,10 @@ def test_host_validation_errors(lib):
     assert _create(np.zeros((4, 4)), precision=9)[0] == gd.GD_E_INVALID_ARG
     assert _create(np.zeros((4, 4)), noise_D=-1.0)[0] == gd.GD_E_INVALID_ARG
     assert _create(np.zeros((4, 4)), h_q=float("nan"))[0] == gd.GD_E_INVALID_ARG
-    assert _create(np.zeros((4, 4)), reserved=1)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), variant=2)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), eps_hat=-1.0)[0] == gd.GD_E_INVALID_ARG
+    assert _create(np.zeros((4, 4)), variant=1, integrator=1)[0] == gd.GD_E_UNSUPPORTED
+    assert _create(np.zeros((4, 4)), variant=1, precision=1)[0] == gd.GD_E_UNSUPPORTED
     for q in (0, 1, 9):
         assert _create(np.zeros((4, 4)), model=gd.GD_POTTS, q=q, h_q=0.5)[0] == gd.GD_E_INVALID_ARG
     assert _create(np.zeros((4, 4)), model=gd.GD_POTTS, q=3)[0] == gd.GD_E_INVALID_ARG
