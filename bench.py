@@ -7,9 +7,9 @@ all R trajectories, including the device energy check (discretise, energy
 GEMM, best-of-R) every `check` steps.  Default workload: XY model, N = 1024,
 J_ij ~ N(0, 1/N), R = 1024 complex trajectories, RK4 dt = 0.02, FP32, 5000
 steps.  Prints one JSON line with spin-updates/s (N * R * steps / s), the
-roofline position of the dominant kernel (device time per launch from HIP
-events recorded on the solver's stream around the coupling launches of every
-8th step of the timed run) and the
+roofline position of the dominant kernel (device time per launch from one
+pair of HIP events recorded on the solver's stream around all coupling
+launches of every 8th step of the timed run) and the
 FP64 oracle timed on the host CPU over a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -549,8 +549,8 @@ def main():
     model = gd.GD_XY if wl["model"] == "xy" else gd.GD_ISING
     integ = gd.GD_RK4 if wl["integrator"] == "rk4" else gd.GD_EULER
     torch.cuda.init()
-    # inputs resident in HBM before the timed region; HIP events around every
-    # coupling launch on the solver's stream (GD_F_PROFILE)
+    # inputs resident in HBM before the timed region; HIP events on the
+    # solver's stream around the coupling launches of every 8th step (GD_F_PROFILE)
     prec_name = wl.get("precision", "fp32")
     prec = {"fp32": gd.GD_PREC_FP32, "bf16": gd.GD_PREC_BF16, "fp16": gd.GD_PREC_FP16}[prec_name]
     S = gd.Solver(J, model=model, integrator=integ, dt=wl["dt"], eps=0.1, precision=prec,

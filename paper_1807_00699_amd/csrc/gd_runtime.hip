@@ -142,7 +142,8 @@ struct gd_solver {
     double ttt_seconds = 0.0, best_energy = HUGE_VAL;
     int64_t ttt_steps = 0;
     std::vector<hipEvent_t> events;
-    int64_t ev_used = 0;       // events recorded by the current gd_run call
+    int64_t ev_used = 0;       // event pairs recorded by the current gd_run call
+    int64_t ev_launches = 0;   // coupling launches bracketed by those pairs
 
     long long plane() const { return (long long)Rp * Np; }
     bool mod() const { return prm.variant == GD_VARIANT_MOD; }
@@ -289,7 +290,27 @@ hipError_t refresh_shadow(gd_solver *s, int k) {
 // Enqueue integration step number t.  `dt_override` >= 0 replaces dt (used
 // with 0 by the tuner: the state is then left bit-for-bit unchanged, noise
 // included, since its amplitude is D sqrt(dt)).
+// HIP event pair around work on the solver's stream (GD_F_PROFILE)
+int ev_begin(gd_solver *s) {
+    const size_t k = (size_t)s->ev_used * 2;
+    while (s->events.size() < k + 2) {
+        hipEvent_t e;
+        GD_HIP(hipEventCreate(&e));
+        s->events.push_back(e);
+    }
+    GD_HIP(hipEventRecord(s->events[k], s->stream));
+    return GD_OK;
+}
+
+int ev_end(gd_solver *s, int launches) {
+    GD_HIP(hipEventRecord(s->events[(size_t)s->ev_used * 2 + 1], s->stream));
+    s->ev_used++;
+    s->ev_launches += launches;
+    return GD_OK;
+}
+
 int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed, int64_t t) {
+    int rc;
     DenseStepArgs a = base_args(s);
     if (dt_override >= 0.0f) a.dt = dt_override;
     if (s->prm.noise_D != 0.0) {
@@ -302,51 +323,21 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
         a.psi_out = s->psi[s->cur ^ 1];
         a.gam_in = s->gam;
         a.gam_out = s->gam_s;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-            const size_t k = (size_t)s->ev_used * 2;
-            while (s->events.size() < k + 2) {
-                hipEvent_t e;
-                GD_HIP(hipEventCreate(&e));
-                s->events.push_back(e);
-            }
-            e0 = s->events[k];
-            e1 = s->events[k + 1];
-            GD_HIP(hipEventRecord(e0, s->stream));
-        }
+        if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
         GD_HIP(launch_gdmod(s->complex_mode(), a, s->dJ, s->K, float(double(a.dt) * s->prm.eps_hat),
                             s->stream));
-        if (timed) {
-            GD_HIP(hipEventRecord(e1, s->stream));
-            s->ev_used++;
-        }
+        if (timed && (rc = ev_end(s, 1)) != GD_OK) return rc;
         std::swap(s->gam, s->gam_s);
         s->cur ^= 1;
         return GD_OK;
     }
-    const bool cx = s->complex_mode();
     auto launch = [&](int mode, const DenseStepArgs &x) -> int {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-            const size_t k = (size_t)s->ev_used * 2;
-            while (s->events.size() < k + 2) {
-                hipEvent_t e;
-                GD_HIP(hipEventCreate(&e));
-                s->events.push_back(e);
-            }
-            e0 = s->events[k];
-            e1 = s->events[k + 1];
-            GD_HIP(hipEventRecord(e0, s->stream));
-        }
         GD_HIP(launch_coupling(s, cfg, mode, x));
-        if (timed) {
-            GD_HIP(hipEventRecord(e1, s->stream));
-            s->ev_used++;
-        }
         return GD_OK;
     };
-    int rc;
     const bool lp = s->op != OP_F32;
+    // GD_F_PROFILE: one event pair around all coupling launches of the step
+    if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
     if (s->integrator() == GD_EULER) {
         a.B = lp ? s->shadow[s->cur] : (const void *)s->psi[s->cur];
         a.shadow_out = s->shadow[s->cur ^ 1];
@@ -355,6 +346,7 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
         a.gam_in = s->gam;
         a.gam_out = s->gam;
         if ((rc = launch(MODE_EULER, a)) != GD_OK) return rc;
+        if (timed && (rc = ev_end(s, 1)) != GD_OK) return rc;
         s->cur ^= 1;
         return GD_OK;
     }
@@ -378,6 +370,7 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
     a.B = op_of(iA); a.psi_in = Sa; a.gam_in = s->gam_s; a.psi_out = Y; a.gam_out = s->gam;
     a.shadow_out = s->shadow[iY];
     if ((rc = launch(MODE_RK4, a)) != GD_OK) return rc;
+    if (timed && (rc = ev_end(s, 4)) != GD_OK) return rc;
     return GD_OK;
 }
 
@@ -833,6 +826,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     }
     const bool timed = (s->prm.flags & GD_F_PROFILE) != 0;
     s->ev_used = 0;
+    s->ev_launches = 0;
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = s->prm.check_interval;
     int64_t done = 0;
@@ -891,8 +885,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             GD_HIP(hipEventElapsedTime(&ms, s->events[(size_t)k * 2], s->events[(size_t)k * 2 + 1]));
             s->kernel_ms += ms;
         }
-        s->launches_timed += s->ev_used;
+        s->launches_timed += s->ev_launches;
         s->ev_used = 0;
+        s->ev_launches = 0;
     }
     GD_HIP(launch_count_flags(s->flags, s->R, s->dCount, s->stream));
     int cnt = 0;
