@@ -15,7 +15,7 @@
 // per-trajectory quantity is a plane [Rp][Np] (trajectory-major, spin index
 // contiguous).  The product is C[i][r] = sum_k J[i][k] Psi[r][k]: both
 // operands are K-contiguous, so global->LDS copies are plain 16-byte vector
-// loads and LDS holds both tiles as [row][k] with a 4-float pad per row
+// loads and LDS holds both tiles as [row][k] with an 8-float pad per row
 // (conflict-free 16-byte LDS reads).
 //
 // Tiling: a workgroup owns BM rows x BN GEMM columns, WM x WN waves; a wave
@@ -28,7 +28,15 @@
 // K order inside a 16-wide slice is permuted: lane group q = lane/16 feeds
 // k = 4q + t to MFMA number t (A and B use the same permutation), so each
 // lane fetches its 4 operands of a slice with one ds_read_b128.
+//
+// Pipelining: chunk loads are issued LA chunks ahead (register sets), the
+// next chunk is written to the other LDS buffer half-way through the current
+// one, LDS operand reads run one slice ahead of the MFMAs, and (when they fit)
+// the epilogue's state operands are loaded two chunks before the end.  KS > 1
+// splits K between KS groups of waves of the same tile (more waves per CU).
 #include "gd_epilogue.h"
+
+#include <type_traits>
 
 namespace gd {
 
@@ -53,11 +61,13 @@ __device__ inline void tile_map(int b, int nblk, int n_mt, int n_ct, int &mt, in
     ct = in / gsz;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE>
-__global__ void __launch_bounds__(64 * WM * WN)
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE, int KS, int LA>
+__global__ void __launch_bounds__(64 * WM * WN * KS)
 dense_step_f32(DenseStepArgs a) {
-    constexpr int LDP = BK + 4;     // LDS row pitch in floats
-    constexpr int NT = 64 * WM * WN;
+    // LDS row pitch in floats: an 8-float pad makes the 16-byte operand reads
+    // bank-conflict free on gfx950 (a 4-float pad still conflicts)
+    constexpr int LDP = BK + 8;
+    constexpr int NTG = 64 * WM * WN;   // threads of one K group
     constexpr int TM = BM / WM;     // rows per wave
     constexpr int TN = BN / WN;     // GEMM columns per wave
     constexpr int MB = TM / 16;     // 16-row MFMA blocks per wave
@@ -66,15 +76,23 @@ dense_step_f32(DenseStepArgs a) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
     static_assert(!CPLX || (NB % 2 == 0), "complex waves pair re/im blocks");
     constexpr int KQ = BK / 4;                 // float4 per row chunk
-    constexpr int AL = BM * KQ / NT;           // A float4 loads per thread
-    constexpr int BL = BN * KQ / NT;           // B float4 loads per thread
-    static_assert(BM * KQ % NT == 0 && BN * KQ % NT == 0, "load split");
+    constexpr int AL = BM * KQ / NTG;          // A float4 loads per thread
+    constexpr int BL = BN * KQ / NTG;          // B float4 loads per thread
+    static_assert(BM * KQ % NTG == 0 && BN * KQ % NTG == 0, "load split");
+    constexpr int TILE = (BM + BN) * LDP;
+    static_assert(LA == 1 || LA == 2, "load lookahead of one or two chunks");
+    // KS > 1: KS groups of WM x WN waves take K chunks g, g + KS, ... of the
+    // same output tile (more waves per CU to hide latency); group 0 adds the
+    // other groups' partial sums through LDS and runs the epilogue.
+    static_assert(KS == 1 || (KS - 1) * NTG * MB * NB * 4 <= KS * 2 * TILE, "reduction fits LDS");
 
-    __shared__ __attribute__((aligned(16))) float lds[2][(BM + BN) * LDP];
+    __shared__ __attribute__((aligned(16))) float lds[KS][2][TILE];
 
     const int tid = threadIdx.x;
+    const int grp = tid / NTG;
+    const int tg = tid % NTG;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = tg >> 6;
     const int wm = wave % WM;
     const int wn = wave / WM;
     const int n_mt = a.Np / BM;
@@ -87,37 +105,39 @@ dense_step_f32(DenseStepArgs a) {
 
     const float *J = static_cast<const float *>(a.J);
     const float *Bop = static_cast<const float *>(a.B);
+    float(*gl)[TILE] = lds[grp];
 
-    f32x4 ra[AL], rb[BL];
-    auto gload = [&](int k0) {
+    // LA > 1: chunk loads are issued LA chunks ahead into LA register sets
+    f32x4 ra[LA][AL], rb[LA][BL];
+    auto gload = [&](int k0, int set) {
 #pragma unroll
         for (int u = 0; u < AL; ++u) {
-            const int q = tid + u * NT;
+            const int q = tg + u * NTG;
             const int row = q / KQ, kq = q % KQ;
-            ra[u] = *reinterpret_cast<const f32x4 *>(J + (m0 + row) * Np + k0 + kq * 4);
+            ra[set][u] = *reinterpret_cast<const f32x4 *>(J + (m0 + row) * Np + k0 + kq * 4);
         }
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
-            const int q = tid + u * NT;
+            const int q = tg + u * NTG;
             const int col = q / KQ, kq = q % KQ;
             const int plane = CPLX ? col / (BN / 2) : 0;
             const int tr = CPLX ? col % (BN / 2) : col;
-            rb[u] = *reinterpret_cast<const f32x4 *>(Bop + plane * a.plane_stride +
+            rb[set][u] = *reinterpret_cast<const f32x4 *>(Bop + plane * a.plane_stride +
                                                      (r0 + tr) * Np + k0 + kq * 4);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int set) {
 #pragma unroll
         for (int u = 0; u < AL; ++u) {
-            const int q = tid + u * NT;
+            const int q = tg + u * NTG;
             const int row = q / KQ, kq = q % KQ;
-            *reinterpret_cast<f32x4 *>(&lds[buf][row * LDP + kq * 4]) = ra[u];
+            *reinterpret_cast<f32x4 *>(&gl[buf][row * LDP + kq * 4]) = ra[set][u];
         }
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
-            const int q = tid + u * NT;
+            const int q = tg + u * NTG;
             const int col = q / KQ, kq = q % KQ;
-            *reinterpret_cast<f32x4 *>(&lds[buf][(BM + col) * LDP + kq * 4]) = rb[u];
+            *reinterpret_cast<f32x4 *>(&gl[buf][(BM + col) * LDP + kq * 4]) = rb[set][u];
         }
     };
     // LDS column (within the B tile) of column block nb of this wave
@@ -140,7 +160,7 @@ dense_step_f32(DenseStepArgs a) {
     // The epilogue's state operands are loaded into registers two K chunks
     // before the end of the main loop (when they fit the register budget), so
     // their HBM latency overlaps the last matrix iterations.
-    constexpr bool PREF = (MODE != MODE_ENERGY) && (MB * NP * (CPLX ? 44 : 32) <= 96);
+    constexpr bool PREF = KS == 1 && LA == 1 && (MODE != MODE_ENERGY) && (MB * NP * (CPLX ? 44 : 32) <= 96);
     EpiIn pre[PREF ? MB : 1][PREF ? NP : 1];
     auto prefetch = [&]() {
         if constexpr (PREF) {
@@ -154,75 +174,118 @@ dense_step_f32(DenseStepArgs a) {
     };
 
     const int nk = a.Np / BK;
-    const int kpf = nk >= 2 ? nk - 2 : 0;
+    const int nit = (nk + KS - 1) / KS;        // iterations of every group
+    const int itpf = nit >= 2 ? nit - 2 : 0;
     const int l16 = lane & 15;
     const int lq = lane >> 4;
     constexpr int NS = BK / 16;   // 16-wide K slices per chunk
-    gload(0);
-    lstore(0);
+    if (grp < nk) gload(grp * BK, 0);
+    if (grp < nk) lstore(0, 0);
+#pragma unroll
+    for (int j = 1; j < LA; ++j)
+        if (grp + j * KS < nk) gload((grp + j * KS) * BK, j);
     __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        const bool more = kc + 1 < nk;
-        if (more) gload((kc + 1) * BK);
-        if (kc == kpf) prefetch();   // issued after the chunk load, so that load is not held up
-        // operands of slice kk+1 are read from LDS while slice kk multiplies
-        f32x4 av[2][MB], bv[2][NB];
-        auto lread = [&](int kk, int set) {
+    // one iteration; SL = it % LA is a compile-time constant so the register
+    // sets of the chunk loads are indexed statically
+    auto iteration = [&](int it, auto slc) {
+        constexpr int SL = decltype(slc)::value;
+        const int buf = it & 1;
+        const int kc = it * KS + grp;            // this group's chunk
+        const bool have = kc < nk;
+        const bool more = kc + KS < nk;
+        if (kc + LA * KS < nk) gload((kc + LA * KS) * BK, SL);
+        if (grp == 0 && it == itpf) prefetch();   // after the chunk load, so that load is not held up
+        if (have) {
+            // operands of slice kk+1 are read from LDS while slice kk multiplies
+            f32x4 av[2][MB], bv[2][NB];
+            auto lread = [&](int kk, int set) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    av[set][mb] = *reinterpret_cast<const f32x4 *>(
+                        &gl[buf][(wm * TM + mb * 16 + l16) * LDP + kk * 16 + lq * 4]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    bv[set][nb] = *reinterpret_cast<const f32x4 *>(
+                        &gl[buf][(BM + bcol(nb) + l16) * LDP + kk * 16 + lq * 4]);
+            };
+            lread(0, 0);
+#pragma unroll
+            for (int kk = 0; kk < NS; ++kk) {
+                const int set = kk & 1;
+                if (kk + 1 < NS) lread(kk + 1, set ^ 1);
+                // the next chunk goes to the other buffer half-way through this one
+                // (that buffer was last read before the previous barrier)
+                if (kk == NS / 2 && more) lstore(buf ^ 1, (SL + 1) % LA);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                av[set][mb][t], bv[set][nb][t], acc[mb][nb], 0, 0, 0);
+            }
+            if (NS == 1 && more) lstore(buf ^ 1, (SL + 1) % LA);
+        }
+        __syncthreads();
+    };
+    for (int it = 0; it < nit; it += LA) {
+        iteration(it, std::integral_constant<int, 0>{});
+        if constexpr (LA > 1)
+            if (it + 1 < nit) iteration(it + 1, std::integral_constant<int, 1>{});
+    }
+    if constexpr (KS > 1) {
+        // partial sums of groups 1..KS-1 -> group 0 (all LDS reads of the loop are done)
+        float *xs = &lds[0][0][0];
+        if (grp > 0) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                av[set][mb] = *reinterpret_cast<const f32x4 *>(
-                    &lds[buf][(wm * TM + mb * 16 + l16) * LDP + kk * 16 + lq * 4]);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                bv[set][nb] = *reinterpret_cast<const f32x4 *>(
-                    &lds[buf][(BM + bcol(nb) + l16) * LDP + kk * 16 + lq * 4]);
-        };
-        lread(0, 0);
+                for (int nb = 0; nb < NB; ++nb)
+                    *reinterpret_cast<f32x4 *>(
+                        &xs[((((grp - 1) * MB + mb) * NB + nb) * NTG + tg) * 4]) = acc[mb][nb];
+        }
+        __syncthreads();
+        if (grp == 0) {
 #pragma unroll
-        for (int kk = 0; kk < NS; ++kk) {
-            const int set = kk & 1;
-            if (kk + 1 < NS) lread(kk + 1, set ^ 1);
-            // the next chunk goes to the other buffer half-way through this one
-            // (that buffer was last read before the previous barrier)
-            if (kk == NS / 2 && more) lstore(buf ^ 1);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int g = 1; g < KS; ++g)
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][mb][t], bv[set][nb][t],
-                                                                          acc[mb][nb], 0, 0, 0);
+                        acc[mb][nb] += *reinterpret_cast<const f32x4 *>(
+                            &xs[((((g - 1) * MB + mb) * NB + nb) * NTG + tg) * 4]);
         }
-        if (NS == 1 && more) lstore(buf ^ 1);
         __syncthreads();
     }
 
     // ---------------------------------------------------------------- epilogue
-    // acc[mb][nb][e] holds row i = m0 + wm*TM + mb*16 + 4*lq + e, column l16 of block nb.
+    // acc[mb][nb][e] holds row i = m0 + wm*TM + mb*16 + 4*lq + e, column l16 of
+    // block nb; only group 0 holds the full sums.
     if constexpr (MODE == MODE_ENERGY) {
         double esum[NP];
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
             const int r = r0 + tcol(tb) + l16;
             double s = 0.0;
+            if (grp == 0) {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, acc[mb][tb],
-                                         CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
+                for (int mb = 0; mb < MB; ++mb)
+                    s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, acc[mb][tb],
+                                             CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
+            }
             s += __shfl_xor(s, 16);
             s += __shfl_xor(s, 32);
             esum[tb] = s;
         }
         // combine the row waves through LDS (the main loop is done with it)
-        double *red = reinterpret_cast<double *>(&lds[0][0]);
-        if (lq == 0) {
+        double *red = reinterpret_cast<double *>(&lds[0][0][0]);
+        if (grp == 0 && lq == 0) {
 #pragma unroll
             for (int tb = 0; tb < NP; ++tb) red[(wm * WN + wn) * (NP * 16) + tb * 16 + l16] = esum[tb];
         }
         __syncthreads();
-        if (wm == 0 && lq == 0) {
+        if (grp == 0 && wm == 0 && lq == 0) {
 #pragma unroll
             for (int tb = 0; tb < NP; ++tb) {
                 double s = 0.0;
@@ -231,6 +294,7 @@ dense_step_f32(DenseStepArgs a) {
             }
         }
     } else {
+        if (grp != 0) return;
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
             const int r = r0 + tcol(tb) + l16;
@@ -250,13 +314,13 @@ dense_step_f32(DenseStepArgs a) {
     }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool CPLX>
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int KS, int LA>
 hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
     if (a.Np % BM || a.Np % BK || a.Rp % TRAJ) return hipErrorInvalidValue;
     const int nblk = (a.Np / BM) * (a.Rp / TRAJ);
-    const dim3 grid(nblk), block(64 * WM * WN);
-#define GD_LAUNCH(M) dense_step_f32<BM, BN, BK, WM, WN, CPLX, M><<<grid, block, 0, st>>>(a)
+    const dim3 grid(nblk), block(64 * WM * WN * KS);
+#define GD_LAUNCH(M) dense_step_f32<BM, BN, BK, WM, WN, CPLX, M, KS, LA><<<grid, block, 0, st>>>(a)
     switch (mode) {
     case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
     case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
@@ -270,20 +334,24 @@ hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Variants {BM, BN (GEMM columns), BK, WM, WN}; identical for real and
-// complex amplitudes (complex tiles hold BN/2 trajectories).  The runtime
-// times the variants that tile a problem and keeps the fastest.
-#define GD_DENSE_VARIANTS(X)      \
-    X(0, 64, 64, 32, 2, 2)        \
-    X(1, 64, 128, 32, 2, 2)       \
-    X(2, 128, 128, 32, 2, 2)      \
-    X(3, 32, 64, 32, 1, 2)        \
-    X(4, 64, 64, 64, 2, 2)        \
-    X(5, 64, 128, 64, 2, 2)       \
-    X(6, 128, 64, 32, 4, 1)
+// Variants {BM, BN (GEMM columns), BK, WM, WN, KS (K groups), LA (load
+// lookahead in chunks)}; identical for real and complex amplitudes (complex
+// tiles hold BN/2 trajectories).  The runtime times the variants that tile a
+// problem and keeps the fastest.
+#define GD_DENSE_VARIANTS(X)            \
+    X(0, 64, 64, 32, 2, 2, 1, 1)        \
+    X(1, 64, 128, 32, 2, 2, 1, 1)       \
+    X(2, 128, 128, 32, 2, 2, 1, 1)      \
+    X(3, 32, 64, 32, 1, 2, 1, 1)        \
+    X(4, 64, 64, 64, 2, 2, 1, 1)        \
+    X(5, 64, 128, 64, 2, 2, 1, 1)       \
+    X(6, 128, 64, 32, 4, 1, 1, 1)       \
+    X(7, 64, 64, 32, 2, 2, 2, 1)        \
+    X(8, 64, 64, 32, 2, 2, 1, 2)        \
+    X(9, 128, 128, 32, 2, 2, 1, 2)
 
-constexpr int kCfg[][5] = {
-#define GD_ROW(id, bm, bn, bk, wm, wn) {bm, bn, bk, wm, wn},
+constexpr int kCfg[][7] = {
+#define GD_ROW(id, bm, bn, bk, wm, wn, ks, la) {bm, bn, bk, wm, wn, ks, la},
     GD_DENSE_VARIANTS(GD_ROW)
 #undef GD_ROW
 };
@@ -300,17 +368,17 @@ DenseConfig dense_config(bool complex_mode, int idx) {
     c.bk = kCfg[idx][2];
     c.wn = kCfg[idx][4];
     c.traj_tile = complex_mode ? c.bn / 2 : c.bn;
-    c.threads = 64 * kCfg[idx][3] * kCfg[idx][4];
+    c.threads = 64 * kCfg[idx][3] * kCfg[idx][4] * kCfg[idx][5];
     return c;
 }
 
 hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                              const DenseStepArgs &a, hipStream_t st) {
     if (op != OP_F32) return hipErrorInvalidValue;
-#define GD_CASE(id, bm, bn, bk, wm, wn)                                                  \
+#define GD_CASE(id, bm, bn, bk, wm, wn, ks, la)                                          \
     case id:                                                                             \
-        return complex_mode ? launch_modes<bm, bn, bk, wm, wn, true>(mode, a, st)        \
-                            : launch_modes<bm, bn, bk, wm, wn, false>(mode, a, st);
+        return complex_mode ? launch_modes<bm, bn, bk, wm, wn, true, ks, la>(mode, a, st) \
+                            : launch_modes<bm, bn, bk, wm, wn, false, ks, la>(mode, a, st);
     switch (cfg.id) { GD_DENSE_VARIANTS(GD_CASE) }
 #undef GD_CASE
     return hipErrorInvalidValue;
