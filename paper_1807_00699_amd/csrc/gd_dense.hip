@@ -293,6 +293,42 @@ dense_step_f32(DenseStepArgs a) {
                 a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l16] = s;
             }
         }
+    } else if constexpr (!PREF && (CPLX ? 2 : 1) * TRAJ * (BM + 4) <= KS * 2 * TILE) {
+        // The sums are staged through LDS as [trajectory][row] (the main loop
+        // is done with it) so that the state update runs with consecutive
+        // lanes on consecutive spins of one trajectory (contiguous runs per
+        // wave instead of 64-byte pieces of 16 trajectories); every thread of
+        // the workgroup, all K groups included, takes part in the update.
+        constexpr int TP = BM + 4;                          // LDS pitch in floats
+        float *st = &lds[0][0][0];
+        float *sti = st + TRAJ * TP;                       // imaginary sums (complex)
+        if (grp == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) {
+                const int tr = tcol(tb) + l16;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const int row = wm * TM + mb * 16 + 4 * lq;
+                    *reinterpret_cast<f32x4 *>(&st[tr * TP + row]) = acc[mb][tb];
+                    if (CPLX) *reinterpret_cast<f32x4 *>(&sti[tr * TP + row]) = acc[mb][NP + tb];
+                }
+            }
+        }
+        __syncthreads();
+        constexpr int NT = NTG * KS;
+        constexpr int RG = BM / 4;                          // 4-row groups per trajectory
+        static_assert((TRAJ * RG) % NT == 0, "epilogue split");
+#pragma unroll 4
+        for (int u = 0; u < TRAJ * RG / NT; ++u) {
+            const int g = tid + u * NT;
+            const int tr = g / RG, row = (g % RG) * 4;
+            const int r = r0 + tr;
+            const bool rvalid = r < a.R;
+            const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
+            const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
+            const bool bad = step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, cr, ci);
+            if (bad && rvalid) a.flags[r] = 1;
+        }
     } else {
         if (grp != 0) return;
 #pragma unroll

@@ -164,26 +164,37 @@ dense_step_lp(DenseStepArgs a) {
     gload(0);
     lstore(0);
     __syncthreads();
+    constexpr int NS = BK / 16;   // 16-wide K slices per chunk
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
-        if (kc + 1 < nk) gload((kc + 1) * BK);
-#pragma unroll
-        for (int kk = 0; kk < BK / 16; ++kk) {
-            u32x4 av[MB], bv[NB];
+        const bool more = kc + 1 < nk;
+        if (more) gload((kc + 1) * BK);
+        // operands of slice kk+1 are read from LDS while slice kk multiplies;
+        // the next chunk goes to the other buffer half-way through this one
+        u32x4 av[2][MB], bv[2][NB];
+        auto lread = [&](int kk, int set) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                av[mb] = *reinterpret_cast<const u32x4 *>(
+                av[set][mb] = *reinterpret_cast<const u32x4 *>(
                     &lds[buf][(wm * TM + mb * 32 + l32) * LDP + kk * 16 + lh * 8]);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                bv[nb] = *reinterpret_cast<const u32x4 *>(
+                bv[set][nb] = *reinterpret_cast<const u32x4 *>(
                     &lds[buf][(BM + bcol(nb) + l32) * LDP + kk * 16 + lh * 8]);
+        };
+        lread(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) {
+            const int set = kk & 1;
+            if (kk + 1 < NS) lread(kk + 1, set ^ 1);
+            if (kk == NS / 2 && more) lstore(buf ^ 1);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma32<OPT>(av[mb], bv[nb], acc[mb][nb]);
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[mb][nb] = mfma32<OPT>(av[set][mb], bv[set][nb], acc[mb][nb]);
         }
-        if (kc + 1 < nk) lstore(buf ^ 1);
+        if (NS == 1 && more) lstore(buf ^ 1);
         __syncthreads();
     }
 
@@ -222,7 +233,44 @@ dense_step_lp(DenseStepArgs a) {
                 a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l32] = s;
             }
         }
+    } else if constexpr ((CPLX ? 2 : 1) * TRAJ * (BM + 4) * 4 <= 2 * (BM + BN) * LDP * 2) {
+        // The sums are staged through LDS as [trajectory][row] (the main loop
+        // is done with it) so that the state update runs with consecutive
+        // lanes on consecutive spins of one trajectory: every state load and
+        // store of a wave is then a few fully used contiguous runs instead of
+        // 16-byte pieces of 32 trajectories.
+        constexpr int TP = BM + 4;                          // LDS pitch in floats
+        float *st = reinterpret_cast<float *>(&lds[0][0]);
+        float *sti = st + TRAJ * TP;                       // imaginary sums (complex)
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int tr = tcol(tb) + l32;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = wm * TM + mb * 32 + 8 * q + 4 * lh;
+                    *reinterpret_cast<f32x4 *>(&st[tr * TP + row]) = sub4(acc[mb][tb], q);
+                    if (CPLX) *reinterpret_cast<f32x4 *>(&sti[tr * TP + row]) = sub4(acc[mb][NP + tb], q);
+                }
+        }
+        __syncthreads();
+        constexpr int NT = 64 * WM * WN;
+        constexpr int RG = BM / 4;                          // 4-row groups per trajectory
+        static_assert((TRAJ * RG) % NT == 0, "epilogue split");
+#pragma unroll 4
+        for (int u = 0; u < TRAJ * RG / NT; ++u) {
+            const int g = threadIdx.x + u * NT;
+            const int tr = g / RG, row = (g % RG) * 4;
+            const int r = r0 + tr;
+            const bool rvalid = r < a.R;
+            const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
+            const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
+            const bool bad = step_epilogue4<MODE, CPLX, OPT>(a, m0 + row, r, rvalid, cr, ci);
+            if (bad && rvalid) a.flags[r] = 1;
+        }
     } else {
+        // tiles too wide to stage: update straight from the accumulator layout
 #pragma unroll
         for (int tb = 0; tb < NP; ++tb) {
             const int r = r0 + tcol(tb) + l32;

@@ -261,3 +261,54 @@ def test_state_errors():
             gd.gd_run(S.h, 4, 1)   # batch mismatch
         st = S.stats()
         assert st.steps_done == 5 and st.batch == 3 and st.spin_updates == 16 * 3 * 5
+
+
+def test_degenerate_sizes_and_zero_steps():
+    """n = 1 (no coupling: Eq. (main) reduces to the single-mode logistic law
+    with the field), n = 2, R = 1, an all-zero J (coupling scale falls back to
+    1), and gd_run with 0 steps (state unchanged)."""
+    # n = 1 with a field: the oracle with the same inputs
+    J1 = np.zeros((1, 1), np.float32)
+    g1 = np.array([1.0], np.float32)
+    x0 = np.array([[0.05], [-0.02], [0.0]], np.float32)
+    with gd.Solver(J1, g1, dt=0.05, eps=0.1) as S:
+        S.set_init(3, x0)
+        assert S.scale == 1.0
+        S.run(0)
+        p, gm, step = S.state()
+        assert step == 0 and np.array_equal(p, x0) and np.all(gm == 0.0)
+        S.run(300)
+        p, gm, _ = S.state()
+        E, best = S.energy()
+    op, og = O.run(J1, x0, model="ising", steps=300, dt=0.05, eps=0.1, g=g1, s=1.0)
+    assert np.abs(p - op).max() <= 1e-5 * np.abs(op).max()
+    assert np.abs(gm - og).max() <= 1e-5 * max(1.0, np.abs(og).max())
+    # E = g s with s = sign(x): the field pushes x negative
+    assert np.array_equal(E, g1[0] * np.where(op[:, 0] < 0, -1.0, 1.0))
+    # n = 2, R = 1: antiferromagnetic pair, ground state anti-aligned, E = -2 J12 s1 s2 = -2
+    J2 = np.array([[0, -1], [-1, 0]], np.float32)
+    with gd.Solver(J2, dt=0.05) as S:
+        S.set_init(1, np.array([[0.05, 0.03]], np.float32))
+        S.run(2000)
+        sp = S.spins()
+        E, _ = S.energy()
+    assert sp[0, 0] == -sp[0, 1] and E[0] == -2.0
+    # all-zero couplings, XY, RK4: every amplitude follows its own logistic law
+    Z = np.zeros((70, 70), np.float32)
+    psi = I.psi0_complex(70, 5, 9)
+    with gd.Solver(Z, model=gd.GD_XY, integrator=gd.GD_RK4, dt=0.02) as S:
+        S.set_init(5, psi)
+        S.run(100)
+        p, gm, _ = S.state()
+    op, og = O.run(Z, psi, model="xy", steps=100, dt=0.02, eps=0.1, s=1.0, integrator=O.RK4)
+    assert np.abs(p - op).max() <= 1e-5 * np.abs(op).max()
+
+
+def test_n8192_sampled_parity():
+    """The largest dense size in the tests: N = 8192 (J 256 MiB FP32), R = 256,
+    Euler, dense +-1 couplings, sampled trajectories over 20 steps (the tile
+    choice is the one the autotuner makes for this shape)."""
+    n, R = 8192, 256
+    J = I.dense_pm1(n, 8192)
+    psi0 = I.psi0_real(n, R, 8192)
+    _parity_run(J, psi0, "ising", gd.GD_EULER, 0.05, R_sub=[0, 255], steps_list=(1, 10, 20))
