@@ -3,6 +3,8 @@
 // reductions and the FP64 re-scoring of Eq. (h).
 #include "gd_internal.h"
 
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -109,10 +111,10 @@ __global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ 
                              float *__restrict__ angle, int32_t *__restrict__ states,
                              int *__restrict__ flags, int n, int R, int Np, int Rp, int P,
                              long long ps) {
-    const long long total = (long long)Rp * Np;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-         t += (long long)gridDim.x * blockDim.x) {
-        const int r = int(t / Np), i = int(t % Np);
+    // 2-D grid: trajectories along y, spins along x (no 64-bit division)
+    for (int r = blockIdx.y; r < Rp; r += gridDim.y)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += gridDim.x * blockDim.x) {
+        const long long t = (long long)r * Np + i;
         const bool in = (r < R) && (i < n);
         float d0 = 0.0f, d1 = 0.0f, th = 0.0f;
         if (in) {
@@ -149,17 +151,24 @@ __global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ 
     }
 }
 
-// E[r] = sum over row tiles in fixed order; then argmin with ties -> lowest r.
-__global__ void energy_reduce_k(const double *__restrict__ partial, int ntiles, int Rp, int R,
-                                double *__restrict__ E, int *__restrict__ best) {
+// E[r] = sum over row tiles in fixed order (one thread per trajectory).
+__global__ void energy_sum_k(const double *__restrict__ partial, int ntiles, int Rp, int R,
+                             double *__restrict__ E) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double s = 0.0;
+    for (int t = 0; t < ntiles; ++t) s += partial[(long long)t * Rp + r];
+    E[r] = s;
+}
+
+// best = argmin_r E[r], ties -> lowest r (one workgroup).
+__global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__restrict__ best) {
     __shared__ double sv[256];
     __shared__ int si[256];
     double bv = __builtin_inf();
     int bi = 0x7fffffff;
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
-        double s = 0.0;
-        for (int t = 0; t < ntiles; ++t) s += partial[(long long)t * Rp + r];
-        E[r] = s;
+        const double s = E[r];
         if (s < bv || (s == bv && r < bi)) { bv = s; bi = r; }
     }
     sv[threadIdx.x] = bv;
@@ -301,7 +310,8 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
                              int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
                              int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st) {
     if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
-    discretise_k<<<grid_for((long long)Rp * Np), 256, 0, st>>>(psi, D, shadowD, op, readout, q, spins8,
+    const dim3 grid(unsigned(std::min(64, (Np + 255) / 256)), unsigned(std::min(Rp, 65535)));
+    discretise_k<<<grid, 256, 0, st>>>(psi, D, shadowD, op, readout, q, spins8,
                                                               angle, states, flags, n, R, Np, Rp,
                                                               nplanes, plane_stride);
     return hipGetLastError();
@@ -309,7 +319,9 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
 
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
                                 int *best, hipStream_t st) {
-    energy_reduce_k<<<1, 256, 0, st>>>(partial, ntiles, Rp, R, E, best);
+    if (R < 1) return hipErrorInvalidValue;
+    energy_sum_k<<<(R + 255) / 256, 256, 0, st>>>(partial, ntiles, Rp, R, E);
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best);
     return hipGetLastError();
 }
 
