@@ -113,19 +113,26 @@ def cpu_baseline(wl, J, psi0, target_s):
     threads = min(16, os.cpu_count() or 1)
     integ = O.RK4 if wl["integrator"] == "rk4" else O.EULER
     n = wl["n"]
-    R_s = min(wl["R"], threads * 2)
-    steps = 2
+    # small instances: all trajectories (the sample is then the workload itself,
+    # run for as many steps as fill the time budget)
+    R_s = wl["R"] if n * wl["R"] <= 65536 else min(wl["R"], threads * 2)
+    steps = 20
     # pilot, then size the sample to ~target_s
     t0 = time.perf_counter()
     O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
           integrator=integ, nthreads=threads)
     pilot = time.perf_counter() - t0
     steps = max(1, int(target_s * steps / max(pilot, 1e-6)))
-    steps = min(steps, wl["steps"])
-    t0 = time.perf_counter()
-    O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
-          integrator=integ, nthreads=threads)
-    el = time.perf_counter() - t0
+    cap = 100 * wl["steps"]
+    steps = min(steps, cap)
+    for _ in range(3):          # the pilot includes start-up costs: re-size once or twice
+        t0 = time.perf_counter()
+        O.run(J, psi0[:R_s], model=wl["model"], steps=steps, dt=wl["dt"], eps=0.1,
+              integrator=integ, nthreads=threads)
+        el = time.perf_counter() - t0
+        if el >= 0.5 * target_s or steps >= cap:
+            break
+        steps = min(cap, int(steps * target_s / max(el, 1e-6)))
     return {"value": n * R_s * steps / el, "unit": "spin-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{R_s} of {wl['R']} trajectories x {steps} steps, {el:.1f} s"}
@@ -183,18 +190,29 @@ def bench_batch(args, wl, steps):
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         threads = min(16, os.cpu_count() or 1)
-        # sample: the first 16 instances, 16 trajectories each, a few hundred steps
-        t0 = time.perf_counter()
-        done = 0
-        nsteps = 100
+        # sample: the first 16 instances, 16 trajectories each, as many steps as
+        # fill the time budget (a 20-step pilot sizes it)
+        mats = []
         for k in range(16):
             n = int(sizes[k])
             e, w, _ = I.regular3_maxcut(n, 1000 + k)
-            J = I.edges_to_dense(n, e, w)
-            O.run(J, x0[:n * 16].reshape(16, n) if k == 0 else I.psi0_real(n, 16, 5000 + k),
-                  model="ising", steps=nsteps, dt=wl["dt"], eps=0.1, nthreads=threads)
-            done += n * 16 * nsteps
-        elc = time.perf_counter() - t0
+            mats.append((n, I.edges_to_dense(n, e, w), I.psi0_real(n, 16, 5000 + k)))
+
+        def sweep(nsteps):
+            t0 = time.perf_counter()
+            done = 0
+            for n, J, x in mats:
+                O.run(J, x, model="ising", steps=nsteps, dt=wl["dt"], eps=0.1, nthreads=threads)
+                done += n * 16 * nsteps
+            return done, time.perf_counter() - t0
+
+        _, pilot = sweep(20)
+        nsteps = max(20, min(20 * steps, int(args.cpu_seconds * 20 / max(pilot, 1e-6))))
+        for _ in range(3):
+            done, elc = sweep(nsteps)
+            if elc >= 0.5 * args.cpu_seconds or nsteps >= 20 * steps:
+                break
+            nsteps = min(20 * steps, int(nsteps * args.cpu_seconds / max(elc, 1e-6)))
         out["cpu_baseline"] = {"value": done / elc, "unit": "spin-updates/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"16 instances x 16 trajectories x {nsteps} steps "
