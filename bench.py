@@ -87,6 +87,8 @@ def parse():
                     help="only run a plain device copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--scaling", action="store_true",
                     help="steps and time to a stationary state vs N (XY, U[-10,10], paper regime)")
+    ap.add_argument("--gdmod-scaling", action="store_true",
+                    help="steps to a stationary state vs N, GD vs GD-mod (XY, U[-10,10], Euler)")
     ap.add_argument("--maxcut800", action="store_true",
                     help="N=800 G(n,0.06) max-cut stand-ins: cut quality and time, 100 runs each")
     return ap.parse_args()
@@ -469,6 +471,59 @@ def scaling(args):
                       "budget_steps": budget}), flush=True)
 
 
+def gdmod_scaling(args):
+    """Steps to a stationary state vs N for GD and GD-mod on the same problems
+    (the paper expects GD-mod's iteration count to grow more slowly with N,
+    Sec. 4).  XY, dense U[-10,10] couplings, explicit Euler dt = 0.02,
+    eps = 0.5, eps_hat = 0.5, Psi(0) = 0 with D = 1e-6, gamma_c = max_i
+    sum_j |J_ij| / s for both (GD-mod needs positive gains; the same loss keeps
+    the comparison fair), 32 runs per N, stationarity as in --scaling."""
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    torch.cuda.init()
+    R, check, budget = 32, 100, 60000
+    rows = []
+    for n in (100, 200, 400, 800, 1600):
+        J = I.dense_uniform(n, 9000 + n)
+        Jd = J.astype(np.float64)
+        s = float(np.sqrt((Jd**2).sum() / n))
+        gc = float(np.abs(Jd).sum(1).max() / s)
+        row = {"n": n, "runs": R, "gamma_c": gc}
+        for name, var in (("gd", gd.GD_VARIANT_GD), ("gdmod", gd.GD_VARIANT_MOD)):
+            with gd.Solver(J, model=gd.GD_XY, dt=0.02, eps=0.5, variant=var, eps_hat=0.5,
+                           gamma_c=gc, noise_D=1e-6, noise_seed=n, init_amp=0.0) as S:
+                S.set_init(R)
+                first = _stationary_steps(S, R, budget, check)
+                S.set_init(R)
+                S.run(20)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.run(500)
+                ms = (time.perf_counter() - t0) / 500 * 1e3
+                E, b = S.energy()
+            reached = first >= 0
+            med = float(np.median(np.where(reached, first, budget + 1)))
+            row[name] = {"reached": int(reached.sum()),
+                         "median_steps": med if med <= budget else None,
+                         "ms_per_step_batch": ms}
+        rows.append(row)
+        print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+
+    def slope(name):
+        pts = [(r["n"], r[name]["median_steps"]) for r in rows if r[name]["median_steps"]]
+        if len(pts) < 2:
+            return None
+        return float(np.polyfit(np.log([p[0] for p in pts]), np.log([p[1] for p in pts]), 1)[0])
+
+    print(json.dumps({"gdmod_scaling": "steps to a stationary state vs N, GD vs GD-mod (XY, U[-10,10], "
+                                       "Euler dt=0.02, eps=eps_hat=0.5)",
+                      "rows": rows, "fit_exponent_median_steps": {"gd": slope("gd"), "gdmod": slope("gdmod")},
+                      "budget_steps": budget}), flush=True)
+
+
 def maxcut800(args):
     """Max-cut stand-ins shaped like the paper's N = 800 benchmarks (Sec. 3):
     five G(800, 0.06) graphs with unit weights and five with +-1 weights, 100
@@ -546,6 +601,9 @@ def main():
         return
     if args.maxcut800:
         maxcut800(args)
+        return
+    if args.gdmod_scaling:
+        gdmod_scaling(args)
         return
     if args.compare_ttt:
         compare_ttt(args)
