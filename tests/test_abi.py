@@ -106,6 +106,9 @@ def test_host_validation_errors(lib):
     z = np.zeros((4, 4), np.float32)
     assert lib.gd_create(C.byref(h), 4, z.ctypes.data_as(C.c_void_p), None, 0, C.byref(bad)) == gd.GD_E_INVALID_ARG
     assert lib.gd_create(C.byref(h), 0, z.ctypes.data_as(C.c_void_p), None, 0, None) == gd.GD_E_INVALID_ARG
+    # size limits: 1 <= n <= 65536 (checked before J is read)
+    assert lib.gd_create(C.byref(h), 65537, z.ctypes.data_as(C.c_void_p), None, 0, None) == gd.GD_E_INVALID_ARG
+    assert lib.gd_create(C.byref(h), -3, z.ctypes.data_as(C.c_void_p), None, 0, None) == gd.GD_E_INVALID_ARG
     assert lib.gd_create(C.byref(h), 4, None, None, 0, None) == gd.GD_E_INVALID_ARG
     assert lib.gd_create(C.byref(h), 4, z.ctypes.data_as(C.c_void_p), None, 5, None) == gd.GD_E_INVALID_ARG
     # calls on a NULL handle fail cleanly

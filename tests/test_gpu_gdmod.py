@@ -110,3 +110,24 @@ def test_gdmod_set_state_resets_couplings_and_rejects_bad_calls():
         S.run(1, batch=2)
         with pytest.raises(gd.GDError):
             S.mod_couplings(0)
+
+
+def test_gdmod_full_size_sampled():
+    """GD-mod at the benchmark's size: XY N = 1024, R = 256, Euler dt = 0.02,
+    eps_hat = 0.2 (the timed launch configuration), 200 steps, trajectories
+    0, 131 and 255 against the oracle (Psi, gamma and K)."""
+    n, R = 1024, 256
+    J = I.dense_gaussian(n, 1)
+    psi0 = I.psi0_complex(n, R, 1)
+    gc = _gamma_c(J)
+    sub = [0, 131, 255]
+    with gd.Solver(J, model=gd.GD_XY, dt=0.02, eps=0.1, variant=gd.GD_VARIANT_MOD, eps_hat=0.2,
+                   gamma_c=gc) as S:
+        S.set_init(R, psi0)
+        S.run(200)
+        p, gm, _ = S.state()
+        Kg = np.stack([S.mod_couplings(r) for r in sub])
+    op, og, oK = O.run_mod(J, psi0[sub], model="xy", steps=200, dt=0.02, eps=0.1, eps_hat=0.2,
+                           gamma_c=gc, s=float(np.sqrt((J.astype(np.float64) ** 2).sum() / n)))
+    assert _rel(p[sub], op).max() <= TOL and _rel(gm[sub], og).max() <= TOL
+    assert _rel(Kg, oK).max() <= TOL

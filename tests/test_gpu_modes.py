@@ -278,3 +278,31 @@ def test_resonant_model_argument_checks():
         S.run(1, batch=4)
         with pytest.raises(gd.GDError):
             S.spins(gd.GD_SPINS_STATE_I32)
+
+
+def test_noise_xy1024_full_size_sampled():
+    """The benchmark's XY shape (N = 1024, R = 1024, RK4 dt = 0.02) in the paper
+    regime (Psi(0) = 0, D = 0.01, gain from below), trajectories 0, 500 and
+    1023 against the oracle at steps 1, 50 and 200."""
+    n, R = 1024, 1024
+    J = I.dense_gaussian(n, 1)
+    s = np.sqrt((J.astype(np.float64) ** 2).sum() / n)
+    gc = _below(J, s, 0.1)
+    sub = [0, 500, 1023]
+    with gd.Solver(J, model=gd.GD_XY, integrator=gd.GD_RK4, dt=0.02, gamma_c=gc, noise_D=0.01,
+                   noise_seed=12, init_amp=0.0) as S:
+        S.set_init(R)
+        prev = 0
+        op = np.zeros((len(sub), n, 2))
+        og = np.zeros((len(sub), n))
+        for st in (1, 50, 200):
+            S.run(st - prev)
+            p, gm, _ = S.state()
+            # trajectories are keyed by their global index r: run them one by one
+            for k, r in enumerate(sub):
+                a, b = O.run(J, op[k:k + 1], og[k:k + 1], model="xy", steps=st - prev, dt=0.02,
+                             integrator=O.RK4, s=S.scale, gamma_c=gc, noise_D=0.01, noise_seed=12,
+                             t0=prev, r0=r)
+                op[k], og[k] = a[0], b[0]
+            prev = st
+            assert _rel(p[sub], op).max() <= TOL and _rel(gm[sub], og).max() <= TOL, st
