@@ -65,13 +65,10 @@ __device__ inline void clock_planes(int k, int q, double &d0, double &d1) {
     case 2: d0 = k ? -1.0 : 1.0; d1 = 0.0; return;
     case 3: d0 = k ? -0.5 : 1.0; d1 = k == 0 ? 0.0 : (k == 1 ? 1.0 : -1.0); return;
     case 4: d0 = k == 0 ? 1.0 : (k == 2 ? -1.0 : 0.0); d1 = k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); return;
-    case 6: {
-        const double c6[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
-        const double s6[6] = {0.0, 1.0, 1.0, 0.0, -1.0, -1.0};
-        d0 = c6[k];
-        d1 = s6[k];
+    case 6:   // cos: 1, 1/2, -1/2, -1, -1/2, 1/2; sin / (sqrt(3)/2): 0, 1, 1, 0, -1, -1
+        d0 = k == 0 ? 1.0 : (k == 3 ? -1.0 : ((k == 1 || k == 5) ? 0.5 : -0.5));
+        d1 = (k == 0 || k == 3) ? 0.0 : (k < 3 ? 1.0 : -1.0);
         return;
-    }
     default: sincospi(2.0 * k / q, &d1, &d0); return;
     }
 }
@@ -106,26 +103,37 @@ __device__ inline void readout_planes(double x, double y, int ro, int q, double 
 }
 
 // Readout onto the spin domains of Eq. (h).
-__global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ D, void *shadowD,
-                             int op, int ro, int q, int8_t *__restrict__ spins8,
-                             float *__restrict__ angle, int32_t *__restrict__ states,
-                             int *__restrict__ flags, int n, int R, int Np, int Rp, int P,
-                             long long ps) {
-    // 2-D grid: trajectories along y, spins along x (no 64-bit division)
+__global__ void __launch_bounds__(256)
+discretise_k(const float *__restrict__ psi, float *__restrict__ D, void *shadowD,
+             int op, int ro, int q, int8_t *__restrict__ spins8,
+             float *__restrict__ angle, int32_t *__restrict__ states,
+             int *__restrict__ flags, int n, int R, int Np, int Rp, int P,
+             long long ps) {
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    // 2-D grid: trajectories along y, groups of 4 consecutive spins along x
+    // (Np is a multiple of 4: 16-byte plane loads and stores)
+    const int nq = Np / 4;
     for (int r = blockIdx.y; r < Rp; r += gridDim.y)
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += gridDim.x * blockDim.x) {
-        const long long t = (long long)r * Np + i;
-        const bool in = (r < R) && (i < n);
-        float d0 = 0.0f, d1 = 0.0f, th = 0.0f;
-        if (in) {
-            const float x = psi[t];
-            const float y = P == 2 ? psi[ps + t] : 0.0f;
+    for (int iq = blockIdx.x * blockDim.x + threadIdx.x; iq < nq; iq += gridDim.x * blockDim.x) {
+        const int i0 = iq * 4;
+        const long long t = (long long)r * Np + i0;
+        const f32x4 xv = *reinterpret_cast<const f32x4 *>(psi + t);
+        const f32x4 yv = P == 2 ? *reinterpret_cast<const f32x4 *>(psi + ps + t) : f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 d0v = {0.f, 0.f, 0.f, 0.f}, d1v = {0.f, 0.f, 0.f, 0.f};
+        bool nan = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + e;
+            if (r >= R || i >= n) continue;
+            const float x = xv[e], y = yv[e];
             double e0, e1;
             int k;
             readout_planes(x, y, ro, q, e0, e1, k);
-            d0 = float(e0);
-            d1 = float(e1);
+            d0v[e] = float(e0);
+            d1v[e] = float(e1);
+            float th;
             if (ro == RO_PHASOR) {
+                th = 0.0f;
                 if (!(x == 0.0f && y == 0.0f)) {
                     th = atan2f(y, x);
                     if (th < 0.0f) th += 6.28318530717958647692f;
@@ -140,13 +148,17 @@ __global__ void discretise_k(const float *__restrict__ psi, float *__restrict__ 
             if (spins8) spins8[o] = k ? int8_t(-1) : int8_t(1);
             if (angle) angle[o] = th;
             if (states) states[o] = k;
-            if (__builtin_isnan(x) || __builtin_isnan(y)) flags[r] = 1;
+            nan |= __builtin_isnan(x) || __builtin_isnan(y);
         }
-        D[t] = d0;
-        if (P == 2) D[ps + t] = d1;
+        if (nan) flags[r] = 1;
+        *reinterpret_cast<f32x4 *>(D + t) = d0v;
+        if (P == 2) *reinterpret_cast<f32x4 *>(D + ps + t) = d1v;
         if (shadowD) {
-            store_shadow(shadowD, t, d0, op);
-            if (P == 2) store_shadow(shadowD, ps + t, d1, op);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                store_shadow(shadowD, t + e, d0v[e], op);
+                if (P == 2) store_shadow(shadowD, ps + t + e, d1v[e], op);
+            }
         }
     }
 }
@@ -310,7 +322,8 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
                              int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
                              int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st) {
     if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
-    const dim3 grid(unsigned(std::min(64, (Np + 255) / 256)), unsigned(std::min(Rp, 65535)));
+    if (Np % 4) return hipErrorInvalidValue;
+    const dim3 grid(unsigned(std::min(64, (Np / 4 + 255) / 256)), unsigned(std::min(Rp, 65535)));
     discretise_k<<<grid, 256, 0, st>>>(psi, D, shadowD, op, readout, q, spins8,
                                                               angle, states, flags, n, R, Np, Rp,
                                                               nplanes, plane_stride);

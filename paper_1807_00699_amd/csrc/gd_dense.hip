@@ -37,6 +37,7 @@
 #include "gd_epilogue.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace gd {
 
@@ -350,6 +351,312 @@ dense_step_f32(DenseStepArgs a) {
     }
 }
 
+// Direct-to-LDS variant (BK = 32 or 64): chunk tiles are copied from global
+// memory straight into LDS by global_load_lds_dwordx4 (each wave instruction
+// fills 1 KiB: 8 rows of 32 floats or 4 rows of 64), with no register staging
+// and no LDS store instructions; a wave only waits for its copies at the end
+// of the chunk, before the barrier.  Rows are unpadded; the 16-byte slot s of
+// row w is stored at slot s ^ ((w >> 1) & 7) (BK = 32) or s ^ (w & 15)
+// (BK = 64), which spreads the 16-byte operand reads of 16 consecutive rows
+// over all 64 banks.  The state update always uses the LDS-staged sums.
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+template <int BK>
+__device__ inline int dl_swz(int row) { return BK == 32 ? (row >> 1) & 7 : row & 15; }
+
+// s_waitcnt immediate: wait until at most n vector-memory operations of this
+// wave are outstanding and all its LDS operations have completed (expcnt left
+// at its maximum)
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
+
+// State operands the pointwise update reads per (trajectory, 4 rows) group:
+// Psi (re, im), gamma, and for RK stages 2..4 also the stage base y and the
+// slope accumulator.
+template <int MODE, bool CPLX>
+constexpr int epi_fields() {
+    if constexpr (MODE == MODE_ENERGY) return 0;
+    constexpr int per = CPLX ? 3 : 2;
+    return (MODE == MODE_RK2 || MODE == MODE_RK3 || MODE == MODE_RK4) ? 3 * per : per;
+}
+
+// f(integral_constant<P>) for each P of the sequence, in order
+template <typename F, int... P>
+__device__ inline void seq_apply(F &&f, std::integer_sequence<int, P...>) {
+    (f(std::integral_constant<int, P>{}), ...);
+}
+
+template <bool CPLX>
+__device__ inline const float *epi_field_ptr(const DenseStepArgs &a, int f) {
+    constexpr int per = CPLX ? 3 : 2;
+    const float *base[3][2] = {{a.psi_in, a.gam_in}, {a.y_psi, a.y_gam}, {a.acc_psi, a.acc_gam}};
+    const int blk = f / per, k = f % per;
+    if (CPLX && k == 1) return base[blk][0] + a.plane_stride;
+    return base[blk][k == 0 ? 0 : 1];
+}
+
+// PF > 0: the state operands of the update are loaded into registers during
+// the last K chunks, PF wave loads per chunk, each issued after that chunk's
+// copies.  A wave waits for a chunk's copies with vmcnt(PF): vector-memory
+// loads complete in issue order, so the operand loads issued since stay in
+// flight and each one has a chunk's matrix work to land in; spreading them
+// keeps the HBM burst of all workgroups (which run in step) small.
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int MODE, int PF>
+__global__ void __launch_bounds__(64 * WM * WN)
+dense_step_f32_dl(DenseStepArgs a) {
+    static_assert(BK == 32 || BK == 64, "chunk width");
+    constexpr int SPR = BK / 4;                        // 16-byte slots per row
+    constexpr int NT = 64 * WM * WN;
+    constexpr int NW = WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int MB = TM / 16, NB = TN / 16;
+    constexpr int NP = CPLX ? NB / 2 : NB;
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    static_assert(!CPLX || (NB % 2 == 0), "complex waves pair re/im blocks");
+    constexpr int TILE = (BM + BN) * BK;               // floats per buffer
+    constexpr int NI = TILE / 256;                     // 1 KiB copies per chunk
+    static_assert(NI % NW == 0 && BM % 8 == 0, "copy split");
+    __shared__ __attribute__((aligned(1024))) float lds[2][TILE];
+    // state-update groups (trajectory, 4 rows) of each thread
+    constexpr int RG = BM / 4;
+    static_assert((TRAJ * RG) % NT == 0, "epilogue split");
+    constexpr int NU = TRAJ * RG / NT;
+    constexpr int NF = PF > 0 ? epi_fields<MODE, CPLX>() : 0;
+    constexpr int NPF = NU * NF;                       // operand loads per wave
+    constexpr int TAIL = PF > 0 ? (NPF + PF - 1) / PF : 0;   // chunks that carry them
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int n_mt = a.Np / BM, n_ct = a.Rp / TRAJ;
+    int mt, ct;
+    tile_map(blockIdx.x, gridDim.x, n_mt, n_ct, mt, ct);
+    const int m0 = mt * BM, r0 = ct * TRAJ;
+    const long long Np = a.Np;
+    const float *J = static_cast<const float *>(a.J);
+    const float *Bop = static_cast<const float *>(a.B);
+
+    // this lane's source row offsets for its copies (fixed across chunks)
+    const float *src[NI / NW];
+#pragma unroll
+    for (int u = 0; u < NI / NW; ++u) {
+        const int j = wave + u * NW;                   // copy index: 64 / SPR rows
+        const int row = j * (64 / SPR) + lane / SPR;
+        const int ls = (lane % SPR) ^ dl_swz<BK>(row);  // logical slot stored in this lane's slot
+        if (row < BM) {
+            src[u] = J + (m0 + row) * Np + ls * 4;
+        } else {
+            const int col = row - BM;
+            const int plane = CPLX ? col / (BN / 2) : 0;
+            const int tr = CPLX ? col % (BN / 2) : col;
+            src[u] = Bop + plane * a.plane_stride + (r0 + tr) * Np + ls * 4;
+        }
+    }
+    auto copy_chunk = [&](int k0, int buf) {
+#pragma unroll
+        for (int u = 0; u < NI / NW; ++u) {
+            const int j = wave + u * NW;
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(src[u] + k0), (lvoid_t *)&lds[buf][j * 256], 16, 0, 0);
+        }
+    };
+    auto bcol = [&](int nb) -> int {
+        if (CPLX) {
+            const int p = nb / NP, tb = nb % NP;
+            return p * (BN / 2) + wn * (TN / 2) + tb * 16;
+        }
+        return wn * TN + nb * 16;
+    };
+    auto tcol = [&](int tb) -> int { return CPLX ? wn * (TN / 2) + tb * 16 : wn * TN + tb * 16; };
+    // element offset of state-update group u of this thread
+    auto grp_idx = [&](int u) -> long long {
+        const int g = tid + u * NT;
+        return (long long)(r0 + g / RG) * Np + m0 + (g % RG) * 4;
+    };
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 pf[NPF > 0 ? NPF : 1];
+
+    const int nk = a.Np / BK;
+    const int l16 = lane & 15, lq = lane >> 4;
+    // one K chunk; P >= 0 issues operand loads P*PF .. P*PF+PF-1
+    auto chunk = [&](int kc, auto pslot) {
+        constexpr int P = decltype(pslot)::value;
+        const int buf = kc & 1;
+        // the buffer refilled here was last read before the previous barrier
+        if (kc + 1 < nk) copy_chunk((kc + 1) * BK, buf ^ 1);
+        constexpr int NL = P < 0 ? 0 : (NPF - P * PF < PF ? NPF - P * PF : PF);
+        if constexpr (NL > 0) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const int q = P * PF + l;              // constant after unrolling
+                pf[q] = *reinterpret_cast<const f32x4 *>(epi_field_ptr<CPLX>(a, q % NF) + grp_idx(q / NF));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        f32x4 av[2][MB], bv[2][NB];
+        auto lread = [&](int kk, int set) {
+            const int s = kk * 4 + lq;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int row = wm * TM + mb * 16 + l16;
+                av[set][mb] = *reinterpret_cast<const f32x4 *>(&lds[buf][row * BK + (s ^ dl_swz<BK>(row)) * 4]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int row = BM + bcol(nb) + l16;
+                bv[set][nb] = *reinterpret_cast<const f32x4 *>(&lds[buf][row * BK + (s ^ dl_swz<BK>(row)) * 4]);
+            }
+        };
+        lread(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            const int set = kk & 1;
+            if (kk + 1 < BK / 16) lread(kk + 1, set ^ 1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[set][mb][t], bv[set][nb][t],
+                                                                          acc[mb][nb], 0, 0, 0);
+        }
+        // this wave's copies of the next chunk have landed (operand loads
+        // issued after them may still be in flight) and its LDS reads of this
+        // chunk are done; then a plain workgroup barrier, with compiler-only
+        // fences around it (a release fence would also wait for the operand
+        // loads)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(NL));
+        __asm__ __volatile__("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        __asm__ __volatile__("" ::: "memory");
+    };
+    copy_chunk(0, 0);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    __syncthreads();
+    int kc = 0;
+    for (; kc < nk - TAIL; ++kc) chunk(kc, std::integral_constant<int, -1>{});
+    if constexpr (TAIL > 0) {
+        // the launcher guarantees nk >= TAIL
+        seq_apply([&](auto p) { chunk(kc + decltype(p)::value, p); }, std::make_integer_sequence<int, TAIL>{});
+    }
+
+    if constexpr (MODE == MODE_ENERGY) {
+        double esum[NP];
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int r = r0 + tcol(tb) + l16;
+            double s = 0.0;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 16 + 4 * lq, r, acc[mb][tb],
+                                         CPLX ? acc[mb][NP + tb] : acc[mb][tb]);
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            esum[tb] = s;
+        }
+        double *red = reinterpret_cast<double *>(&lds[0][0]);
+        if (lq == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) red[(wm * WN + wn) * (NP * 16) + tb * 16 + l16] = esum[tb];
+        }
+        __syncthreads();
+        if (wm == 0 && lq == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) {
+                double s = 0.0;
+                for (int w = 0; w < WM; ++w) s += red[(w * WN + wn) * (NP * 16) + tb * 16 + l16];
+                a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l16] = s;
+            }
+        }
+    } else {
+        constexpr int TP = BM + 4;
+        static_assert((CPLX ? 2 : 1) * TRAJ * TP <= 2 * TILE, "staging fits LDS");
+        float *st = &lds[0][0];
+        float *sti = st + TRAJ * TP;
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int tr = tcol(tb) + l16;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int row = wm * TM + mb * 16 + 4 * lq;
+                *reinterpret_cast<f32x4 *>(&st[tr * TP + row]) = acc[mb][tb];
+                if (CPLX) *reinterpret_cast<f32x4 *>(&sti[tr * TP + row]) = acc[mb][NP + tb];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int g = tid + u * NT;
+            const int tr = g / RG, row = (g % RG) * 4;
+            const int r = r0 + tr;
+            const bool rvalid = r < a.R;
+            const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
+            const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
+            bool bad;
+            if constexpr (NPF > 0) {
+                EpiIn in;
+                in.ep = *reinterpret_cast<const f32x4 *>(a.eps + m0 + row);
+                in.hh = *reinterpret_cast<const f32x4 *>(a.h1 + m0 + row);
+                const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                const f32x4 *q = &pf[u * NF];
+                constexpr int per = CPLX ? 3 : 2;
+                in.xr = q[0];
+                in.xi = CPLX ? q[1] : z;
+                in.gm = q[per - 1];
+                if constexpr (NF > per) {
+                    in.yr = q[per];
+                    in.yi = CPLX ? q[per + 1] : z;
+                    in.yg = q[2 * per - 1];
+                    in.ar = q[2 * per];
+                    in.ai = CPLX ? q[2 * per + 1] : z;
+                    in.ag = q[3 * per - 1];
+                }
+                bad = epi_apply<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, in, cr, ci);
+            } else {
+                bad = step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, cr, ci);
+            }
+            if (bad && rvalid) a.flags[r] = 1;
+        }
+    }
+}
+
+// chunks of the operand-load tail of the direct-to-LDS kernel in this mode
+template <bool CPLX, int PF>
+inline int dl_tail_chunks(int mode, int nu) {
+    if (PF == 0 || mode == MODE_ENERGY) return 0;
+    const int per = CPLX ? 3 : 2;
+    const int nf = (mode == MODE_RK2 || mode == MODE_RK3 || mode == MODE_RK4) ? 3 * per : per;
+    return (nu * nf + PF - 1) / PF;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int PF>
+hipError_t launch_modes_dl(int mode, const DenseStepArgs &a, hipStream_t st) {
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    if (a.Np % BM || a.Np % BK || a.Rp % TRAJ) return hipErrorInvalidValue;
+    if (a.Np / BK < dl_tail_chunks<CPLX, PF>(mode, TRAJ * (BM / 4) / (64 * WM * WN))) return hipErrorInvalidValue;
+    const int nblk = (a.Np / BM) * (a.Rp / TRAJ);
+    const dim3 grid(nblk), block(64 * WM * WN);
+#define GD_LAUNCH(M) dense_step_f32_dl<BM, BN, BK, WM, WN, CPLX, M, PF><<<grid, block, 0, st>>>(a)
+    switch (mode) {
+    case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
+    case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
+    case MODE_RK2: GD_LAUNCH(MODE_RK2); break;
+    case MODE_RK3: GD_LAUNCH(MODE_RK3); break;
+    case MODE_RK4: GD_LAUNCH(MODE_RK4); break;
+    case MODE_ENERGY: GD_LAUNCH(MODE_ENERGY); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef GD_LAUNCH
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int KS, int LA>
 hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
@@ -371,23 +678,29 @@ hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
 }
 
 // Variants {BM, BN (GEMM columns), BK, WM, WN, KS (K groups), LA (load
-// lookahead in chunks)}; identical for real and complex amplitudes (complex
-// tiles hold BN/2 trajectories).  The runtime times the variants that tile a
-// problem and keeps the fastest.
-#define GD_DENSE_VARIANTS(X)            \
-    X(0, 64, 64, 32, 2, 2, 1, 1)        \
-    X(1, 64, 128, 32, 2, 2, 1, 1)       \
-    X(2, 128, 128, 32, 2, 2, 1, 1)      \
-    X(3, 32, 64, 32, 1, 2, 1, 1)        \
-    X(4, 64, 64, 64, 2, 2, 1, 1)        \
-    X(5, 64, 128, 64, 2, 2, 1, 1)       \
-    X(6, 128, 64, 32, 4, 1, 1, 1)       \
-    X(7, 64, 64, 32, 2, 2, 2, 1)        \
-    X(8, 64, 64, 32, 2, 2, 1, 2)        \
-    X(9, 128, 128, 32, 2, 2, 1, 2)
+// lookahead in chunks), DL (0: chunks staged through registers; else
+// direct-to-LDS copies with DL - 1 state-operand loads per tail chunk)}; identical for real and
+// complex amplitudes (complex tiles hold BN/2 trajectories).  The runtime
+// times the variants that tile a problem and keeps the fastest.
+#define GD_DENSE_VARIANTS(X)               \
+    X(0, 64, 64, 32, 2, 2, 1, 1, 0)        \
+    X(1, 64, 128, 32, 2, 2, 1, 1, 0)       \
+    X(2, 128, 128, 32, 2, 2, 1, 1, 0)      \
+    X(3, 32, 64, 32, 1, 2, 1, 1, 0)        \
+    X(4, 64, 64, 64, 2, 2, 1, 1, 0)        \
+    X(5, 64, 128, 64, 2, 2, 1, 1, 0)       \
+    X(6, 128, 64, 32, 4, 1, 1, 1, 0)       \
+    X(7, 64, 64, 32, 2, 2, 2, 1, 0)        \
+    X(8, 64, 64, 32, 2, 2, 1, 2, 0)        \
+    X(9, 128, 128, 32, 2, 2, 1, 2, 0)      \
+    X(10, 64, 64, 32, 2, 2, 1, 1, 1)       \
+    X(11, 64, 128, 32, 2, 2, 1, 1, 1)      \
+    X(12, 64, 64, 32, 2, 2, 1, 1, 2)       \
+    X(13, 64, 64, 32, 2, 2, 1, 1, 3)       \
+    X(14, 64, 64, 64, 2, 2, 1, 1, 3)
 
-constexpr int kCfg[][7] = {
-#define GD_ROW(id, bm, bn, bk, wm, wn, ks, la) {bm, bn, bk, wm, wn, ks, la},
+constexpr int kCfg[][8] = {
+#define GD_ROW(id, bm, bn, bk, wm, wn, ks, la, dl) {bm, bn, bk, wm, wn, ks, la, dl},
     GD_DENSE_VARIANTS(GD_ROW)
 #undef GD_ROW
 };
@@ -405,23 +718,35 @@ DenseConfig dense_config(bool complex_mode, int idx) {
     c.wn = kCfg[idx][4];
     c.traj_tile = complex_mode ? c.bn / 2 : c.bn;
     c.threads = 64 * kCfg[idx][3] * kCfg[idx][4] * kCfg[idx][5];
+    // direct-to-LDS variants with operand loads need as many K chunks as the
+    // longest load tail (RK stages) has chunks
+    const int pf = kCfg[idx][7] - 1;
+    if (pf > 0) {
+        const int nu = c.traj_tile * (c.bm / 4) / c.threads;
+        const int nf = 3 * (complex_mode ? 3 : 2);
+        c.min_np = c.bk * ((nu * nf + pf - 1) / pf);
+    }
     return c;
 }
 
 hipError_t launch_dense_step(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                              const DenseStepArgs &a, hipStream_t st) {
     if (op != OP_F32) return hipErrorInvalidValue;
-#define GD_CASE(id, bm, bn, bk, wm, wn, ks, la)                                          \
+#define GD_CASE(id, bm, bn, bk, wm, wn, ks, la, dl)                                      \
     case id:                                                                             \
-        return complex_mode ? launch_modes<bm, bn, bk, wm, wn, true, ks, la>(mode, a, st) \
-                            : launch_modes<bm, bn, bk, wm, wn, false, ks, la>(mode, a, st);
+        if constexpr (dl > 0)                                                            \
+            return complex_mode ? launch_modes_dl<bm, bn, bk, wm, wn, true, dl - 1>(mode, a, st) \
+                                : launch_modes_dl<bm, bn, bk, wm, wn, false, dl - 1>(mode, a, st); \
+        else                                                                             \
+            return complex_mode ? launch_modes<bm, bn, bk, wm, wn, true, ks, la>(mode, a, st) \
+                                : launch_modes<bm, bn, bk, wm, wn, false, ks, la>(mode, a, st);
     switch (cfg.id) { GD_DENSE_VARIANTS(GD_CASE) }
 #undef GD_CASE
     return hipErrorInvalidValue;
 }
 
 bool dense_config_fits(const DenseConfig &c, int Np, int Rp) {
-    return Np % c.bm == 0 && Np % c.bk == 0 && Rp % c.traj_tile == 0;
+    return Np % c.bm == 0 && Np % c.bk == 0 && Rp % c.traj_tile == 0 && Np >= c.min_np;
 }
 
 }  // namespace gd

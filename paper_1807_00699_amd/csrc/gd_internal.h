@@ -69,6 +69,7 @@ struct DenseConfig {
     int wn;        // waves along the column dimension
     int traj_tile; // trajectories per workgroup
     int threads;
+    int min_np = 0; // smallest padded size the variant runs
 };
 
 int dense_config_count(bool complex_mode);

@@ -115,6 +115,52 @@ def test_xy1024_full_size_sampled_parity():
     _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=sub, steps_list=(1, 50, 200))
 
 
+# every FP32 coupling-kernel variant of the runtime's table (tile shapes, K
+# groups, load lookahead, direct-to-LDS copies with and without the spread
+# state-operand loads); N = 1000 pads to 1024 so each of them tiles it and the
+# direct-to-LDS load tails fit
+FP32_VARIANTS = range(15)
+
+
+@pytest.mark.parametrize("model,integrator,dt", [("xy", gd.GD_RK4, 0.02), ("ising", gd.GD_EULER, 0.05)])
+def test_every_fp32_variant_parity_n1000(monkeypatch, model, integrator, dt):
+    """Each variant forced in turn: Psi and gamma after 1 and 30 steps within
+    the bar of the FP64 oracle (same floor rule as above), and the FP32 device
+    energies of the readout within 2e-5 of the oracle's FP64 energies of the
+    same spins."""
+    n, R, steps = 1000, 100, (1, 30)
+    cx = model == "xy"
+    J = I.dense_gaussian(n, 7) if cx else I.dense_pm1(n, 7)
+    psi0 = I.psi0_complex(n, R, 7) if cx else I.psi0_real(n, R, 7)
+    s = O.coupling_scale(J.astype(np.float64))
+    ref = []
+    op, og = psi0.astype(np.float64), np.zeros((R, n))
+    fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
+    prev = 0
+    for st in steps:
+        op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
+        fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
+        prev = st
+        ref.append((op, og, np.maximum(TOL, 4 * np.maximum(_rel(fp, op), _rel(fg, og)))))
+    mdl = gd.GD_XY if cx else gd.GD_ISING
+    for cid in FP32_VARIANTS:
+        monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))
+        with gd.Solver(J, model=mdl, integrator=integrator, dt=dt, eps=0.1) as S:
+            S.set_init(R, psi0)
+            prev = 0
+            for st, (op, og, bound) in zip(steps, ref):
+                S.run(st - prev)
+                prev = st
+                p, gm, _ = S.state()
+                ep, eg = _rel(p, op), _rel(gm, og)
+                assert np.all(ep <= bound) and np.all(eg <= bound), (cid, st, ep.max(), eg.max())
+                assert np.mean((ep <= TOL) & (eg <= TOL)) >= 0.9, (cid, st)
+            Ed, _ = S.energy(device_path=True)
+            sp = S.spins()
+        Eo = O.energy_xy(J, sp) if cx else O.energy_ising(J, sp).astype(np.float64)
+        assert np.allclose(Ed, Eo, rtol=2e-5, atol=1e-3), (cid, np.abs(Ed - Eo).max())
+
+
 def test_xy3000_dense_uniform_sampled_parity():
     """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
     U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
