@@ -370,31 +370,6 @@ __device__ inline int dl_swz(int row) { return BK == 32 ? (row >> 1) & 7 : row &
 // at its maximum)
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
 
-// State operands the pointwise update reads per (trajectory, 4 rows) group:
-// Psi (re, im), gamma, and for RK stages 2..4 also the stage base y and the
-// slope accumulator.
-template <int MODE, bool CPLX>
-constexpr int epi_fields() {
-    if constexpr (MODE == MODE_ENERGY) return 0;
-    constexpr int per = CPLX ? 3 : 2;
-    return (MODE == MODE_RK2 || MODE == MODE_RK3 || MODE == MODE_RK4) ? 3 * per : per;
-}
-
-// f(integral_constant<P>) for each P of the sequence, in order
-template <typename F, int... P>
-__device__ inline void seq_apply(F &&f, std::integer_sequence<int, P...>) {
-    (f(std::integral_constant<int, P>{}), ...);
-}
-
-template <bool CPLX>
-__device__ inline const float *epi_field_ptr(const DenseStepArgs &a, int f) {
-    constexpr int per = CPLX ? 3 : 2;
-    const float *base[3][2] = {{a.psi_in, a.gam_in}, {a.y_psi, a.y_gam}, {a.acc_psi, a.acc_gam}};
-    const int blk = f / per, k = f % per;
-    if (CPLX && k == 1) return base[blk][0] + a.plane_stride;
-    return base[blk][k == 0 ? 0 : 1];
-}
-
 // PF > 0: the state operands of the update are loaded into registers during
 // the last K chunks, PF wave loads per chunk, each issued after that chunk's
 // copies.  A wave waits for a chunk's copies with vmcnt(PF): vector-memory
@@ -602,22 +577,7 @@ dense_step_f32_dl(DenseStepArgs a) {
             bool bad;
             if constexpr (NPF > 0) {
                 EpiIn in;
-                in.ep = *reinterpret_cast<const f32x4 *>(a.eps + m0 + row);
-                in.hh = *reinterpret_cast<const f32x4 *>(a.h1 + m0 + row);
-                const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 *q = &pf[u * NF];
-                constexpr int per = CPLX ? 3 : 2;
-                in.xr = q[0];
-                in.xi = CPLX ? q[1] : z;
-                in.gm = q[per - 1];
-                if constexpr (NF > per) {
-                    in.yr = q[per];
-                    in.yi = CPLX ? q[per + 1] : z;
-                    in.yg = q[2 * per - 1];
-                    in.ar = q[2 * per];
-                    in.ai = CPLX ? q[2 * per + 1] : z;
-                    in.ag = q[3 * per - 1];
-                }
+                epi_fill<MODE, CPLX>(a, m0 + row, &pf[u * NF], in);
                 bad = epi_apply<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, in, cr, ci);
             } else {
                 bad = step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, cr, ci);

@@ -16,6 +16,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <utility>
+
 namespace gd {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -86,6 +88,52 @@ __device__ inline void epi_load(const DenseStepArgs &a, int i0, int r, EpiIn &in
         in.ar = *reinterpret_cast<const f32x4 *>(a.acc_psi + idx);
         in.ai = CPLX ? *reinterpret_cast<const f32x4 *>(a.acc_psi + ps + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
         in.ag = *reinterpret_cast<const f32x4 *>(a.acc_gam + idx);
+    }
+}
+
+// State operands the pointwise update reads per (trajectory, 4 rows) group:
+// Psi (re, im), gamma, and for RK stages 2..4 also the stage base y and the
+// slope accumulator.
+template <int MODE, bool CPLX>
+constexpr int epi_fields() {
+    if constexpr (MODE == MODE_ENERGY) return 0;
+    constexpr int per = CPLX ? 3 : 2;
+    return (MODE == MODE_RK2 || MODE == MODE_RK3 || MODE == MODE_RK4) ? 3 * per : per;
+}
+
+// f(integral_constant<P>) for each P of the sequence, in order
+template <typename F, int... P>
+__device__ inline void seq_apply(F &&f, std::integer_sequence<int, P...>) {
+    (f(std::integral_constant<int, P>{}), ...);
+}
+
+template <bool CPLX>
+__device__ inline const float *epi_field_ptr(const DenseStepArgs &a, int f) {
+    constexpr int per = CPLX ? 3 : 2;
+    const float *base[3][2] = {{a.psi_in, a.gam_in}, {a.y_psi, a.y_gam}, {a.acc_psi, a.acc_gam}};
+    const int blk = f / per, k = f % per;
+    if (CPLX && k == 1) return base[blk][0] + a.plane_stride;
+    return base[blk][k == 0 ? 0 : 1];
+}
+
+// EpiIn of one group from its state fields q[0 .. epi_fields) loaded ahead
+// (in epi_field_ptr order) and the per-row eps and h1 loaded here
+template <int MODE, bool CPLX>
+__device__ inline void epi_fill(const DenseStepArgs &a, int i0, const f32x4 *q, EpiIn &in) {
+    constexpr int per = CPLX ? 3 : 2;
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    in.ep = *reinterpret_cast<const f32x4 *>(a.eps + i0);
+    in.hh = *reinterpret_cast<const f32x4 *>(a.h1 + i0);
+    in.xr = q[0];
+    in.xi = CPLX ? q[1] : z;
+    in.gm = q[per - 1];
+    if constexpr (epi_fields<MODE, CPLX>() > per) {
+        in.yr = q[per];
+        in.yi = CPLX ? q[per + 1] : z;
+        in.yg = q[2 * per - 1];
+        in.ar = q[2 * per];
+        in.ai = CPLX ? q[2 * per + 1] : z;
+        in.ag = q[3 * per - 1];
     }
 }
 

@@ -103,6 +103,25 @@ def test_one_step_bound_complex_rk4():
     _one_step_check(J, p, gam, gd.GD_PREC_BF16, model="xy", dt=0.02, integrator=gd.GD_RK4)
 
 
+# every reduced-precision variant of the runtime's table (tile shapes, BK),
+# each forced in turn
+LP_VARIANTS = range(4)
+
+
+def test_every_lowprec_variant_one_step_bound(monkeypatch):
+    n, R = 1024, 256
+    J = I.sparse_pm1(n, 11)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1.2, 1.2, (R, n)).astype(np.float32)
+    gam = rng.uniform(-0.5, 1.5, (R, n)).astype(np.float32)
+    p = rng.uniform(-1, 1, (R, n, 2)).astype(np.float32)
+    sub = [0, 1, 130, 255]
+    for cid in LP_VARIANTS:
+        monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))
+        _one_step_check(J, x, gam, gd.GD_PREC_BF16, sub=sub)
+        _one_step_check(J, p, gam, gd.GD_PREC_FP16, model="xy", sub=sub, dt=0.02, integrator=gd.GD_RK4)
+
+
 def test_ising4096_full_size_sampled():
     """N = 4096 density-0.5 {-1,0,+1} couplings, R = 4096, BF16 operand with
     FP8-stored J, in the launch configuration of the benchmark: the one-step
