@@ -201,72 +201,90 @@ __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__rest
 }
 
 // FP64 re-score of Eq. (h) for the discretised state, formed in FP64 from
-// the FP32 amplitudes by the readout of the model.  Workgroup (row tile t of
-// 64 spins, column tile of 64 trajectories): T = J d over K through LDS in
-// FP64, then partial[t][r] = sum_{i in tile} [ -(d0_i T0_i + w d1_i T1_i)
-// + g_i d0_i ] (w: weight of the second plane).
+// the FP32 amplitudes by the readout of the model.  The readout planes are
+// written once in FP64 ([P][Rp][Np], zero outside n x R); then per workgroup
+// (row tile t of 64 spins, column tile of 64 trajectories): T = J d over K
+// through LDS in FP64, and partial[t][r] = sum_{i in tile} [ -(d0_i T0_i +
+// w d1_i T1_i) + g_i d0_i ] (w: weight of the second plane).
 constexpr int E64_T = 64;
 constexpr int E64_K = 16;
 
-__device__ inline void planes_at(const float *psi, long long ps, int P, int ro, int q, long long idx,
-                                 bool in, double &dr, double &di) {
-    dr = 0.0;
-    di = 0.0;
-    if (!in) return;
-    int k;
-    readout_planes(psi[idx], P == 2 ? psi[ps + idx] : 0.0f, ro, q, dr, di, k);
+__global__ void __launch_bounds__(256)
+planes64_k(const float *__restrict__ psi, double *__restrict__ D64, int n, int R, int Np, int Rp, int P,
+           long long ps, int ro, int q) {
+    for (int r = blockIdx.y; r < Rp; r += gridDim.y)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += gridDim.x * blockDim.x) {
+            const long long t = (long long)r * Np + i;
+            double d0 = 0.0, d1 = 0.0;
+            if (r < R && i < n) {
+                int k;
+                readout_planes(psi[t], P == 2 ? psi[ps + t] : 0.0f, ro, q, d0, d1, k);
+            }
+            D64[t] = d0;
+            if (P == 2) D64[ps + t] = d1;
+        }
 }
 
+template <int P>
 __global__ void __launch_bounds__(256)
-energy_fp64_k(const float *__restrict__ J, const float *__restrict__ psi, const float *__restrict__ g,
-              double *__restrict__ partial, int Np, int Rp, int n, int R, int P, long long ps, int ro,
-              int q, double w) {
+energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const float *__restrict__ g,
+              double *__restrict__ partial, int Np, int Rp, long long ps, double w) {
     __shared__ double sJ[E64_K][E64_T + 1];
-    __shared__ double sDr[E64_K][E64_T + 1];
-    __shared__ double sDi[E64_K][E64_T + 1];
+    __shared__ double sD[P][E64_K][E64_T + 1];
     __shared__ double red[16][E64_T];
     const int mt = blockIdx.x, ct = blockIdx.y;
     const int i0 = mt * E64_T, r0 = ct * E64_T;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 4x4 outputs per thread
-    double ar[4][4], ai[4][4];
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) ar[a][b] = ai[a][b] = 0.0;
+    double acc[P][4][4];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[p][a][b] = 0.0;
     for (int k0 = 0; k0 < Np; k0 += E64_K) {
-        for (int e = threadIdx.x; e < E64_K * E64_T; e += 256) {
+        // 64 rows x 16 k of J and of each plane: 4 elements per thread
+#pragma unroll
+        for (int u = 0; u < E64_K * E64_T / 256; ++u) {
+            const int e = threadIdx.x + u * 256;
             const int row = e / E64_K, kk = e % E64_K;
             sJ[kk][row] = (double)J[(long long)(i0 + row) * Np + k0 + kk];
-            const int r = r0 + row, j = k0 + kk;
-            double dr, di;
-            planes_at(psi, ps, P, ro, q, (long long)r * Np + j, r < R && j < n, dr, di);
-            sDr[kk][row] = dr;
-            sDi[kk][row] = di;
+#pragma unroll
+            for (int p = 0; p < P; ++p) sD[p][kk][row] = D64[p * ps + (long long)(r0 + row) * Np + k0 + kk];
         }
         __syncthreads();
+#pragma unroll 4
         for (int kk = 0; kk < E64_K; ++kk) {
-            double av[4], br[4], bi[4];
+            double av[4], bv[P][4];
+#pragma unroll
             for (int a = 0; a < 4; ++a) av[a] = sJ[kk][ty * 4 + a];
-            for (int b = 0; b < 4; ++b) {
-                br[b] = sDr[kk][tx * 4 + b];
-                bi[b] = sDi[kk][tx * 4 + b];
-            }
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) {
-                    ar[a][b] = fma(av[a], br[b], ar[a][b]);
-                    ai[a][b] = fma(av[a], bi[b], ai[a][b]);
-                }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bv[p][b] = sD[p][kk][tx * 4 + b];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[p][a][b] = fma(av[a], bv[p][b], acc[p][a][b]);
         }
         __syncthreads();
     }
     double colsum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int i = i0 + ty * 4 + a;
+#pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int r = r0 + tx * 4 + b;
-            double dr, di;
-            planes_at(psi, ps, P, ro, q, (long long)r * Np + i, r < R && i < n, dr, di);
-            colsum[b] += -(dr * ar[a][b] + w * (di * ai[a][b])) + (double)g[i] * dr;
+            const long long t = (long long)(r0 + tx * 4 + b) * Np + i;
+            const double d0 = D64[t];
+            double s = d0 * acc[0][a][b];
+            if (P == 2) s += w * (D64[ps + t] * acc[P - 1][a][b]);
+            colsum[b] += -s + (double)g[i] * d0;
         }
     }
+#pragma unroll
     for (int b = 0; b < 4; ++b) red[ty][tx * 4 + b] = colsum[b];
     __syncthreads();
     if (threadIdx.x < E64_T) {
@@ -338,15 +356,20 @@ hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R
     return hipGetLastError();
 }
 
-hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *partial,
-                              int Np, int Rp, int n, int R, int nplanes, long long plane_stride,
-                              int readout, int q, hipStream_t st) {
+hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *D64,
+                              double *partial, int Np, int Rp, int n, int R, int nplanes,
+                              long long plane_stride, int readout, int q, hipStream_t st) {
     if (Np % E64_T || Rp % E64_T) return hipErrorInvalidValue;
     if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
+    if (nplanes != 1 && nplanes != 2) return hipErrorInvalidValue;
     const double w = readout == RO_CLOCK ? (double)clock_im_weight(q) : 1.0;
-    dim3 grid(Np / E64_T, Rp / E64_T);
-    energy_fp64_k<<<grid, 256, 0, st>>>(J, psi, g, partial, Np, Rp, n, R, nplanes, plane_stride,
-                                        readout, q, w);
+    const dim3 pgrid(unsigned(std::min(64, (Np + 255) / 256)), unsigned(std::min(Rp, 65535)));
+    planes64_k<<<pgrid, 256, 0, st>>>(psi, D64, n, R, Np, Rp, nplanes, plane_stride, readout, q);
+    const dim3 grid(Np / E64_T, Rp / E64_T);
+    if (nplanes == 2)
+        energy_fp64_k<2><<<grid, 256, 0, st>>>(J, D64, g, partial, Np, Rp, plane_stride, w);
+    else
+        energy_fp64_k<1><<<grid, 256, 0, st>>>(J, D64, g, partial, Np, Rp, plane_stride, w);
     return hipGetLastError();
 }
 

@@ -288,6 +288,276 @@ dense_step_lp(DenseStepArgs a) {
     }
 }
 
+// Direct-to-LDS variant (BK = 64).  Both chunk tiles are copied from global
+// memory into LDS by global_load_lds_dwordx4 (1 KiB per wave instruction,
+// rows unpadded), so J stays FP8 in LDS (64-byte rows) and is widened after
+// the LDS read: half the LDS bytes of a 16-bit J for its copy and its reads.
+// The K order inside each 32-wide block is permuted identically for both
+// operands so that one 16-byte LDS read of FP8 J feeds two MFMA K slices:
+// lane half h, slice s of the pair, element e takes logical k = 16h + 8s + e.
+// 16-byte slots are XOR-swizzled by row (slot ^ ((row >> 2) & 3) for 64-byte
+// rows, slot ^ ((row >> 1) & 7) for 128-byte rows), so 16 consecutive rows
+// read at one slot hit all 64 banks.  The state update stages the sums of one
+// wave column at a time through LDS.
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+template <int ROWB>
+__device__ inline int lp_swz(int row) { return ROWB == 64 ? (row >> 2) & 3 : (row >> 1) & 7; }
+
+// 8 FP8 (E4M3) values in two dwords -> 8 16-bit operands (exact)
+template <int OPT>
+__device__ inline u32x4 widen_fp8x8(unsigned int w0, unsigned int w1) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    u32x4 r;
+    if constexpr (OPT == OP_BF16) {
+        r[0] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, false));
+        r[1] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, true));
+        r[2] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, false));
+        r[3] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, true));
+    } else {
+        r[0] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w0, 1.0f, false));
+        r[1] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w0, 1.0f, true));
+        r[2] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w1, 1.0f, false));
+        r[3] = __builtin_bit_cast(unsigned int, __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w1, 1.0f, true));
+    }
+    return r;
+}
+
+template <int BM, int BN, int WM, int WN, bool CPLX, int MODE, int OPT, bool JFP8, int LDSMIN>
+__global__ void __launch_bounds__(64 * WM * WN)
+dense_step_lp_dl(DenseStepArgs a) {
+    constexpr int BK = 64;
+    constexpr int NT = 64 * WM * WN, NW = WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int MB = TM / 32, NB = TN / 32;
+    constexpr int NP = CPLX ? NB / 2 : NB;
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    static_assert(!CPLX || (NB % 2 == 0), "complex waves pair re/im blocks");
+    constexpr int RA = JFP8 ? BK : 2 * BK;            // bytes per A (J) row in LDS
+    constexpr int RB = 2 * BK;                        // bytes per B (Psi) row
+    constexpr int ABYTES = BM * RA, TILEB = ABYTES + BN * RB;
+    constexpr int NIA = ABYTES / 1024, NI = TILEB / 1024;   // 1 KiB copies per chunk
+    static_assert(NI % NW == 0 && ABYTES % 1024 == 0, "copy split");
+    constexpr int NCW = NI / NW;
+    // staged state update: one wave column (TRAJ / WN trajectories) per pass
+    constexpr int TP = BM + 4;
+    constexpr int TRP = TRAJ / WN;
+    constexpr int STB = (CPLX ? 2 : 1) * TRP * TP * 4;
+    constexpr int LDSB0 = 2 * TILEB > STB ? 2 * TILEB : STB;
+    constexpr int LDSB = LDSB0 > LDSMIN ? LDSB0 : LDSMIN;
+    __shared__ __attribute__((aligned(1024))) unsigned char lds[LDSB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int n_mt = a.Np / BM, n_ct = a.Rp / TRAJ;
+    int mt, ct;
+    tile_map_lp(blockIdx.x, gridDim.x, n_mt, n_ct, mt, ct);
+    const int m0 = mt * BM, r0 = ct * TRAJ;
+    const long long Np = a.Np;
+    const unsigned char *Jb = static_cast<const unsigned char *>(a.J);
+    const unsigned char *Bb = static_cast<const unsigned char *>(a.B);
+
+    // this lane's source of each of its copies (fixed across chunks, + k0 bytes)
+    const unsigned char *src[NCW];
+    int kscale[NCW];                                   // bytes per k of that source
+#pragma unroll
+    for (int u = 0; u < NCW; ++u) {
+        const int j = wave + u * NW;                   // copy index
+        if (j < NIA) {
+            constexpr int LPR = RA / 16;               // lanes per row
+            const int row = j * (64 / LPR) + lane / LPR;
+            const int ls = (lane % LPR) ^ lp_swz<RA>(row);
+            src[u] = Jb + ((m0 + row) * Np) * (JFP8 ? 1 : 2) + ls * 16;
+            kscale[u] = JFP8 ? 1 : 2;
+        } else {
+            const int row = (j - NIA) * 8 + lane / 8;  // B row = GEMM column
+            const int ls = (lane % 8) ^ lp_swz<RB>(row);
+            const int plane = CPLX ? row / (BN / 2) : 0;
+            const int tr = CPLX ? row % (BN / 2) : row;
+            src[u] = Bb + (plane * a.plane_stride + (long long)(r0 + tr) * Np) * 2 + ls * 16;
+            kscale[u] = 2;
+        }
+    }
+    auto copy_chunk = [&](int k0, int buf) {
+#pragma unroll
+        for (int u = 0; u < NCW; ++u) {
+            const int j = wave + u * NW;
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(src[u] + (long long)k0 * kscale[u]),
+                                             (lvoid_t *)&lds[buf * TILEB + j * 1024], 16, 0, 0);
+        }
+    };
+    auto bcol = [&](int nb) -> int {
+        if (CPLX) {
+            const int p = nb / NP, tb = nb % NP;
+            return p * (BN / 2) + wn * (TN / 2) + tb * 32;
+        }
+        return wn * TN + nb * 32;
+    };
+    auto tcol = [&](int tb) -> int { return CPLX ? wn * (TN / 2) + tb * 32 : wn * TN + tb * 32; };
+
+    f32x16 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
+
+    const int nk = a.Np / BK;
+    const int l32 = lane & 31, lh = lane >> 5;
+    copy_chunk(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) copy_chunk((kc + 1) * BK, buf ^ 1);
+        const unsigned char *At = &lds[buf * TILEB];
+        const unsigned char *Bt = At + ABYTES;
+        // operands of K-slice pair m (two 16-wide slices): A [MB][2], B [NB][2]
+        u32x4 av[2][MB][2], bv[2][NB][2];
+        auto lread = [&](int m, int set) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int row = wm * TM + mb * 32 + l32;
+                if constexpr (JFP8) {
+                    const int slot = (2 * m + lh) ^ lp_swz<RA>(row);
+                    const u32x4 w = *reinterpret_cast<const u32x4 *>(At + row * RA + slot * 16);
+                    av[set][mb][0] = widen_fp8x8<OPT>(w[0], w[1]);
+                    av[set][mb][1] = widen_fp8x8<OPT>(w[2], w[3]);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int slot = (4 * m + 2 * lh + s) ^ lp_swz<RA>(row);
+                        av[set][mb][s] = *reinterpret_cast<const u32x4 *>(At + row * RA + slot * 16);
+                    }
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int row = bcol(nb) + l32;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int slot = (4 * m + 2 * lh + s) ^ lp_swz<RB>(row);
+                    bv[set][nb][s] = *reinterpret_cast<const u32x4 *>(Bt + row * RB + slot * 16);
+                }
+            }
+        };
+        lread(0, 0);
+#pragma unroll
+        for (int m = 0; m < BK / 32; ++m) {
+            const int set = m & 1;
+            if (m + 1 < BK / 32) lread(m + 1, set ^ 1);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[mb][nb] = mfma32<OPT>(av[set][mb][s], bv[set][nb][s], acc[mb][nb]);
+        }
+        // this wave's copies of the next chunk have landed; then the workgroup
+        // barrier (all copies landed, all reads of this chunk done)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    // acc[mb][nb][4q + e]: row i = m0 + wm*TM + mb*32 + 8q + 4*lh + e, column l32 of block nb
+    auto sub4 = [](const f32x16 &v, int q) -> f32x4 {
+        return f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+    };
+    if constexpr (MODE == MODE_ENERGY) {
+        double esum[NP];
+#pragma unroll
+        for (int tb = 0; tb < NP; ++tb) {
+            const int r = r0 + tcol(tb) + l32;
+            double s = 0.0;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    s += energy_terms4<CPLX>(a, m0 + wm * TM + mb * 32 + 8 * q + 4 * lh, r,
+                                             sub4(acc[mb][tb], q),
+                                             CPLX ? sub4(acc[mb][NP + tb], q) : sub4(acc[mb][tb], q));
+            s += __shfl_xor(s, 32);
+            esum[tb] = s;
+        }
+        double *red = reinterpret_cast<double *>(&lds[0]);
+        if (lh == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) red[(wm * WN + wn) * (NP * 32) + tb * 32 + l32] = esum[tb];
+        }
+        __syncthreads();
+        if (wm == 0 && lh == 0) {
+#pragma unroll
+            for (int tb = 0; tb < NP; ++tb) {
+                double s = 0.0;
+                for (int w = 0; w < WM; ++w) s += red[(w * WN + wn) * (NP * 32) + tb * 32 + l32];
+                a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l32] = s;
+            }
+        }
+    } else {
+        // pass p: the waves of column p stage their sums as [trajectory][row]
+        // (TRP trajectories), then every thread updates 4-row groups of them
+        float *st = reinterpret_cast<float *>(&lds[0]);
+        float *sti = st + TRP * TP;
+        constexpr int RG = BM / 4;
+        static_assert((TRP * RG) % NT == 0, "epilogue split");
+#pragma unroll
+        for (int p = 0; p < WN; ++p) {
+            if (wn == p) {
+#pragma unroll
+                for (int tb = 0; tb < NP; ++tb) {
+                    const int tr = tcol(tb) - p * TRP + l32;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int row = wm * TM + mb * 32 + 8 * q + 4 * lh;
+                            *reinterpret_cast<f32x4 *>(&st[tr * TP + row]) = sub4(acc[mb][tb], q);
+                            if (CPLX)
+                                *reinterpret_cast<f32x4 *>(&sti[tr * TP + row]) = sub4(acc[mb][NP + tb], q);
+                        }
+                }
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int u = 0; u < TRP * RG / NT; ++u) {
+                const int g = tid + u * NT;
+                const int tr = g / RG, row = (g % RG) * 4;
+                const int r = r0 + p * TRP + tr;
+                const bool rvalid = r < a.R;
+                const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
+                const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
+                const bool bad = step_epilogue4<MODE, CPLX, OPT>(a, m0 + row, r, rvalid, cr, ci);
+                if (bad && rvalid) a.flags[r] = 1;
+            }
+            if (p + 1 < WN) __syncthreads();
+        }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, bool CPLX, int OPT, bool JFP8, int LDSMIN>
+hipError_t launch_lp_dl_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
+    constexpr int TRAJ = CPLX ? BN / 2 : BN;
+    if (a.Np % BM || a.Np % 64 || a.Rp % TRAJ) return hipErrorInvalidValue;
+    const dim3 grid((a.Np / BM) * (a.Rp / TRAJ)), block(64 * WM * WN);
+#define GD_LAUNCH(M) dense_step_lp_dl<BM, BN, WM, WN, CPLX, M, OPT, JFP8, LDSMIN><<<grid, block, 0, st>>>(a)
+    switch (mode) {
+    case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
+    case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
+    case MODE_RK2: GD_LAUNCH(MODE_RK2); break;
+    case MODE_RK3: GD_LAUNCH(MODE_RK3); break;
+    case MODE_RK4: GD_LAUNCH(MODE_RK4); break;
+    case MODE_ENERGY: GD_LAUNCH(MODE_ENERGY); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef GD_LAUNCH
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool CPLX, int OPT, bool JFP8>
 hipError_t launch_lp_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
@@ -307,10 +577,13 @@ hipError_t launch_lp_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, int DL>
 hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &a, hipStream_t st) {
-#define GD_SEL(C, O, F)                                                                    \
-    if (cx == C && op == O && jfp8 == F) return launch_lp_modes<BM, BN, BK, WM, WN, C, O, F>(mode, a, st);
+#define GD_SEL(C, O, F)                                                                              \
+    if (cx == C && op == O && jfp8 == F) {                                                           \
+        if constexpr (DL > 0) return launch_lp_dl_modes<BM, BN, WM, WN, C, O, F, (DL - 1) * 1024>(mode, a, st); \
+        else return launch_lp_modes<BM, BN, BK, WM, WN, C, O, F>(mode, a, st);                       \
+    }
     GD_SEL(false, OP_BF16, true) GD_SEL(false, OP_BF16, false)
     GD_SEL(false, OP_F16, true) GD_SEL(false, OP_F16, false)
     GD_SEL(true, OP_BF16, true) GD_SEL(true, OP_BF16, false)
@@ -319,15 +592,18 @@ hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &
     return hipErrorInvalidValue;
 }
 
-// Variants {BM, BN (GEMM columns), BK, WM, WN}
-#define GD_LP_VARIANTS(X)        \
-    X(0, 128, 128, 64, 2, 2)     \
-    X(1, 64, 128, 64, 2, 2)      \
-    X(2, 128, 256, 64, 2, 2)     \
-    X(3, 128, 128, 32, 2, 2)
+// Variants {BM, BN (GEMM columns), BK, WM, WN, DL (direct-to-LDS copies, J
+// kept FP8 in LDS)}
+#define GD_LP_VARIANTS(X)           \
+    X(0, 128, 128, 64, 2, 2, 0)     \
+    X(1, 64, 128, 64, 2, 2, 0)      \
+    X(2, 128, 256, 64, 2, 2, 0)     \
+    X(3, 128, 128, 32, 2, 2, 0)     \
+    X(4, 128, 128, 64, 2, 2, 1)     \
+    X(5, 128, 128, 64, 2, 2, 73)
 
-constexpr int kLpCfg[][5] = {
-#define GD_ROW(id, bm, bn, bk, wm, wn) {bm, bn, bk, wm, wn},
+constexpr int kLpCfg[][6] = {
+#define GD_ROW(id, bm, bn, bk, wm, wn, dl) {bm, bn, bk, wm, wn, dl},
     GD_LP_VARIANTS(GD_ROW)
 #undef GD_ROW
 };
@@ -351,8 +627,8 @@ DenseConfig dense_lp_config(bool complex_mode, int idx) {
 hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                                 bool j_fp8, const DenseStepArgs &a, hipStream_t st) {
     if (op != OP_BF16 && op != OP_F16) return hipErrorInvalidValue;
-#define GD_CASE(id, bm, bn, bk, wm, wn) \
-    case id: return launch_lp<bm, bn, bk, wm, wn>(complex_mode, op, j_fp8, mode, a, st);
+#define GD_CASE(id, bm, bn, bk, wm, wn, dl) \
+    case id: return launch_lp<bm, bn, bk, wm, wn, dl>(complex_mode, op, j_fp8, mode, a, st);
     switch (cfg.id) { GD_LP_VARIANTS(GD_CASE) }
 #undef GD_CASE
     return hipErrorInvalidValue;

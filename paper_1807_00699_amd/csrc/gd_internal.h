@@ -154,9 +154,10 @@ hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R
                                 int *best, hipStream_t st);
 // FP64 re-score from the FP32 amplitudes (unit phasors / signs formed in FP64):
 // partial[t][r] = sum_{i in tile t} [-Re(conj(d_i) (J d)_i) + g_i Re(d_i)]
-hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *partial,
-                              int Np, int Rp, int n, int R, int nplanes, long long plane_stride,
-                              int readout, int q, hipStream_t st);
+// D64: scratch for the FP64 readout planes, nplanes * Rp * Np doubles
+hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, double *D64,
+                              double *partial, int Np, int Rp, int n, int R, int nplanes,
+                              long long plane_stride, int readout, int q, hipStream_t st);
 // shadow copy of FP32 planes in BF16 / FP16
 hipError_t launch_make_shadow(const float *src, void *dst, long long count, int op, hipStream_t st);
 // any_flag: out[0] = number of r < R with flags[r] != 0

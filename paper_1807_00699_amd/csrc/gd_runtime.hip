@@ -132,6 +132,7 @@ struct gd_solver {
     float *gam = nullptr, *gam_s = nullptr, *acc_psi = nullptr, *acc_gam = nullptr;
     float *D = nullptr;
     float *K = nullptr;        // GD-mod couplings [R][Np][Np]
+    double *D64 = nullptr;     // FP64 readout planes of the re-score (allocated on first use)
     double *partial = nullptr, *dE = nullptr;
     int *flags = nullptr, *dBest = nullptr, *dCount = nullptr;
     int cur = 0;
@@ -160,6 +161,8 @@ void free_state(gd_solver *s) {
     for (void *&p : s->shadow) { if (p) (void)hipFree(p); p = nullptr; }
     if (s->shadowD) (void)hipFree(s->shadowD);
     s->shadowD = nullptr;
+    if (s->D64) (void)hipFree(s->D64);
+    s->D64 = nullptr;
     if (s->partial) (void)hipFree(s->partial);
     if (s->dE) (void)hipFree(s->dE);
     if (s->flags) (void)hipFree(s->flags);
@@ -917,7 +920,11 @@ static int energies(gd_solver *s, double *E, int32_t *best, bool fp64) {
     GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr, nullptr,
                              s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
     if (fp64) {
-        GD_HIP(launch_energy_fp64(s->dJ, cur, s->dG, s->partial, s->Np, s->Rp, s->n, s->R, s->P,
+        if (!s->D64) {
+            const int rc = dalloc(&s->D64, (size_t)s->plane() * s->P);
+            if (rc != GD_OK) return rc;
+        }
+        GD_HIP(launch_energy_fp64(s->dJ, cur, s->dG, s->D64, s->partial, s->Np, s->Rp, s->n, s->R, s->P,
                                   s->plane(), s->ro, s->prm.q, s->stream));
     } else {
         DenseStepArgs a = base_args(s);

@@ -105,13 +105,18 @@ def test_one_step_bound_complex_rk4():
 
 # every reduced-precision variant of the runtime's table (tile shapes, BK),
 # each forced in turn
-LP_VARIANTS = range(4)
+LP_VARIANTS = range(6)
 
 
 def test_every_lowprec_variant_one_step_bound(monkeypatch):
+    """{-1, 0, +1} couplings (BF16 Euler Ising, FP16 RK4 XY) and couplings
+    spread over many FP8 codes (both operand types), N = 1024, R = 256."""
     n, R = 1024, 256
     J = I.sparse_pm1(n, 11)
     rng = np.random.default_rng(11)
+    vals = np.array([-448, -3, -2, -1.5, -1, -0.5, -0.015625, 0, 0.015625, 0.25, 1, 1.75, 2, 6, 448],
+                    np.float32)
+    Jc = I.sym_from_upper(rng.choice(vals, (n, n)).astype(np.float64))
     x = rng.uniform(-1.2, 1.2, (R, n)).astype(np.float32)
     gam = rng.uniform(-0.5, 1.5, (R, n)).astype(np.float32)
     p = rng.uniform(-1, 1, (R, n, 2)).astype(np.float32)
@@ -120,6 +125,8 @@ def test_every_lowprec_variant_one_step_bound(monkeypatch):
         monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))
         _one_step_check(J, x, gam, gd.GD_PREC_BF16, sub=sub)
         _one_step_check(J, p, gam, gd.GD_PREC_FP16, model="xy", sub=sub, dt=0.02, integrator=gd.GD_RK4)
+        _one_step_check(Jc, x, gam, gd.GD_PREC_BF16, sub=sub)
+        _one_step_check(Jc, x, gam, gd.GD_PREC_FP16, sub=sub)
 
 
 def test_ising4096_full_size_sampled():
