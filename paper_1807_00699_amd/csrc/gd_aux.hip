@@ -225,73 +225,89 @@ planes64_k(const float *__restrict__ psi, double *__restrict__ D64, int n, int R
         }
 }
 
+// T = J d on the FP64 matrix cores (v_mfma_f64_16x16x4_f64): workgroup tile
+// 64 rows x 64 trajectories, 2 x 2 waves of 32 x 32 (2 x 2 blocks of 16 x 16),
+// K chunks of 16 staged in LDS as [row][k] doubles with a one-double pad (the
+// 8-byte operand reads of 16 rows at one k then hit distinct banks).  MFMA
+// operands: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k; result
+// D[l / 16 + 4 e][l % 16] in element e of lane l (rows interleaved, unlike
+// the FP32 16x16x4 layout).
 template <int P>
 __global__ void __launch_bounds__(256)
 energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const float *__restrict__ g,
               double *__restrict__ partial, int Np, int Rp, long long ps, double w) {
-    __shared__ double sJ[E64_K][E64_T + 1];
-    __shared__ double sD[P][E64_K][E64_T + 1];
-    __shared__ double red[16][E64_T];
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    constexpr int KP = E64_K + 1;
+    __shared__ double sJ[E64_T][KP];
+    __shared__ double sD[P][E64_T][KP];
+    __shared__ double red[2][E64_T];
     const int mt = blockIdx.x, ct = blockIdx.y;
     const int i0 = mt * E64_T, r0 = ct * E64_T;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 4x4 outputs per thread
-    double acc[P][4][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int l16 = lane & 15, lq = lane >> 4;
+    f64x4 acc[P][2][2];
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[p][a][b] = 0.0;
+            for (int nb = 0; nb < 2; ++nb) acc[p][mb][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < Np; k0 += E64_K) {
         // 64 rows x 16 k of J and of each plane: 4 elements per thread
 #pragma unroll
         for (int u = 0; u < E64_K * E64_T / 256; ++u) {
-            const int e = threadIdx.x + u * 256;
+            const int e = tid + u * 256;
             const int row = e / E64_K, kk = e % E64_K;
-            sJ[kk][row] = (double)J[(long long)(i0 + row) * Np + k0 + kk];
+            sJ[row][kk] = (double)J[(long long)(i0 + row) * Np + k0 + kk];
 #pragma unroll
-            for (int p = 0; p < P; ++p) sD[p][kk][row] = D64[p * ps + (long long)(r0 + row) * Np + k0 + kk];
+            for (int p = 0; p < P; ++p) sD[p][row][kk] = D64[p * ps + (long long)(r0 + row) * Np + k0 + kk];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < E64_K; ++kk) {
-            double av[4], bv[P][4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = sJ[kk][ty * 4 + a];
+        for (int k4 = 0; k4 < E64_K / 4; ++k4) {
+            const int k = 4 * k4 + lq;
+            double av[2], bv[P][2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) av[mb] = sJ[wm * 32 + mb * 16 + l16][k];
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bv[p][b] = sD[p][kk][tx * 4 + b];
+                for (int nb = 0; nb < 2; ++nb) bv[p][nb] = sD[p][wn * 32 + nb * 16 + l16][k];
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[p][a][b] = fma(av[a], bv[p][b], acc[p][a][b]);
+                    for (int nb = 0; nb < 2; ++nb)
+                        acc[p][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[p][nb], acc[p][mb][nb],
+                                                                             0, 0, 0);
         }
         __syncthreads();
     }
-    double colsum[4] = {0.0, 0.0, 0.0, 0.0};
+    // per trajectory column: sum over this wave's rows, then over the lanes
+    // that hold the same column, then over the two row waves
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ty * 4 + a;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const long long t = (long long)(r0 + tx * 4 + b) * Np + i;
-            const double d0 = D64[t];
-            double s = d0 * acc[0][a][b];
-            if (P == 2) s += w * (D64[ps + t] * acc[P - 1][a][b]);
-            colsum[b] += -s + (double)g[i] * d0;
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) red[ty][tx * 4 + b] = colsum[b];
-    __syncthreads();
-    if (threadIdx.x < E64_T) {
+    for (int nb = 0; nb < 2; ++nb) {
+        const int rl = wn * 32 + nb * 16 + l16;
+        const long long rb = (long long)(r0 + rl) * Np;
         double s = 0.0;
-        for (int y = 0; y < 16; ++y) s += red[y][threadIdx.x];
-        partial[(long long)mt * Rp + r0 + threadIdx.x] = s;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = i0 + wm * 32 + mb * 16 + lq + 4 * e;
+                const double d0 = D64[rb + i];
+                double t = d0 * acc[0][mb][nb][e];
+                if (P == 2) t += w * (D64[ps + rb + i] * acc[P - 1][mb][nb][e]);
+                s += -t + (double)g[i] * d0;
+            }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (lq == 0) red[wm][rl] = s;
     }
+    __syncthreads();
+    if (tid < E64_T) partial[(long long)mt * Rp + r0 + tid] = red[0][tid] + red[1][tid];
 }
 
 __global__ void make_shadow_k(const float *__restrict__ src, void *dst, long long count, int op) {

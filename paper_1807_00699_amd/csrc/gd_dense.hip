@@ -4,7 +4,8 @@
 // coupling sum C_ir = (1/s) sum_j J_ij Psi_jr of Eq. (main) as a GEMM on the
 // matrix cores (v_mfma_f32_16x16x4_f32, FP32 in and out), and then applies the
 // pointwise part of Eq. (main) and Eq. (gamma) in the epilogue, so that the
-// coupling result never leaves registers:
+// coupling result never goes to HBM (it stays in registers, or passes
+// through LDS to put consecutive lanes on consecutive spins):
 //   f   = Psi (gamma - gamma_c - |Psi|^2) + C + h_1
 //   phi = eps_i (rho_th - |Psi|^2)
 // followed by an Euler update or one stage of the classical RK4 scheme on
@@ -15,8 +16,10 @@
 // per-trajectory quantity is a plane [Rp][Np] (trajectory-major, spin index
 // contiguous).  The product is C[i][r] = sum_k J[i][k] Psi[r][k]: both
 // operands are K-contiguous, so global->LDS copies are plain 16-byte vector
-// loads and LDS holds both tiles as [row][k] with an 8-float pad per row
-// (conflict-free 16-byte LDS reads).
+// loads.  The register-staged variants hold both tiles in LDS as [row][k]
+// with an 8-float pad per row; the direct-to-LDS variants (further below)
+// copy chunks straight into unpadded, XOR-swizzled rows.  Both read 16 bytes
+// per lane without bank conflicts.
 //
 // Tiling: a workgroup owns BM rows x BN GEMM columns, WM x WN waves; a wave
 // owns (BM/WM) x (BN/WN) as 16x16 MFMA blocks.  Complex amplitudes use BN/2

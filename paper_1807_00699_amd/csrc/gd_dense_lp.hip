@@ -325,9 +325,21 @@ __device__ inline u32x4 widen_fp8x8(unsigned int w0, unsigned int w1) {
     return r;
 }
 
-template <int BM, int BN, int WM, int WN, bool CPLX, int MODE, int OPT, bool JFP8, int LDSMIN>
+// s_waitcnt immediate: at most n vector-memory operations of this wave
+// outstanding, all its LDS operations complete (expcnt at its maximum)
+constexpr int lp_vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
+
+// PFX = LDS floor (KiB) * 16 + PF.  PF > 0: the state operands of the first
+// update groups (at most 16 wave loads per thread, a register budget) are
+// loaded during the last K chunks, one per chunk after that chunk's copies;
+// a wave then waits for its copies with vmcnt(loads issued since), since
+// vector-memory loads complete in issue order, and meets the others at a
+// plain barrier, so each load has the chunk's matrix work to land in.
+template <int BM, int BN, int WM, int WN, bool CPLX, int MODE, int OPT, bool JFP8, int PFX>
 __global__ void __launch_bounds__(64 * WM * WN)
 dense_step_lp_dl(DenseStepArgs a) {
+    constexpr int PF = PFX & 15;
+    constexpr int LDSMIN = (PFX >> 4) * 1024;
     constexpr int BK = 64;
     constexpr int NT = 64 * WM * WN, NW = WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -407,12 +419,33 @@ dense_step_lp_dl(DenseStepArgs a) {
 
     const int nk = a.Np / BK;
     const int l32 = lane & 31, lh = lane >> 5;
+    // update groups: pass p (wave column), group u of the thread's groups
+    // in that pass; operands loaded ahead for the first NUP groups in
+    // (pass, group) order
+    constexpr int RG = BM / 4;
+    static_assert((TRP * RG) % NT == 0, "epilogue split");
+    constexpr int NUPP = TRP * RG / NT;               // groups per thread and pass
+    constexpr int NF = PF > 0 ? epi_fields<MODE, CPLX>() : 0;
+    constexpr int NUP = NF == 0 ? 0 : (16 / NF < WN * NUPP ? 16 / NF : WN * NUPP);
+    constexpr int NPF = NUP * NF;
+    f32x4 pf[NPF > 0 ? NPF : 1];
+    auto grp_idx = [&](int v) -> long long {          // v = pass * NUPP + u
+        const int p = v / NUPP, g = tid + (v % NUPP) * NT;
+        return (long long)(r0 + p * TRP + g / RG) * Np + m0 + (g % RG) * 4;
+    };
     copy_chunk(0, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
+    auto chunk = [&](int kc, auto pslot) {
+        constexpr int PS = decltype(pslot)::value;
         const int buf = kc & 1;
         if (kc + 1 < nk) copy_chunk((kc + 1) * BK, buf ^ 1);
+        constexpr int NL = PS < 0 ? 0 : 1;
+        if constexpr (NL > 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            pf[PS] = *reinterpret_cast<const f32x4 *>(epi_field_ptr<CPLX>(a, PS % NF) + grp_idx(PS / NF));
+            __builtin_amdgcn_sched_barrier(0);
+        }
         const unsigned char *At = &lds[buf * TILEB];
         const unsigned char *Bt = At + ABYTES;
         // operands of K-slice pair m (two 16-wide slices): A [MB][2], B [NB][2]
@@ -457,11 +490,23 @@ dense_step_lp_dl(DenseStepArgs a) {
                     for (int nb = 0; nb < NB; ++nb)
                         acc[mb][nb] = mfma32<OPT>(av[set][mb][s], bv[set][nb][s], acc[mb][nb]);
         }
-        // this wave's copies of the next chunk have landed; then the workgroup
-        // barrier (all copies landed, all reads of this chunk done)
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
+        // this wave's copies of the next chunk have landed (an operand load
+        // issued after them may still be in flight); then a plain workgroup
+        // barrier with compiler-only fences (a release fence would also wait
+        // for the operand load)
+        __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(NL));
+        if constexpr (PF > 0) {
+            __asm__ __volatile__("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            __asm__ __volatile__("" ::: "memory");
+        } else {
+            __syncthreads();
+        }
+    };
+    int kc = 0;
+    for (; kc < nk - NPF; ++kc) chunk(kc, std::integral_constant<int, -1>{});
+    if constexpr (NPF > 0)   // the launcher guarantees nk >= NPF
+        seq_apply([&](auto q) { chunk(kc + decltype(q)::value, q); }, std::make_integer_sequence<int, NPF>{});
 
     // ---------------------------------------------------------------- epilogue
     // acc[mb][nb][4q + e]: row i = m0 + wm*TM + mb*32 + 8q + 4*lh + e, column l32 of block nb
@@ -503,8 +548,6 @@ dense_step_lp_dl(DenseStepArgs a) {
         // (TRP trajectories), then every thread updates 4-row groups of them
         float *st = reinterpret_cast<float *>(&lds[0]);
         float *sti = st + TRP * TP;
-        constexpr int RG = BM / 4;
-        static_assert((TRP * RG) % NT == 0, "epilogue split");
 #pragma unroll
         for (int p = 0; p < WN; ++p) {
             if (wn == p) {
@@ -523,15 +566,23 @@ dense_step_lp_dl(DenseStepArgs a) {
                 }
             }
             __syncthreads();
-#pragma unroll 4
-            for (int u = 0; u < TRP * RG / NT; ++u) {
+#pragma unroll
+            for (int u = 0; u < NUPP; ++u) {
                 const int g = tid + u * NT;
                 const int tr = g / RG, row = (g % RG) * 4;
                 const int r = r0 + p * TRP + tr;
                 const bool rvalid = r < a.R;
                 const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
                 const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
-                const bool bad = step_epilogue4<MODE, CPLX, OPT>(a, m0 + row, r, rvalid, cr, ci);
+                const int v = p * NUPP + u;
+                bool bad;
+                if (v < NUP) {
+                    EpiIn in;
+                    epi_fill<MODE, CPLX>(a, m0 + row, &pf[(v < NUP ? v : 0) * NF], in);
+                    bad = epi_apply<MODE, CPLX, OPT>(a, m0 + row, r, rvalid, in, cr, ci);
+                } else {
+                    bad = step_epilogue4<MODE, CPLX, OPT>(a, m0 + row, r, rvalid, cr, ci);
+                }
                 if (bad && rvalid) a.flags[r] = 1;
             }
             if (p + 1 < WN) __syncthreads();
@@ -539,12 +590,14 @@ dense_step_lp_dl(DenseStepArgs a) {
     }
 }
 
-template <int BM, int BN, int WM, int WN, bool CPLX, int OPT, bool JFP8, int LDSMIN>
+template <int BM, int BN, int WM, int WN, bool CPLX, int OPT, bool JFP8, int PFX>
 hipError_t launch_lp_dl_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     constexpr int TRAJ = CPLX ? BN / 2 : BN;
     if (a.Np % BM || a.Np % 64 || a.Rp % TRAJ) return hipErrorInvalidValue;
+    // the operand-load tail needs at most 16 chunks
+    if ((PFX & 15) && a.Np / 64 < 16) return hipErrorInvalidValue;
     const dim3 grid((a.Np / BM) * (a.Rp / TRAJ)), block(64 * WM * WN);
-#define GD_LAUNCH(M) dense_step_lp_dl<BM, BN, WM, WN, CPLX, M, OPT, JFP8, LDSMIN><<<grid, block, 0, st>>>(a)
+#define GD_LAUNCH(M) dense_step_lp_dl<BM, BN, WM, WN, CPLX, M, OPT, JFP8, PFX><<<grid, block, 0, st>>>(a)
     switch (mode) {
     case MODE_EULER: GD_LAUNCH(MODE_EULER); break;
     case MODE_RK1: GD_LAUNCH(MODE_RK1); break;
@@ -581,7 +634,7 @@ template <int BM, int BN, int BK, int WM, int WN, int DL>
 hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &a, hipStream_t st) {
 #define GD_SEL(C, O, F)                                                                              \
     if (cx == C && op == O && jfp8 == F) {                                                           \
-        if constexpr (DL > 0) return launch_lp_dl_modes<BM, BN, WM, WN, C, O, F, (DL - 1) * 1024>(mode, a, st); \
+        if constexpr (DL > 0) return launch_lp_dl_modes<BM, BN, WM, WN, C, O, F, DL - 1>(mode, a, st);     \
         else return launch_lp_modes<BM, BN, BK, WM, WN, C, O, F>(mode, a, st);                       \
     }
     GD_SEL(false, OP_BF16, true) GD_SEL(false, OP_BF16, false)
@@ -592,15 +645,17 @@ hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &
     return hipErrorInvalidValue;
 }
 
-// Variants {BM, BN (GEMM columns), BK, WM, WN, DL (direct-to-LDS copies, J
-// kept FP8 in LDS)}
+// Variants {BM, BN (GEMM columns), BK, WM, WN, DL (0: register-staged; else
+// direct-to-LDS copies with J kept FP8 in LDS, DL - 1 = LDS floor in KiB * 16
+// + state-operand loads per tail chunk)}
 #define GD_LP_VARIANTS(X)           \
     X(0, 128, 128, 64, 2, 2, 0)     \
     X(1, 64, 128, 64, 2, 2, 0)      \
     X(2, 128, 256, 64, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)     \
     X(4, 128, 128, 64, 2, 2, 1)     \
-    X(5, 128, 128, 64, 2, 2, 73)
+    X(5, 128, 128, 64, 2, 2, 1153)  \
+    X(6, 128, 128, 64, 2, 2, 1154)
 
 constexpr int kLpCfg[][6] = {
 #define GD_ROW(id, bm, bn, bk, wm, wn, dl) {bm, bn, bk, wm, wn, dl},
@@ -621,6 +676,7 @@ DenseConfig dense_lp_config(bool complex_mode, int idx) {
     c.wn = kLpCfg[idx][4];
     c.traj_tile = complex_mode ? c.bn / 2 : c.bn;
     c.threads = 64 * kLpCfg[idx][3] * kLpCfg[idx][4];
+    if (kLpCfg[idx][5] > 0 && ((kLpCfg[idx][5] - 1) & 15)) c.min_np = 16 * 64;   // operand-load tail
     return c;
 }
 

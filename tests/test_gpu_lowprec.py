@@ -105,7 +105,7 @@ def test_one_step_bound_complex_rk4():
 
 # every reduced-precision variant of the runtime's table (tile shapes, BK),
 # each forced in turn
-LP_VARIANTS = range(6)
+LP_VARIANTS = range(7)
 
 
 def test_every_lowprec_variant_one_step_bound(monkeypatch):
