@@ -165,7 +165,13 @@ typedef struct gd_run_stats {
     int64_t ttt_steps;        /* steps done at that check */
     double best_energy;       /* lowest device-checked energy so far (+inf if none) */
     int32_t best_index;       /* its trajectory */
-    int32_t kernel_config;    /* id of the coupling kernel variant in use */
+    int32_t kernel_config;    /* id of the coupling kernel variant in use: when a batch is
+                                 set up (gd_set_init, gd_set_state, the first gd_run) the
+                                 library times the variants that fit the problem, once per
+                                 (model, precision, size, batch, integrator), and keeps the
+                                 fastest; the environment variable GD_DENSE_CONFIG=<id>
+                                 pins one instead (the set-up call then fails with
+                                 GD_E_INVALID_ARG if that id does not fit) */
 } gd_run_stats;
 
 typedef struct gd_solver gd_solver;
