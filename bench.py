@@ -89,6 +89,8 @@ def parse():
                     help="steps and time to a stationary state vs N (XY, U[-10,10], paper regime)")
     ap.add_argument("--gdmod-scaling", action="store_true",
                     help="steps to a stationary state vs N, GD vs GD-mod (XY, U[-10,10], Euler)")
+    ap.add_argument("--learned", action="store_true",
+                    help="throughput of the learned proposal's training and inference kernels")
     ap.add_argument("--maxcut800", action="store_true",
                     help="N=800 G(n,0.06) max-cut stand-ins: cut quality and time, 100 runs each")
     return ap.parse_args()
@@ -524,6 +526,86 @@ def gdmod_scaling(args):
                       "budget_steps": budget}), flush=True)
 
 
+def learned_bench(args):
+    """Throughput of the learned proposal's own kernels, one JSON line.
+    Data: 256 random 3-regular max-cut instances, N even in [512, 2048]
+    (the training distribution), features from gd_features (30 block-power
+    iterations), random +-1 labels (the arithmetic does not depend on them);
+    all rows and labels resident on the device.  Timed: FP32 training steps
+    (forward, backward, Adam) on minibatches of 64 instances; FP16 and FP32
+    inference over all spins; gd_propose (features + FP16 network + initial
+    state) for the 256 instances x R = 64.  Flops per spin row: forward
+    2 (20*64 + 64*64 + 64*2) = 11 008, a training step about three times that
+    (forward, activation and weight gradients); the kernels run on the FP32
+    vector ALUs (78.6 TFLOP/s without packed math)."""
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    torch.cuda.init()
+    sizes, insts = I.maxcut_batch(256, 512, 2048, 7)
+    sizes = np.asarray(sizes, np.int64)
+    with gd.BatchSolver(insts) as B:
+        X, _, _ = gd.gd_features(B.h, int(sizes.sum()), len(insts), 30)
+    rng = np.random.default_rng(7)
+    lab = np.where(rng.random(X.shape[0]) < 0.5, -1.0, 1.0).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(lab).cuda()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    fwd = 2 * (20 * 64 + 64 * 64 + 64 * 2)
+    peak = 78.6
+    out = {"learned": "proposal network throughput (device buffers)", "rows_total": int(X.shape[0]),
+           "instances": len(insts), "flops_per_row_forward": fwd, "flops_per_row_train": 3 * fwd,
+           "peak_tflops_fp32_valu": peak}
+    steps = args.steps or 40
+    with gd.MLP(seed=1, device=True) as m:
+        batches = []
+        for b in range(4):
+            r0, r1 = int(off[64 * b]), int(off[64 * (b + 1)])
+            seg = (off[64 * b:64 * (b + 1) + 1] - r0).astype(np.int32)
+            batches.append((Xd[r0:r1], Ld[r0:r1], seg))
+        for w in range(3):
+            m.train_step_device(*batches[w % 4], 1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = 0
+        for s in range(steps):
+            xb, lb, sg = batches[s % 4]
+            m.train_step_device(xb, lb, sg, 1e-3)
+            rows += int(xb.shape[0])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["train"] = {"steps": steps, "rows_per_s": rows / el, "instances_per_s": 64 * steps / el,
+                        "ms_per_step": 1e3 * el / steps,
+                        "tflops": 3 * fwd * rows / el / 1e12,
+                        "frac": 3 * fwd * rows / el / 1e12 / peak}
+        o = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
+        for name, fp16 in (("infer_fp16", True), ("infer_fp32", False)):
+            for _ in range(3):
+                m.forward_device(Xd, o, fp16)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(50):
+                m.forward_device(Xd, o, fp16)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            r = 50 * X.shape[0] / el
+            out[name] = {"rows_per_s": r, "us_per_call": 1e6 * el / 50, "tflops": fwd * r / 1e12,
+                         "frac": fwd * r / 1e12 / peak}
+    with gd.BatchSolver(insts) as B, gd.MLP(seed=1) as mh:
+        gd.gd_propose(B.h, mh, 64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            gd.gd_propose(B.h, mh, 64)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["propose"] = {"instances_per_s": 10 * len(insts) / el, "ms_per_call": 1e3 * el / 10,
+                          "R": 64, "feature_iterations": 30}
+    print(json.dumps(out), flush=True)
+
+
 def maxcut800(args):
     """Max-cut stand-ins shaped like the paper's N = 800 benchmarks (Sec. 3):
     five G(800, 0.06) graphs with unit weights and five with +-1 weights, 100
@@ -607,6 +689,9 @@ def main():
         return
     if args.compare_ttt:
         compare_ttt(args)
+        return
+    if args.learned:
+        learned_bench(args)
         return
     import torch
 

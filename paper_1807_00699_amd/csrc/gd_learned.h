@@ -32,7 +32,8 @@ struct MlpTrainArgs {
     float *out;                    // [M][2]
     float *sigma;                  // [K]
     float *spin_loss;              // [M]
-    float *dO, *H1, *H2, *dH1, *dH2;
+    float *dO;                     // [M][2]
+    float *H1, *H2, *dH1, *dH2;    // feature-major [H][M]: activations and their gradients
     float *partial;                // [nparts][kMlpNParam]
     float *grad_out;               // [kMlpNParam] (nullable)
     double *loss;                  // [1]

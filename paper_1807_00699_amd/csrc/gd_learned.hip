@@ -309,13 +309,10 @@ __global__ void __launch_bounds__(FT) feat_k(FeatArgs a) {
 
 constexpr int MT = 256;
 
-__device__ inline void mlp_load_params(const float *__restrict__ p, float *sp) {
-    for (int q = threadIdx.x; q < NPAR; q += blockDim.x) sp[q] = p[q];
-    __syncthreads();
-}
-
-// forward of one spin with parameters in LDS; z1/z2 pre-activations
-__device__ inline void mlp_fwd1(const float *sp, const float *x, float *z1, float *z2, float *o) {
+// forward of one spin; z1/z2 pre-activations.  sp: the parameters, read at
+// wave-uniform addresses (from global memory the compiler turns them into
+// scalar loads feeding the FMAs)
+__device__ inline void mlp_fwd1(const float *__restrict__ sp, const float *x, float *z1, float *z2, float *o) {
     for (int j = 0; j < H; ++j) {
         float acc = sp[OFF_B1 + j];
         for (int f = 0; f < F; ++f) acc += x[f] * sp[OFF_W1 + f * H + j];
@@ -335,8 +332,7 @@ __device__ inline void mlp_fwd1(const float *sp, const float *x, float *z1, floa
 
 __global__ void __launch_bounds__(MT) mlp_forward_k(const float *__restrict__ p, const float *__restrict__ X,
                                                    float *__restrict__ out, int M) {
-    __shared__ float sp[NPAR];
-    mlp_load_params(p, sp);
+    const float *__restrict__ sp = p;
     const int m = blockIdx.x * MT + threadIdx.x;
     if (m >= M) return;
     float x[F], z1[H], z2[H], o[NO];
@@ -415,9 +411,12 @@ __global__ void __launch_bounds__(256) mlp_segment_k(const float *__restrict__ o
 }
 
 // backward per spin: dO, dH2, dH1 and the activations needed for weight grads
+// Activations and their gradients are written feature-major ([H][M]), so the
+// stores of a wave (consecutive spins) are contiguous.
 __global__ void __launch_bounds__(MT) mlp_backward_k(MlpTrainArgs a) {
     __shared__ float sp[NPAR];
-    mlp_load_params(a.params, sp);
+    for (int q = threadIdx.x; q < NPAR; q += MT) sp[q] = a.params[q];
+    __syncthreads();
     const int m = blockIdx.x * MT + threadIdx.x;
     if (m >= a.M) return;
     const int k = a.spin_inst[m];
@@ -440,81 +439,106 @@ __global__ void __launch_bounds__(MT) mlp_backward_k(MlpTrainArgs a) {
     for (int b = 0; b < H; ++b) {
         const float g = d0 * sp[OFF_W3 + b * NO] + d1 * sp[OFF_W3 + b * NO + 1];
         dh2[b] = z2[b] > 0.0f ? g : 0.0f;
-        a.H2[(long long)m * H + b] = fmaxf(z2[b], 0.0f);
-        a.dH2[(long long)m * H + b] = dh2[b];
+        a.H2[(long long)b * a.M + m] = fmaxf(z2[b], 0.0f);
+        a.dH2[(long long)b * a.M + m] = dh2[b];
     }
     for (int j = 0; j < H; ++j) {
         float g = 0.0f;
         for (int b = 0; b < H; ++b) g += dh2[b] * sp[OFF_W2 + j * H + b];
-        a.H1[(long long)m * H + j] = fmaxf(z1[j], 0.0f);
-        a.dH1[(long long)m * H + j] = z1[j] > 0.0f ? g : 0.0f;
+        a.H1[(long long)j * a.M + m] = fmaxf(z1[j], 0.0f);
+        a.dH1[(long long)j * a.M + m] = z1[j] > 0.0f ? g : 0.0f;
     }
 }
 
 // weight-gradient partials: block p reduces spins [p*chunk, (p+1)*chunk) into
-// partial[p][NPAR].  Each thread owns parameters q = tid + MT * slot.
+// partial[p][NPAR], each parameter summed over the spins in order.  Tiles of
+// WG_TILE spins are staged in LDS; register blocks per thread: a 4 x 4 block
+// of W2 (16 products per 8 LDS reads), 5 entries of one W1 column, and one of
+// B1 / B2 / W3 (plus B3 for two threads).
 constexpr int WG_TILE = 32;
-constexpr int WG_SLOTS = (NPAR + MT - 1) / MT;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+static_assert(MT == 256 && H == 64 && F == 20 && NO == 2, "thread map of mlp_wgrad_k");
 __global__ void __launch_bounds__(MT) mlp_wgrad_k(MlpTrainArgs a, int chunk) {
-    __shared__ float sX[WG_TILE][F], sH1[WG_TILE][H], sH2[WG_TILE][H];
-    __shared__ float sD1[WG_TILE][H], sD2[WG_TILE][H], sDO[WG_TILE][NO];
-    float acc[WG_SLOTS];
-    for (int q = 0; q < WG_SLOTS; ++q) acc[q] = 0.0f;
+    // rows padded to H + 4 floats: the transposing LDS stores (consecutive
+    // spins) spread over banks, the 16-byte reads stay aligned
+    constexpr int HP = H + 4;
+    __shared__ __attribute__((aligned(16))) float sX[WG_TILE][F], sH1[WG_TILE][HP], sH2[WG_TILE][HP];
+    __shared__ __attribute__((aligned(16))) float sD1[WG_TILE][HP], sD2[WG_TILE][HP], sDO[WG_TILE][NO];
+    const int t = threadIdx.x;
+    const int j0 = (t / 16) * 4, b0 = (t % 16) * 4;    // W2 block
+    const int wj = t % 64, f0 = (t / 64) * 5;           // W1: rows f0..f0+4 of column wj
+    float w2[4][4], w1[5], one = 0.0f, b3 = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w2[u][v] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) w1[u] = 0.0f;
     const int m0 = blockIdx.x * chunk;
     const int m1 = min(a.M, m0 + chunk);
-    for (int t0 = m0; t0 < m1; t0 += WG_TILE) {
-        const int cnt = min(WG_TILE, m1 - t0);
-        for (int q = threadIdx.x; q < WG_TILE * H; q += MT) {
-            const int r = q / H, c = q % H;
+    for (int r0 = m0; r0 < m1; r0 += WG_TILE) {
+        const int cnt = min(WG_TILE, m1 - r0);
+        for (int q = t; q < WG_TILE * H; q += MT) {
+            const int r = q % WG_TILE, c = q / WG_TILE;     // feature-major sources
             const bool in = r < cnt;
-            const long long m = (long long)(t0 + r);
-            sH1[r][c] = in ? a.H1[m * H + c] : 0.0f;
-            sH2[r][c] = in ? a.H2[m * H + c] : 0.0f;
-            sD1[r][c] = in ? a.dH1[m * H + c] : 0.0f;
-            sD2[r][c] = in ? a.dH2[m * H + c] : 0.0f;
-            if (c < F) sX[r][c] = in ? a.X[m * F + c] : 0.0f;
-            if (c < NO) sDO[r][c] = in ? a.dO[m * NO + c] : 0.0f;
+            const long long mc = (long long)c * a.M + r0 + r;
+            sH1[r][c] = in ? a.H1[mc] : 0.0f;
+            sH2[r][c] = in ? a.H2[mc] : 0.0f;
+            sD1[r][c] = in ? a.dH1[mc] : 0.0f;
+            sD2[r][c] = in ? a.dH2[mc] : 0.0f;
+        }
+        for (int q = t; q < WG_TILE * F; q += MT) {
+            const int r = q / F, c = q % F;
+            sX[r][c] = r < cnt ? a.X[(long long)(r0 + r) * F + c] : 0.0f;
+        }
+        if (t < WG_TILE * NO) {
+            const int r = t / NO, c = t % NO;
+            sDO[r][c] = r < cnt ? a.dO[(long long)(r0 + r) * NO + c] : 0.0f;
         }
         __syncthreads();
-        for (int s = 0; s < WG_SLOTS; ++s) {
-            const int q = threadIdx.x + MT * s;
-            if (q >= NPAR) break;
-            float v = 0.0f;
-            if (q < OFF_B1) {
-                const int f = q / H, j = q % H;
-                for (int r = 0; r < WG_TILE; ++r) v += sX[r][f] * sD1[r][j];
-            } else if (q < OFF_W2) {
-                const int j = q - OFF_B1;
-                for (int r = 0; r < WG_TILE; ++r) v += sD1[r][j];
-            } else if (q < OFF_B2) {
-                const int j = (q - OFF_W2) / H, b = (q - OFF_W2) % H;
-                for (int r = 0; r < WG_TILE; ++r) v += sH1[r][j] * sD2[r][b];
-            } else if (q < OFF_W3) {
-                const int b = q - OFF_B2;
-                for (int r = 0; r < WG_TILE; ++r) v += sD2[r][b];
-            } else if (q < OFF_B3) {
-                const int b = (q - OFF_W3) / NO, o = (q - OFF_W3) % NO;
-                for (int r = 0; r < WG_TILE; ++r) v += sH2[r][b] * sDO[r][o];
-            } else {
-                const int o = q - OFF_B3;
-                for (int r = 0; r < WG_TILE; ++r) v += sDO[r][o];
-            }
-            acc[s] += v;
+        for (int r = 0; r < WG_TILE; ++r) {
+            const f32x4 h1 = *reinterpret_cast<const f32x4 *>(&sH1[r][j0]);
+            const f32x4 d2 = *reinterpret_cast<const f32x4 *>(&sD2[r][b0]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w2[u][v] = fmaf(h1[u], d2[v], w2[u][v]);
+            const float d1 = sD1[r][wj];
+#pragma unroll
+            for (int u = 0; u < 5; ++u) w1[u] = fmaf(sX[r][f0 + u], d1, w1[u]);
+            if (t < 64) one += sD1[r][t];                                      // B1
+            else if (t < 128) one += sD2[r][t - 64];                           // B2
+            else one = fmaf(sH2[r][(t - 128) / 2], sDO[r][(t - 128) % 2], one);  // W3
+            if (t < NO) b3 += sDO[r][t];                                       // B3
         }
         __syncthreads();
     }
-    for (int s = 0; s < WG_SLOTS; ++s) {
-        const int q = threadIdx.x + MT * s;
-        if (q < NPAR) a.partial[(long long)blockIdx.x * NPAR + q] = acc[s];
-    }
+    float *part = a.partial + (long long)blockIdx.x * NPAR;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[OFF_W2 + (j0 + u) * H + b0 + v] = w2[u][v];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) part[OFF_W1 + (f0 + u) * H + wj] = w1[u];
+    if (t < 64) part[OFF_B1 + t] = one;
+    else if (t < 128) part[OFF_B2 + t - 64] = one;
+    else part[OFF_W3 + (t - 128)] = one;
+    if (t < NO) part[OFF_B3 + t] = b3;
 }
 
 // fixed-order sum of the partials, then Adam; loss = fixed-order sum of spin losses
 __global__ void __launch_bounds__(MT) mlp_adam_k(MlpTrainArgs a, int nparts, float lr, int step) {
     const int q = blockIdx.x * MT + threadIdx.x;
     if (q < NPAR) {
-        float g = 0.0f;
-        for (int pp = 0; pp < nparts; ++pp) g += a.partial[(long long)pp * NPAR + q];
+        // eight interleaved running sums (independent loads in flight),
+        // combined in a fixed order
+        float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int pp = 0;
+        for (; pp + 8 <= nparts; pp += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s8[u] += a.partial[(long long)(pp + u) * NPAR + q];
+        for (; pp < nparts; ++pp) s8[pp & 7] += a.partial[(long long)pp * NPAR + q];
+        const float g = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         if (a.grad_out) a.grad_out[q] = g;
         if (lr > 0.0f) {
             const float b1 = 0.9f, b2 = 0.999f;

@@ -38,7 +38,7 @@ struct gd_mlp {
 
 namespace {
 
-constexpr int kParts = 128;
+constexpr int kParts = 512;   // weight-gradient partials (workgroups)
 
 #define GD_TRY(expr)                                                                     \
     do {                                                                                 \

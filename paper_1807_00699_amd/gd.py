@@ -431,14 +431,17 @@ def gd_features(h, total, K, iters=30):
 
 
 class MLP:
-    """Owning wrapper of a gd_mlp handle (host arrays)."""
+    """Owning wrapper of a gd_mlp handle.  device=False: numpy arrays;
+    device=True (GD_F_DEVICE_PTRS): X, labels and outputs are contiguous
+    float32 device tensors, seg stays a host array, params stay host arrays."""
 
-    def __init__(self, params=None, seed=0):
+    def __init__(self, params=None, seed=0, device=False):
         lib = load()
         self.h = C.c_void_p()
-        p = None if params is None else np.ascontiguousarray(params, np.float32)
-        _check(lib.gd_mlp_create(C.byref(self.h), None if p is None else p.ctypes.data_as(C.c_void_p),
-                                 int(seed), 0), "gd_mlp_create")
+        self.device = bool(device)
+        pp, _keep = _ptr(params, device=self.device)
+        _check(lib.gd_mlp_create(C.byref(self.h), pp, int(seed), GD_F_DEVICE_PTRS if self.device else 0),
+               "gd_mlp_create")
 
     def close(self):
         if self.h is not None:
@@ -459,6 +462,8 @@ class MLP:
 
     @property
     def params(self):
+        if self.device:
+            raise GDError(GD_E_INVALID_ARG, "params of a device-pointer MLP: use a host MLP")
         p = np.empty(GD_MLP_NPARAM, np.float32)
         _check(load().gd_mlp_get_params(self.h, p.ctypes.data_as(C.c_void_p)), "gd_mlp_get_params")
         return p
@@ -467,6 +472,21 @@ class MLP:
     def params(self, p):
         p = np.ascontiguousarray(p, np.float32)
         _check(load().gd_mlp_set_params(self.h, p.ctypes.data_as(C.c_void_p)), "gd_mlp_set_params")
+
+    def forward_device(self, X, out, fp16=False):
+        """X [M][GD_NFEAT], out [M][2]: contiguous float32 device tensors."""
+        _check(load().gd_mlp_forward(self.h, int(X.shape[0]), C.c_void_p(X.data_ptr()),
+                                     C.c_void_p(out.data_ptr()), int(bool(fp16))), "gd_mlp_forward")
+
+    def train_step_device(self, X, labels, seg, lr):
+        """X, labels: contiguous float32 device tensors; seg: host int32."""
+        seg = np.ascontiguousarray(seg, np.int32)
+        loss = C.c_double()
+        _check(load().gd_mlp_train_step(self.h, int(X.shape[0]), C.c_void_p(X.data_ptr()),
+                                        C.c_void_p(labels.data_ptr()), len(seg) - 1,
+                                        seg.ctypes.data_as(C.c_void_p), float(lr), C.byref(loss), None),
+               "gd_mlp_train_step")
+        return float(loss.value)
 
     def forward(self, X, fp16=False):
         X = np.ascontiguousarray(X, np.float32)

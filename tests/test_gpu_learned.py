@@ -81,6 +81,30 @@ def test_mlp_forward_gradient_and_adam_match_oracle():
         assert np.abs(m.params - p1)[big].max() < 1e-6
 
 
+def test_mlp_device_pointer_calls_match_host_calls():
+    """GD_F_DEVICE_PTRS handle (device X, labels, outputs and parameters):
+    the same outputs, losses and trained parameters as the host handle."""
+    import torch
+
+    p, X, lab, seg = _toy()
+    pd = torch.from_numpy(p).cuda()
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(lab).cuda()
+    od = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
+    with gd.MLP(p) as mh, gd.MLP(pd, device=True) as md:
+        for fp16 in (False, True):
+            md.forward_device(Xd, od, fp16)
+            assert np.array_equal(od.cpu().numpy(), mh.forward(X, fp16=fp16))
+        for _ in range(3):
+            lh = mh.train_step(X, lab, seg, 1e-3)
+            ld = md.train_step_device(Xd, Ld, seg, 1e-3)
+            assert lh == ld
+        md.forward_device(Xd, od)
+        assert np.array_equal(od.cpu().numpy(), mh.forward(X))
+        with pytest.raises(gd.GDError):
+            md.params
+
+
 def test_training_steps_reduce_loss_on_learnable_labels():
     sizes = [128, 200, 256, 300]
     insts, dense = _batch(sizes, 9)
