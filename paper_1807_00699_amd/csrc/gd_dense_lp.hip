@@ -4,17 +4,20 @@
 //
 // J is stored either in the operand type or, when every coupling is exactly
 // representable there (e.g. couplings in {-1, 0, +1}), in FP8 (OCP E4M3,
-// one byte per coupling) and widened exactly to the operand type while it is
-// staged into LDS (v_cvt_pk_f32_fp8, then the top 16 bits: FP8 values have at
-// most four significant bits, so the truncation is exact).  The operand Psi
+// one byte per coupling) and widened exactly to the operand type: while it is
+// staged into LDS in the register-staged variants (v_cvt_pk_f32_fp8, then the
+// top 16 bits: FP8 values have at most four significant bits, so the
+// truncation is exact), after the LDS read in the direct-to-LDS variants
+// further below (J stays FP8 in LDS there).  The operand Psi
 // is a BF16/FP16 copy of the FP32 amplitudes that the epilogue of the
 // previous step writes next to them; the epilogue itself reads and writes the
 // FP32 state (gd_epilogue.h).
 //
 // Tiling: workgroup BM x BN (GEMM columns), WM x WN waves, each wave a grid of
-// 32x32 MFMA blocks.  LDS holds both tiles as [row][k] in the operand type
-// with an 8-element pad per row; each lane fetches the 8 operands of its
-// half-wave K slice with one ds_read_b128.  Complex tiles pair real and
+// 32x32 MFMA blocks.  The register-staged variants hold both tiles in LDS as
+// [row][k] in the operand type with an 8-element pad per row; each lane
+// fetches the 8 operands of its half-wave K slice with one ds_read_b128.
+// Complex tiles pair real and
 // imaginary column blocks inside a wave as in the FP32 kernel.
 #include "gd_epilogue.h"
 
