@@ -145,6 +145,11 @@ struct gd_solver {
     std::vector<hipEvent_t> events;
     int64_t ev_used = 0;       // event pairs recorded by the current gd_run call
     int64_t ev_launches = 0;   // coupling launches bracketed by those pairs
+    // small problems: kGraphSteps steps captured once in a hipGraph (launch
+    // overhead dominates there); valid for the buffers of the current state
+    // and the amplitude buffer index it was captured from
+    hipGraphExec_t step_graph = nullptr;
+    int step_graph_cur = -1;
 
     long long plane() const { return (long long)Rp * Np; }
     bool mod() const { return prm.variant == GD_VARIANT_MOD; }
@@ -155,6 +160,9 @@ struct gd_solver {
 namespace {
 
 void free_state(gd_solver *s) {
+    if (s->step_graph) (void)hipGraphExecDestroy(s->step_graph);
+    s->step_graph = nullptr;
+    s->step_graph_cur = -1;
     for (float *&p : s->psi) { if (p) (void)hipFree(p); p = nullptr; }
     float **fl[] = {&s->gam, &s->gam_s, &s->acc_psi, &s->acc_gam, &s->D, &s->K};
     for (float **p : fl) { if (*p) (void)hipFree(*p); *p = nullptr; }
@@ -823,6 +831,41 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
     return choose_config(s);
 }
 
+// Replay the captured kGraphSteps steps (capturing them first if the
+// amplitude buffer index differs from the capture's).  kGraphSteps is even,
+// so the Euler buffer ping-pong ends where it started.
+constexpr int kGraphSteps = 32;
+constexpr long long kGraphWork = 1ll << 28;   // Np^2 Rp P below which steps are replayed
+static_assert(kGraphSteps % 2 == 0, "Euler ping-pong parity");
+
+static int launch_step_graph(gd_solver *s) {
+    if (!s->step_graph || s->step_graph_cur != s->cur) {
+        if (s->step_graph) (void)hipGraphExecDestroy(s->step_graph);
+        s->step_graph = nullptr;
+        const int cur0 = s->cur;
+        hipGraph_t g = nullptr;
+        GD_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        int rc = GD_OK;
+        for (int q = 0; q < kGraphSteps && rc == GD_OK; ++q) rc = enqueue_step(s, s->cfg, -1.0f, false, 0);
+        const hipError_t ce = hipStreamEndCapture(s->stream, &g);
+        if (rc != GD_OK || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            s->cur = cur0;
+            return rc != GD_OK ? rc : fail(GD_E_DEVICE, std::string("step graph capture: ") + hipGetErrorString(ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&s->step_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            s->step_graph = nullptr;
+            return fail(GD_E_DEVICE, std::string("step graph: ") + hipGetErrorString(ie));
+        }
+        s->step_graph_cur = cur0;
+        // capture only recorded the steps; s->cur has come back to cur0
+    }
+    GD_HIP(hipGraphLaunch(s->step_graph, s->stream));
+    return GD_OK;
+}
+
 int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
     if (s->batch) return batch_run(s->batch, batch, steps);
@@ -838,6 +881,10 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     s->ev_launches = 0;
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = s->prm.check_interval;
+    // graph replay for small problems: not with profiling events, noise (its
+    // key changes every step) or GD-mod
+    const bool graph_ok = !timed && s->prm.noise_D == 0.0 && !s->mod() &&
+                          (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork;
     int64_t done = 0;
     while (done < steps) {
         int64_t chunk = steps - done;
@@ -845,7 +892,13 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             const int64_t to_check = ci - (s->steps_done % ci);
             chunk = std::min<int64_t>(chunk, to_check);
         }
-        for (int64_t k = 0; k < chunk; ++k) {
+        int64_t k = 0;
+        if (graph_ok) {
+            for (; chunk - k >= kGraphSteps; k += kGraphSteps) {
+                if ((rc = launch_step_graph(s)) != GD_OK) return rc;
+            }
+        }
+        for (; k < chunk; ++k) {
             // GD_F_PROFILE: HIP events around the coupling launches of every
             // kProfileEvery-th step only, so the events barely perturb the run
             const bool sample = timed && ((s->steps_done + k) % kProfileEvery == 0);

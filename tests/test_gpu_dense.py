@@ -161,6 +161,36 @@ def test_every_fp32_variant_parity_n1000(monkeypatch, model, integrator, dt):
         assert np.allclose(Ed, Eo, rtol=2e-5, atol=1e-3), (cid, np.abs(Ed - Eo).max())
 
 
+@pytest.mark.parametrize("model,integrator,n,R", [("ising", gd.GD_EULER, 64, 100), ("xy", gd.GD_RK4, 100, 37),
+                                                   ("ising", gd.GD_RK4, 200, 130)])
+def test_step_graph_replay_matches_eager_bitwise(model, integrator, n, R):
+    """Small problems replay captured 32-step graphs; a GD_F_PROFILE run
+    launches every step eagerly.  Same state bit for bit, across step counts
+    that are not multiples of 32, a set_state in between (recapture from the
+    other amplitude buffer for Euler) and device energy checks every 50 steps."""
+    cx = model == "xy"
+    J = I.dense_gaussian(n, 12) if cx else I.dense_pm1(n, 12)
+    psi0 = I.psi0_complex(n, R, 12) if cx else I.psi0_real(n, R, 12)
+    mdl = gd.GD_XY if cx else gd.GD_ISING
+    outs = []
+    for flags in (0, gd.GD_F_PROFILE):
+        with gd.Solver(J, model=mdl, integrator=integrator, dt=0.02, eps=0.1, flags=flags,
+                       check_interval=50) as S:
+            S.set_init(R, psi0)
+            S.run(77)
+            p, g, st = S.state()
+            S.set_state(p, g, step=st)
+            S.run(101)
+            S.run(64)
+            p, g, st = S.state()
+            E, b = S.energy()
+            outs.append((p, g, st, E, b, S.stats().best_energy))
+    (p0, g0, s0, E0, b0, be0), (p1, g1, s1, E1, b1, be1) = outs
+    assert s0 == s1 == 242
+    assert np.array_equal(p0, p1) and np.array_equal(g0, g1)
+    assert np.array_equal(E0, E1) and b0 == b1 and be0 == be1
+
+
 def test_xy3000_dense_uniform_sampled_parity():
     """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
     U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
