@@ -310,6 +310,63 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
     if (tid < E64_T) partial[(long long)mt * Rp + r0 + tid] = red[0][tid] + red[1][tid];
 }
 
+// Many explicit Euler steps of a small dense problem in one launch (Np <=
+// 128, FP32 operands, no resonant term, no noise): a workgroup holds J and
+// the amplitudes of 256 / Np trajectories in LDS for all the steps, one
+// thread per (spin, trajectory) with its amplitude and gain in registers.
+// Per step: C_ir = sum_j J_ij Psi_jr in j order (J is symmetric, so lanes on
+// consecutive i read row j contiguously), then Eq. (main) and Eq. (gamma)
+// as in the dense kernels' Euler update.
+template <bool CPLX, int NPX>
+__global__ void __launch_bounds__(256)
+small_euler_k(DenseStepArgs a, int steps) {
+    constexpr int TR = 256 / NPX;
+    __shared__ float Js[NPX * NPX];
+    __shared__ float xs[CPLX ? 2 : 1][TR][NPX];
+    const int tid = threadIdx.x;
+    const int i = tid % NPX, tl = tid / NPX;
+    const int r = blockIdx.x * TR + tl;
+    const long long idx = (long long)r * NPX + i;
+    const long long ps = a.plane_stride;
+    const float *J = static_cast<const float *>(a.J);
+    for (int q = tid; q < NPX * NPX; q += 256) Js[q] = J[q];
+    float x = a.psi_in[idx];
+    float y = CPLX ? a.psi_in[ps + idx] : 0.0f;
+    float g = a.gam_in[idx];
+    const float ep = a.eps[i], hh = a.h1[i];
+    const bool valid = r < a.R && i < a.n;
+    xs[0][tl][i] = x;
+    if (CPLX) xs[CPLX ? 1 : 0][tl][i] = y;
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        float cr = 0.0f, ci = 0.0f;
+        for (int j = 0; j < NPX; ++j) {
+            const float w = Js[j * NPX + i];
+            cr = fmaf(w, xs[0][tl][j], cr);
+            if (CPLX) ci = fmaf(w, xs[CPLX ? 1 : 0][tl][j], ci);
+        }
+        if (valid) {
+            const float rho = CPLX ? x * x + y * y : x * x;
+            const float lin = g - a.gamma_c - rho;
+            const float fr = x * lin + cr * a.inv_s + hh;
+            const float fi = CPLX ? y * lin + ci * a.inv_s : 0.0f;
+            const float fg = ep * (a.rho_th - rho);
+            x = x + a.dt * fr;
+            y = y + a.dt * fi;
+            g = g + a.dt * fg;
+        }
+        __syncthreads();                      // every read of this step's amplitudes is done
+        xs[0][tl][i] = x;
+        if (CPLX) xs[CPLX ? 1 : 0][tl][i] = y;
+        __syncthreads();
+    }
+    a.psi_out[idx] = x;
+    if (CPLX) a.psi_out[ps + idx] = y;
+    a.gam_out[idx] = g;
+    // non-finite values persist once they appear, so the final state tells
+    if (r < a.R && !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(g))) a.flags[r] = 1;
+}
+
 __global__ void make_shadow_k(const float *__restrict__ src, void *dst, long long count, int op) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < count;
          t += (long long)gridDim.x * blockDim.x)
@@ -386,6 +443,21 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
         energy_fp64_k<2><<<grid, 256, 0, st>>>(J, D64, g, partial, Np, Rp, plane_stride, w);
     else
         energy_fp64_k<1><<<grid, 256, 0, st>>>(J, D64, g, partial, Np, Rp, plane_stride, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_euler(bool complex_mode, const DenseStepArgs &a, int steps, hipStream_t st) {
+    if (steps < 1 || (a.Np != 64 && a.Np != 128)) return hipErrorInvalidValue;
+    const int tr = 256 / a.Np;
+    if (a.Rp % tr) return hipErrorInvalidValue;
+    const dim3 grid(a.Rp / tr);
+    if (a.Np == 64) {
+        if (complex_mode) small_euler_k<true, 64><<<grid, 256, 0, st>>>(a, steps);
+        else small_euler_k<false, 64><<<grid, 256, 0, st>>>(a, steps);
+    } else {
+        if (complex_mode) small_euler_k<true, 128><<<grid, 256, 0, st>>>(a, steps);
+        else small_euler_k<false, 128><<<grid, 256, 0, st>>>(a, steps);
+    }
     return hipGetLastError();
 }
 

@@ -298,9 +298,6 @@ hipError_t refresh_shadow(gd_solver *s, int k) {
     return launch_make_shadow(s->psi[k], s->shadow[k], s->plane() * s->P, s->op, s->stream);
 }
 
-// Enqueue integration step number t.  `dt_override` >= 0 replaces dt (used
-// with 0 by the tuner: the state is then left bit-for-bit unchanged, noise
-// included, since its amplitude is D sqrt(dt)).
 // HIP event pair around work on the solver's stream (GD_F_PROFILE)
 int ev_begin(gd_solver *s) {
     const size_t k = (size_t)s->ev_used * 2;
@@ -320,6 +317,9 @@ int ev_end(gd_solver *s, int launches) {
     return GD_OK;
 }
 
+// Enqueue integration step number t.  `dt_override` >= 0 replaces dt (used
+// with 0 by the tuner: the state is then left bit-for-bit unchanged, noise
+// included, since its amplitude is D sqrt(dt)).
 int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool timed, int64_t t) {
     int rc;
     DenseStepArgs a = base_args(s);
@@ -835,6 +835,7 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
 // amplitude buffer index differs from the capture's).  kGraphSteps is even,
 // so the Euler buffer ping-pong ends where it started.
 constexpr int kGraphSteps = 32;
+constexpr int kSmallStepsPerLaunch = 4096;
 constexpr long long kGraphWork = 1ll << 28;   // Np^2 Rp P below which steps are replayed
 static_assert(kGraphSteps % 2 == 0, "Euler ping-pong parity");
 
@@ -883,7 +884,13 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const int ci = s->prm.check_interval;
     // graph replay for small problems: not with profiling events, noise (its
     // key changes every step) or GD-mod
-    const bool graph_ok = !timed && s->prm.noise_D == 0.0 && !s->mod() &&
+    // Np <= 128, FP32, Euler, no resonant term, no noise: the fused
+    // multi-step kernel (one event pair per launch when profiled, counting
+    // its steps as coupling launches)
+    const bool small_ok = s->integrator() == GD_EULER && !s->mod() && s->prm.noise_D == 0.0 &&
+                          s->q_res == 0 && s->op == OP_F32 && s->Np <= 128 &&
+                          std::getenv("GD_DENSE_CONFIG") == nullptr;
+    const bool graph_ok = !small_ok && !timed && s->prm.noise_D == 0.0 && !s->mod() &&
                           (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork;
     int64_t done = 0;
     while (done < steps) {
@@ -893,6 +900,22 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             chunk = std::min<int64_t>(chunk, to_check);
         }
         int64_t k = 0;
+        if (small_ok) {
+            // all steps of the chunk in LDS, a bounded number per launch
+            while (k < chunk) {
+                const int m = int(std::min<int64_t>(chunk - k, kSmallStepsPerLaunch));
+                DenseStepArgs a = base_args(s);
+                a.psi_in = s->psi[s->cur];
+                a.psi_out = s->psi[s->cur ^ 1];
+                a.gam_in = s->gam;
+                a.gam_out = s->gam;
+                if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
+                GD_HIP(launch_small_euler(s->complex_mode(), a, m, s->stream));
+                if (timed && (rc = ev_end(s, m)) != GD_OK) return rc;
+                s->cur ^= 1;
+                k += m;
+            }
+        }
         if (graph_ok) {
             for (; chunk - k >= kGraphSteps; k += kGraphSteps) {
                 if ((rc = launch_step_graph(s)) != GD_OK) return rc;
