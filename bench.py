@@ -748,10 +748,10 @@ def main():
     kms = st.kernel_ms - st0.kernel_ms
     avg_s = kms / 1e3 / max(launches, 1)
     flops_launch = 2.0 * n * n * P * R          # coupling GEMM of one launch
-    # padded sizes of at most 128 spins, FP32, Euler: the runtime runs many
-    # steps per launch of its fused small-problem kernel (FP32 vector ALUs);
-    # its events then bracket whole launches and count their steps
-    small = (-(-n // 64) * 64 <= 128 and prec_name == "fp32" and wl["integrator"] == "euler")
+    # padded sizes of at most 128 spins, FP32: the runtime runs many steps per
+    # launch of its fused small-problem kernel (FP32 vector ALUs); its events
+    # then bracket whole launches and count their coupling evaluations
+    small = (-(-n // 64) * 64 <= 128 and prec_name == "fp32")
     achieved = flops_launch / avg_s / 1e12
     out = {
         "metric": "spin-updates/s (N*R*steps/s)",
@@ -770,8 +770,8 @@ def main():
                    "dt": wl["dt"], "energy_check_every": args.check, "kernel_config": st.kernel_config},
         "roofline": ({"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_F32,
                       "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_F32, "traffic": None,
-                      "kernel": "small_euler_k", "launches_counted_as_steps": int(launches),
-                      "avg_step_us": avg_s * 1e6, "flops_per_step": flops_launch}
+                      "kernel": "small_step_k", "coupling_evaluations": int(launches),
+                      "avg_evaluation_us": avg_s * 1e6, "flops_per_evaluation": flops_launch}
                      if small else
                      {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[prec_name],
                       "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS[prec_name],

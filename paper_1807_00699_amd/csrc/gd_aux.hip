@@ -310,19 +310,21 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
     if (tid < E64_T) partial[(long long)mt * Rp + r0 + tid] = red[0][tid] + red[1][tid];
 }
 
-// Many explicit Euler steps of a small dense problem in one launch (Np <=
-// 128, FP32 operands, no resonant term, no noise): a workgroup holds J and
-// the amplitudes of 256 / Np trajectories in LDS for all the steps, one
-// thread per (spin, trajectory) with its amplitude and gain in registers.
-// Per step: C_ir = sum_j J_ij Psi_jr in j order (J is symmetric, so lanes on
-// consecutive i read row j contiguously), then Eq. (main) and Eq. (gamma)
-// as in the dense kernels' Euler update.
-template <bool CPLX, int NPX>
+// Many integration steps of a small dense problem in one launch (Np <= 128,
+// FP32 operands, no resonant term, no noise): a workgroup holds J and the
+// amplitudes of 256 / Np trajectories in LDS for all the steps, one thread
+// per (spin, trajectory) with its amplitude and gain in registers.  Per
+// coupling evaluation: C_ir = sum_j J_ij Psi_jr in j order (J is symmetric,
+// so lanes on consecutive i read row j contiguously), then Eq. (main) and
+// Eq. (gamma) as in the dense kernels: an explicit Euler step, or the four
+// stages of the classical RK4 step on the joint state (Psi, gamma).
+template <bool CPLX, int NPX, bool RK4>
 __global__ void __launch_bounds__(256)
-small_euler_k(DenseStepArgs a, int steps) {
+small_step_k(DenseStepArgs a, int steps) {
     constexpr int TR = 256 / NPX;
+    constexpr int PL = CPLX ? 2 : 1;
     __shared__ float Js[NPX * NPX];
-    __shared__ float xs[CPLX ? 2 : 1][TR][NPX];
+    __shared__ float xs[PL][TR][NPX];
     const int tid = threadIdx.x;
     const int i = tid % NPX, tl = tid / NPX;
     const int r = blockIdx.x * TR + tl;
@@ -335,30 +337,81 @@ small_euler_k(DenseStepArgs a, int steps) {
     float g = a.gam_in[idx];
     const float ep = a.eps[i], hh = a.h1[i];
     const bool valid = r < a.R && i < a.n;
-    xs[0][tl][i] = x;
-    if (CPLX) xs[CPLX ? 1 : 0][tl][i] = y;
-    __syncthreads();
-    for (int st = 0; st < steps; ++st) {
+    // sums over the amplitudes in LDS, then the right-hand side at (sx, sy, sg)
+    auto rhs = [&](float sx, float sy, float sg, float &fr, float &fi, float &fg) {
         float cr = 0.0f, ci = 0.0f;
-        for (int j = 0; j < NPX; ++j) {
-            const float w = Js[j * NPX + i];
-            cr = fmaf(w, xs[0][tl][j], cr);
-            if (CPLX) ci = fmaf(w, xs[CPLX ? 1 : 0][tl][j], ci);
+        // 16 terms at a time: their LDS reads are issued together, then the
+        // multiply-adds run in j order
+        for (int j0 = 0; j0 < NPX; j0 += 16) {
+            float w[16], v0[16], v1[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                w[u] = Js[(j0 + u) * NPX + i];
+                v0[u] = xs[0][tl][j0 + u];
+                v1[u] = CPLX ? xs[PL - 1][tl][j0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                cr = fmaf(w[u], v0[u], cr);
+                if (CPLX) ci = fmaf(w[u], v1[u], ci);
+            }
         }
-        if (valid) {
-            const float rho = CPLX ? x * x + y * y : x * x;
-            const float lin = g - a.gamma_c - rho;
-            const float fr = x * lin + cr * a.inv_s + hh;
-            const float fi = CPLX ? y * lin + ci * a.inv_s : 0.0f;
-            const float fg = ep * (a.rho_th - rho);
-            x = x + a.dt * fr;
-            y = y + a.dt * fi;
-            g = g + a.dt * fg;
-        }
-        __syncthreads();                      // every read of this step's amplitudes is done
-        xs[0][tl][i] = x;
-        if (CPLX) xs[CPLX ? 1 : 0][tl][i] = y;
+        const float rho = CPLX ? sx * sx + sy * sy : sx * sx;
+        const float lin = sg - a.gamma_c - rho;
+        fr = sx * lin + cr * a.inv_s + hh;
+        fi = CPLX ? sy * lin + ci * a.inv_s : 0.0f;
+        fg = ep * (a.rho_th - rho);
+    };
+    // publish amplitudes (sx, sy) once every thread has read the previous ones
+    auto publish = [&](float sx, float sy) {
         __syncthreads();
+        xs[0][tl][i] = sx;
+        if (CPLX) xs[PL - 1][tl][i] = sy;
+        __syncthreads();
+    };
+    publish(x, y);
+    const float dt = a.dt;
+    for (int st = 0; st < steps; ++st) {
+        float fr, fi, fg;
+        if constexpr (!RK4) {
+            rhs(x, y, g, fr, fi, fg);
+            if (valid) {
+                x = x + dt * fr;
+                y = y + dt * fi;
+                g = g + dt * fg;
+            }
+            publish(x, y);
+        } else {
+            // stage inputs s = y + c k with c = dt/2, dt/2, dt; accumulator
+            // k1 + 2 k2 + 2 k3 (rows outside n keep their state)
+            float ar, ai, ag, sx, sy, sg;
+            rhs(x, y, g, fr, fi, fg);                                    // k1
+            ar = fr; ai = fi; ag = fg;
+            sx = valid ? x + 0.5f * dt * fr : x;
+            sy = valid ? y + 0.5f * dt * fi : y;
+            sg = valid ? g + 0.5f * dt * fg : g;
+            publish(sx, sy);
+            rhs(sx, sy, sg, fr, fi, fg);                                 // k2
+            ar += 2.0f * fr; ai += 2.0f * fi; ag += 2.0f * fg;
+            sx = valid ? x + 0.5f * dt * fr : x;
+            sy = valid ? y + 0.5f * dt * fi : y;
+            sg = valid ? g + 0.5f * dt * fg : g;
+            publish(sx, sy);
+            rhs(sx, sy, sg, fr, fi, fg);                                 // k3
+            ar += 2.0f * fr; ai += 2.0f * fi; ag += 2.0f * fg;
+            sx = valid ? x + dt * fr : x;
+            sy = valid ? y + dt * fi : y;
+            sg = valid ? g + dt * fg : g;
+            publish(sx, sy);
+            rhs(sx, sy, sg, fr, fi, fg);                                 // k4
+            const float c6 = dt * (1.0f / 6.0f);
+            if (valid) {
+                x = x + c6 * (ar + fr);
+                y = y + c6 * (ai + fi);
+                g = g + c6 * (ag + fg);
+            }
+            publish(x, y);
+        }
     }
     a.psi_out[idx] = x;
     if (CPLX) a.psi_out[ps + idx] = y;
@@ -446,18 +499,20 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
     return hipGetLastError();
 }
 
-hipError_t launch_small_euler(bool complex_mode, const DenseStepArgs &a, int steps, hipStream_t st) {
+hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps, hipStream_t st) {
     if (steps < 1 || (a.Np != 64 && a.Np != 128)) return hipErrorInvalidValue;
     const int tr = 256 / a.Np;
     if (a.Rp % tr) return hipErrorInvalidValue;
     const dim3 grid(a.Rp / tr);
+#define GD_SMALL(C, N, K) small_step_k<C, N, K><<<grid, 256, 0, st>>>(a, steps)
     if (a.Np == 64) {
-        if (complex_mode) small_euler_k<true, 64><<<grid, 256, 0, st>>>(a, steps);
-        else small_euler_k<false, 64><<<grid, 256, 0, st>>>(a, steps);
+        if (complex_mode) { if (rk4) GD_SMALL(true, 64, true); else GD_SMALL(true, 64, false); }
+        else { if (rk4) GD_SMALL(false, 64, true); else GD_SMALL(false, 64, false); }
     } else {
-        if (complex_mode) small_euler_k<true, 128><<<grid, 256, 0, st>>>(a, steps);
-        else small_euler_k<false, 128><<<grid, 256, 0, st>>>(a, steps);
+        if (complex_mode) { if (rk4) GD_SMALL(true, 128, true); else GD_SMALL(true, 128, false); }
+        else { if (rk4) GD_SMALL(false, 128, true); else GD_SMALL(false, 128, false); }
     }
+#undef GD_SMALL
     return hipGetLastError();
 }
 

@@ -162,9 +162,9 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
 hipError_t launch_make_shadow(const float *src, void *dst, long long count, int op, hipStream_t st);
 // any_flag: out[0] = number of r < R with flags[r] != 0
 hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st);
-// `steps` explicit Euler steps of a small problem (Np 64 or 128; FP32, no
+// `steps` Euler or RK4 steps of a small problem (Np 64 or 128; FP32, no
 // resonant term, no noise) in one launch: psi_in/gam_in -> psi_out/gam_out
 // (gam_out may alias gam_in), flags[r] set if trajectory r ends non-finite.
-hipError_t launch_small_euler(bool complex_mode, const DenseStepArgs &a, int steps, hipStream_t st);
+hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps, hipStream_t st);
 
 }  // namespace gd

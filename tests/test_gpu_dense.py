@@ -316,10 +316,11 @@ def test_symmetries_on_gpu_bitwise():
     assert np.array_equal(xc, -xa) and np.array_equal(gc, ga)
 
 
-def test_small_problem_kernel_against_pinned_variant_and_profile(monkeypatch):
-    """N = 100 XY Euler (padded to 128): the fused multi-step kernel and a
-    pinned coupling-kernel variant agree to the FP32 rounding of the sums
-    after 300 steps, and profiled runs account for their coupling launches."""
+@pytest.mark.parametrize("integrator,per_step", [(gd.GD_EULER, 1), (gd.GD_RK4, 4)])
+def test_small_problem_kernel_against_pinned_variant_and_profile(monkeypatch, integrator, per_step):
+    """N = 100 XY (padded to 128): the fused multi-step kernel and a pinned
+    coupling-kernel variant agree to the FP32 rounding of the sums after 300
+    steps, and profiled runs account for their coupling evaluations."""
     n, R = 100, 37
     J = I.dense_gaussian(n, 13)
     psi0 = I.psi0_complex(n, R, 13)
@@ -327,12 +328,13 @@ def test_small_problem_kernel_against_pinned_variant_and_profile(monkeypatch):
     for pin in (None, "0"):
         if pin is not None:
             monkeypatch.setenv("GD_DENSE_CONFIG", pin)
-        with gd.Solver(J, model=gd.GD_XY, dt=0.02, eps=0.1, flags=gd.GD_F_PROFILE) as S:
+        with gd.Solver(J, model=gd.GD_XY, integrator=integrator, dt=0.02, eps=0.1,
+                       flags=gd.GD_F_PROFILE) as S:
             S.set_init(R, psi0)
             S.run(300)
             st = S.stats()
             # fused kernel: every step counted; pinned variant: every 8th step sampled
-            assert st.kernel_launches == (300 if pin is None else 38) and st.kernel_ms > 0
+            assert st.kernel_launches == per_step * (300 if pin is None else 38) and st.kernel_ms > 0
             res.append(S.state())
     (p0, g0, _), (p1, g1, _) = res
     assert _rel(p0, p1).max() < 1e-4 and _rel(g0, g1).max() < 1e-4
