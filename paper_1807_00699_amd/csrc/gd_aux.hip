@@ -1,7 +1,7 @@
 // Auxiliary kernels of libgd.so: layout conversion, readout (discretisation)
 // of the amplitudes onto the spin domains of Eq. (h), deterministic energy
 // reductions and the FP64 re-scoring of Eq. (h).
-#include "gd_internal.h"
+#include "gd_epilogue.h"
 
 #include <algorithm>
 
@@ -311,16 +311,18 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
 }
 
 // Many integration steps of a small dense problem in one launch (Np <= 128,
-// FP32 operands, no resonant term, no noise): a workgroup holds J and the
+// FP32 operands, no resonant term): a workgroup holds J and the
 // amplitudes of 256 / Np trajectories in LDS for all the steps, one thread
 // per (spin, trajectory) with its amplitude and gain in registers.  Per
 // coupling evaluation: C_ir = sum_j J_ij Psi_jr in j order (J is symmetric,
 // so lanes on consecutive i read row j contiguously), then Eq. (main) and
 // Eq. (gamma) as in the dense kernels: an explicit Euler step, or the four
-// stages of the classical RK4 step on the joint state (Psi, gamma).
+// stages of the classical RK4 step on the joint state (Psi, gamma); then the
+// noise increment of step t0 + st (amplitude a.noise_amp, key derived from
+// `seed` and the step index as on the host).
 template <bool CPLX, int NPX, bool RK4>
 __global__ void __launch_bounds__(256)
-small_step_k(DenseStepArgs a, int steps) {
+small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0) {
     constexpr int TR = 256 / NPX;
     constexpr int PL = CPLX ? 2 : 1;
     __shared__ float Js[NPX * NPX];
@@ -371,6 +373,14 @@ small_step_k(DenseStepArgs a, int steps) {
     };
     publish(x, y);
     const float dt = a.dt;
+    auto add_noise = [&](int st) {
+        if (a.noise_amp != 0.0f && valid) {
+            float g0, g1;
+            noise_pair(mix64(seed ^ mix64((unsigned long long)(t0 + st))), r, i, g0, g1);
+            x += a.noise_amp * g0;
+            if (CPLX) y += a.noise_amp * g1;
+        }
+    };
     for (int st = 0; st < steps; ++st) {
         float fr, fi, fg;
         if constexpr (!RK4) {
@@ -380,6 +390,7 @@ small_step_k(DenseStepArgs a, int steps) {
                 y = y + dt * fi;
                 g = g + dt * fg;
             }
+            add_noise(st);
             publish(x, y);
         } else {
             // stage inputs s = y + c k with c = dt/2, dt/2, dt; accumulator
@@ -410,6 +421,7 @@ small_step_k(DenseStepArgs a, int steps) {
                 y = y + c6 * (ai + fi);
                 g = g + c6 * (ag + fg);
             }
+            add_noise(st);
             publish(x, y);
         }
     }
@@ -499,12 +511,13 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
     return hipGetLastError();
 }
 
-hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps, hipStream_t st) {
+hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps,
+                              unsigned long long seed, long long t0, hipStream_t st) {
     if (steps < 1 || (a.Np != 64 && a.Np != 128)) return hipErrorInvalidValue;
     const int tr = 256 / a.Np;
     if (a.Rp % tr) return hipErrorInvalidValue;
     const dim3 grid(a.Rp / tr);
-#define GD_SMALL(C, N, K) small_step_k<C, N, K><<<grid, 256, 0, st>>>(a, steps)
+#define GD_SMALL(C, N, K) small_step_k<C, N, K><<<grid, 256, 0, st>>>(a, steps, seed, t0)
     if (a.Np == 64) {
         if (complex_mode) { if (rk4) GD_SMALL(true, 64, true); else GD_SMALL(true, 64, false); }
         else { if (rk4) GD_SMALL(false, 64, true); else GD_SMALL(false, 64, false); }

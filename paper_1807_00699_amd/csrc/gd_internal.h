@@ -163,8 +163,11 @@ hipError_t launch_make_shadow(const float *src, void *dst, long long count, int 
 // any_flag: out[0] = number of r < R with flags[r] != 0
 hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st);
 // `steps` Euler or RK4 steps of a small problem (Np 64 or 128; FP32, no
-// resonant term, no noise) in one launch: psi_in/gam_in -> psi_out/gam_out
-// (gam_out may alias gam_in), flags[r] set if trajectory r ends non-finite.
-hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps, hipStream_t st);
+// resonant term) in one launch: psi_in/gam_in -> psi_out/gam_out (gam_out
+// may alias gam_in), flags[r] set if trajectory r ends non-finite.  Noise
+// (a.noise_amp != 0): step t0 + k uses the key SplitMix64(seed ^
+// SplitMix64(t0 + k)), as the step-by-step path does.
+hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps,
+                              unsigned long long seed, long long t0, hipStream_t st);
 
 }  // namespace gd

@@ -884,11 +884,11 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const int ci = s->prm.check_interval;
     // graph replay for small problems: not with profiling events, noise (its
     // key changes every step) or GD-mod
-    // Np <= 128, FP32, no resonant term, no noise: the fused multi-step
+    // Np <= 128, FP32, no resonant term: the fused multi-step
     // kernel (one event pair per launch when profiled, counting its steps'
     // coupling evaluations as launches)
     const bool rk4 = s->integrator() == GD_RK4;
-    const bool small_ok = !s->mod() && s->prm.noise_D == 0.0 &&
+    const bool small_ok = !s->mod() &&
                           s->q_res == 0 && s->op == OP_F32 && s->Np <= 128 &&
                           std::getenv("GD_DENSE_CONFIG") == nullptr;
     const bool graph_ok = !small_ok && !timed && s->prm.noise_D == 0.0 && !s->mod() &&
@@ -911,7 +911,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 a.gam_in = s->gam;
                 a.gam_out = s->gam;
                 if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
-                GD_HIP(launch_small_steps(s->complex_mode(), rk4, a, m, s->stream));
+                if (s->prm.noise_D != 0.0) a.noise_amp = float(s->prm.noise_D * std::sqrt(double(a.dt)));
+                GD_HIP(launch_small_steps(s->complex_mode(), rk4, a, m, s->prm.noise_seed, s->steps_done + k,
+                                          s->stream));
                 if (timed && (rc = ev_end(s, m * (rk4 ? 4 : 1))) != GD_OK) return rc;
                 s->cur ^= 1;
                 k += m;

@@ -90,12 +90,14 @@ def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, **kw):
 
 # ------------------------------------------------------------------ noise (NEXT-1)
 
+@pytest.mark.parametrize("n", [300, 100])
 @pytest.mark.parametrize("model", [gd.GD_ISING, gd.GD_XY])
-def test_noise_increment_matches_oracle_numbers(model):
+def test_noise_increment_matches_oracle_numbers(model, n):
     """J = 0, Psi = 0, eps = 0: one step leaves exactly D sqrt(dt) eta; with
     dt = 0.25 and D = 2, eta itself.  Checked at step 0 and, through
-    gd_set_state, at step 12345 (the step index keys the numbers)."""
-    n, R = 300, 70
+    gd_set_state, at step 12345 (the step index keys the numbers).  n = 100
+    runs the fused small-problem kernel, n = 300 the coupling kernels."""
+    R = 70
     J = np.zeros((n, n), np.float32)
     cx = model != gd.GD_ISING
     shape = (R, n, 2) if cx else (R, n)
