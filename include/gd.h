@@ -172,9 +172,8 @@ typedef struct gd_run_stats {
                                  fastest; the environment variable GD_DENSE_CONFIG=<id>
                                  pins one instead (the set-up call then fails with
                                  GD_E_INVALID_ARG if that id does not fit).  Problems of
-                                 at most 128 padded spins (FP32, no resonant term, no
-                                 pinned variant) use a fused multi-step kernel instead
-                                 of the variants */
+                                 at most 128 padded spins (FP32, no pinned variant) use a
+                                 fused multi-step kernel instead of the variants */
 } gd_run_stats;
 
 typedef struct gd_solver gd_solver;

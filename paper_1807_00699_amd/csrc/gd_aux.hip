@@ -311,7 +311,7 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
 }
 
 // Many integration steps of a small dense problem in one launch (Np <= 128,
-// FP32 operands, no resonant term): a workgroup holds J and the
+// FP32 operands): a workgroup holds J and the
 // amplitudes of 256 / Np trajectories in LDS for all the steps, one thread
 // per (spin, trajectory) with its amplitude and gain in registers.  Per
 // coupling evaluation: C_ir = sum_j J_ij Psi_jr in j order (J is symmetric,
@@ -363,6 +363,18 @@ small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0) 
         fr = sx * lin + cr * a.inv_s + hh;
         fi = CPLX ? sy * lin + ci * a.inv_s : 0.0f;
         fg = ep * (a.rho_th - rho);
+        if (CPLX && a.q >= 2) {
+            // resonant term h_q conj(Psi)^(q-1), as in the dense kernels
+            float pr = sx, pi = -sy;
+            for (int k = 2; k < a.q; ++k) {
+                const float tr = pr * sx + pi * sy;
+                const float ti = pi * sx - pr * sy;
+                pr = tr;
+                pi = ti;
+            }
+            fr += a.hq * pr;
+            fi += a.hq * pi;
+        }
     };
     // publish amplitudes (sx, sy) once every thread has read the previous ones
     auto publish = [&](float sx, float sy) {

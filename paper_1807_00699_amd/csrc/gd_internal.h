@@ -162,8 +162,8 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
 hipError_t launch_make_shadow(const float *src, void *dst, long long count, int op, hipStream_t st);
 // any_flag: out[0] = number of r < R with flags[r] != 0
 hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st);
-// `steps` Euler or RK4 steps of a small problem (Np 64 or 128; FP32, no
-// resonant term) in one launch: psi_in/gam_in -> psi_out/gam_out (gam_out
+// `steps` Euler or RK4 steps of a small problem (Np 64 or 128; FP32) in one
+// launch: psi_in/gam_in -> psi_out/gam_out (gam_out
 // may alias gam_in), flags[r] set if trajectory r ends non-finite.  Noise
 // (a.noise_amp != 0): step t0 + k uses the key SplitMix64(seed ^
 // SplitMix64(t0 + k)), as the step-by-step path does.

@@ -884,12 +884,11 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const int ci = s->prm.check_interval;
     // graph replay for small problems: not with profiling events, noise (its
     // key changes every step) or GD-mod
-    // Np <= 128, FP32, no resonant term: the fused multi-step
+    // Np <= 128, FP32: the fused multi-step
     // kernel (one event pair per launch when profiled, counting its steps'
     // coupling evaluations as launches)
     const bool rk4 = s->integrator() == GD_RK4;
-    const bool small_ok = !s->mod() &&
-                          s->q_res == 0 && s->op == OP_F32 && s->Np <= 128 &&
+    const bool small_ok = !s->mod() && s->op == OP_F32 && s->Np <= 128 &&
                           std::getenv("GD_DENSE_CONFIG") == nullptr;
     const bool graph_ok = !small_ok && !timed && s->prm.noise_D == 0.0 && !s->mod() &&
                           (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork;
