@@ -173,8 +173,10 @@ __global__ void energy_sum_k(const double *__restrict__ partial, int ntiles, int
     E[r] = s;
 }
 
-// best = argmin_r E[r], ties -> lowest r (one workgroup).
-__global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__restrict__ best) {
+// best = argmin_r E[r], ties -> lowest r (one workgroup); best_e = E[best]
+// (one read-back for the host's check)
+__global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__restrict__ best,
+                                double *__restrict__ best_e) {
     __shared__ double sv[256];
     __shared__ int si[256];
     double bv = __builtin_inf();
@@ -197,7 +199,11 @@ __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__rest
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && best) best[0] = (si[0] == 0x7fffffff) ? 0 : si[0];
+    if (threadIdx.x == 0) {
+        const int b = (si[0] == 0x7fffffff) ? 0 : si[0];
+        if (best) best[0] = b;
+        if (best_e) best_e[0] = E[b];
+    }
 }
 
 // FP64 re-score of Eq. (h) for the discretised state, formed in FP64 from
@@ -502,7 +508,7 @@ hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R
                                 int *best, hipStream_t st) {
     if (R < 1) return hipErrorInvalidValue;
     energy_sum_k<<<(R + 255) / 256, 256, 0, st>>>(partial, ntiles, Rp, R, E);
-    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best);
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp);
     return hipGetLastError();
 }
 

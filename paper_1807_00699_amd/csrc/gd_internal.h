@@ -149,7 +149,8 @@ float clock_im_weight(int q);
 hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, int readout, int q,
                              int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
                              int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st);
-// E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r)
+// E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r),
+// E[Rp] = E[best] (E holds Rp + 1 doubles)
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
                                 int *best, hipStream_t st);
 // FP64 re-score from the FP32 amplitudes (unit phasors / signs formed in FP64):

@@ -231,7 +231,7 @@ int alloc_state(gd_solver *s, int R) {
         if (rc == GD_OK) rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadowD), pl * P);
     }
     if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 32) * s->Rp);  // smallest row tile
-    if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp);
+    if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp + 1);   // + E[best] of the last check
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
     if (rc == GD_OK) rc = dalloc(&s->dBest, 1);
     if (rc == GD_OK) rc = dalloc(&s->dCount, 1);
@@ -947,8 +947,8 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             double emin = 0.0;
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+            GD_HIP(hipMemcpyAsync(&emin, s->dE + s->Rp, sizeof(double), hipMemcpyDeviceToHost, s->stream));
             GD_HIP(hipStreamSynchronize(s->stream));
-            GD_HIP(hipMemcpy(&emin, s->dE + bi, sizeof(double), hipMemcpyDeviceToHost));
             if (emin < s->best_energy) {
                 s->best_energy = emin;
                 s->best_index = bi;
