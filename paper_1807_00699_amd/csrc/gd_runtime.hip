@@ -882,11 +882,11 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     s->ev_launches = 0;
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = s->prm.check_interval;
-    // graph replay for small problems: not with profiling events, noise (its
-    // key changes every step) or GD-mod
-    // Np <= 128, FP32: the fused multi-step
-    // kernel (one event pair per launch when profiled, counting its steps'
-    // coupling evaluations as launches)
+    // Np <= 128, FP32 (no pinned variant): the fused multi-step kernel, one
+    // event pair per launch when profiled, counting its steps' coupling
+    // evaluations as launches.  Otherwise small problems replay captured
+    // graphs, except with profiling events, noise (its key changes every
+    // step) or GD-mod.
     const bool rk4 = s->integrator() == GD_RK4;
     const bool small_ok = !s->mod() && s->op == OP_F32 && s->Np <= 128 &&
                           std::getenv("GD_DENSE_CONFIG") == nullptr;
