@@ -450,6 +450,51 @@ small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0) 
     if (r < a.R && !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(g))) a.flags[r] = 1;
 }
 
+// Device energy check of a small problem (Np <= 128) in one launch: per
+// trajectory r, E_r = sum_i [-(d0_i T0_i + w d1_i T1_i) + g_i d0_i] with d
+// the readout planes of the model (formed in FP64, held in FP32 as in the
+// coupling kernels' energy mode) and T = J d summed in FP32 in j order; the
+// terms of the Np spins are added in FP64 in a fixed order.
+template <bool CPLX, int NPX>
+__global__ void __launch_bounds__(256)
+small_energy_k(DenseStepArgs a, int ro, int q, double *__restrict__ E) {
+    constexpr int TR = 256 / NPX;
+    constexpr int PL = CPLX ? 2 : 1;
+    __shared__ float Js[NPX * NPX];
+    __shared__ float ds[PL][TR][NPX];
+    __shared__ double red[TR][NPX];
+    const int tid = threadIdx.x;
+    const int i = tid % NPX, tl = tid / NPX;
+    const int r = blockIdx.x * TR + tl;
+    const long long idx = (long long)r * NPX + i;
+    const float *J = static_cast<const float *>(a.J);
+    for (int qq = tid; qq < NPX * NPX; qq += 256) Js[qq] = J[qq];
+    double e0 = 0.0, e1 = 0.0;
+    if (r < a.R && i < a.n) {
+        int k;
+        readout_planes(a.psi_in[idx], CPLX ? a.psi_in[a.plane_stride + idx] : 0.0f, ro, q, e0, e1, k);
+    }
+    const float d0 = float(e0), d1 = float(e1);
+    ds[0][tl][i] = d0;
+    if (CPLX) ds[PL - 1][tl][i] = d1;
+    __syncthreads();
+    float t0 = 0.0f, t1 = 0.0f;
+    for (int j = 0; j < NPX; ++j) {
+        const float w = Js[j * NPX + i];
+        t0 = fmaf(w, ds[0][tl][j], t0);
+        if (CPLX) t1 = fmaf(w, ds[PL - 1][tl][j], t1);
+    }
+    double term = -(double)d0 * (double)t0 + (double)a.g[i] * (double)d0;
+    if (CPLX) term -= (double)a.im_weight * ((double)d1 * (double)t1);
+    red[tl][i] = term;
+    __syncthreads();
+    for (int w = NPX / 2; w > 0; w >>= 1) {   // fixed-order tree over the spins
+        if (i < w) red[tl][i] += red[tl][i + w];
+        __syncthreads();
+    }
+    if (i == 0 && r < a.R) E[r] = red[tl][0];
+}
+
 __global__ void make_shadow_k(const float *__restrict__ src, void *dst, long long count, int op) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < count;
          t += (long long)gridDim.x * blockDim.x)
@@ -544,6 +589,21 @@ hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &
         else { if (rk4) GD_SMALL(false, 128, true); else GD_SMALL(false, 128, false); }
     }
 #undef GD_SMALL
+    return hipGetLastError();
+}
+
+hipError_t launch_small_energy(bool complex_mode, const DenseStepArgs &a, int readout, int q, double *E,
+                               int *best, hipStream_t st) {
+    if ((a.Np != 64 && a.Np != 128) || a.R < 1) return hipErrorInvalidValue;
+    if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
+    const int tr = 256 / a.Np;
+    if (a.Rp % tr) return hipErrorInvalidValue;
+    const dim3 grid(a.Rp / tr);
+#define GD_SE(C, N) small_energy_k<C, N><<<grid, 256, 0, st>>>(a, readout, q, E)
+    if (a.Np == 64) { if (complex_mode) GD_SE(true, 64); else GD_SE(false, 64); }
+    else { if (complex_mode) GD_SE(true, 128); else GD_SE(false, 128); }
+#undef GD_SE
+    energy_argmin_k<<<1, 256, 0, st>>>(E, a.R, best, E + a.Rp);
     return hipGetLastError();
 }
 

@@ -934,16 +934,23 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         s->spin_updates += (int64_t)s->n * s->R * chunk;
         if (ci > 0 && s->steps_done % ci == 0) {
             // device check: discretise, energy GEMM, deterministic reduction
+            // (small problems: one fused launch and the argmin)
             const float *cur = s->psi[s->cur];
-            GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr,
-                                     nullptr, s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(),
-                                     s->stream));
-            DenseStepArgs a = base_args(s);
-            a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
-            a.psi_in = s->D;
-            GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
-            GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
-                                        s->stream));
+            if (small_ok) {
+                DenseStepArgs a = base_args(s);
+                a.psi_in = cur;
+                GD_HIP(launch_small_energy(s->complex_mode(), a, s->ro, s->prm.q, s->dE, s->dBest, s->stream));
+            } else {
+                GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr,
+                                         nullptr, s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(),
+                                         s->stream));
+                DenseStepArgs a = base_args(s);
+                a.B = s->op == OP_F32 ? (const void *)s->D : s->shadowD;
+                a.psi_in = s->D;
+                GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
+                GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
+                                            s->stream));
+            }
             double emin = 0.0;
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));

@@ -191,6 +191,43 @@ def test_step_graph_replay_matches_eager_bitwise(model, integrator, n, R):
     assert np.array_equal(E0, E1) and b0 == b1 and be0 == be1
 
 
+@pytest.mark.parametrize("model,n,R,q", [("ising", 64, 100, 2), ("xy", 100, 37, 0), ("potts", 90, 40, 3),
+                                         ("potts", 128, 24, 5)])
+def test_small_problem_energy_check_matches_oracle(model, n, R, q):
+    """Np <= 128 takes the fused one-launch energy check.  After a run of
+    exactly one check interval its best energy equals the oracle's Eq. (h)
+    energy of the state's readout minimised over the trajectories: exactly
+    for integer couplings and fields with Ising / q = 3 clock planes, to
+    1e-5 of sum |J| + sum |g| otherwise; its index attains that minimum."""
+    rng = I.rng(n, 77)
+    g = None
+    if model == "xy":
+        J, psi0 = I.dense_gaussian(n, 77), I.psi0_complex(n, R, 77)
+        kw = dict(model=gd.GD_XY)
+    elif model == "ising":
+        J, psi0 = I.dense_pm1(n, 77), I.psi0_real(n, R, 77)
+        kw = dict(model=gd.GD_ISING)
+    else:
+        J, psi0 = I.sparse_pm1(n, 77), I.psi0_complex(n, R, 77)
+        g = rng.integers(-2, 3, n).astype(np.float32)
+        kw = dict(model=gd.GD_POTTS, q=q, h_q=0.5)
+    with gd.Solver(J, g, integrator=gd.GD_RK4, dt=0.02, eps=0.1, check_interval=40, **kw) as S:
+        S.set_init(R, psi0)
+        S.run(40)
+        st = S.stats()
+        sp = S.spins()
+    J64 = J.astype(np.float64)
+    if model == "ising":
+        Eo = O.energy_ising(J64, sp).astype(np.float64)
+    elif model == "xy":
+        Eo = O.energy_xy(J64, sp.astype(np.float64))
+    else:
+        Eo = O.energy_potts(J64, sp, q, g.astype(np.float64))
+    tol = 0.0 if model == "ising" or q == 3 else 1e-5 * (np.abs(J64).sum() + (0 if g is None else np.abs(g).sum()))
+    assert abs(st.best_energy - Eo.min()) <= tol, (st.best_energy, Eo.min())
+    assert 0 <= st.best_index < R and Eo[st.best_index] - Eo.min() <= 2 * tol
+
+
 def test_xy3000_dense_uniform_sampled_parity():
     """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
     U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
