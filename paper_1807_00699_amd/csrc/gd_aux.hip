@@ -592,6 +592,34 @@ hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &
     return hipGetLastError();
 }
 
+// Running best over the device checks of one run, kept on the device so that
+// a run with no target does not wait for every check: seed (e0, i0), then
+// per check keep the first strict minimum of E[best] (as the host rule does).
+__global__ void best_seed_k(double *__restrict__ run_e, int *__restrict__ run_i, double e0, int i0) {
+    if (threadIdx.x == 0) {
+        run_e[0] = e0;
+        run_i[0] = i0;
+    }
+}
+
+__global__ void best_merge_k(const double *__restrict__ e, const int *__restrict__ idx,
+                             double *__restrict__ run_e, int *__restrict__ run_i) {
+    if (threadIdx.x == 0 && e[0] < run_e[0]) {
+        run_e[0] = e[0];
+        run_i[0] = idx[0];
+    }
+}
+
+hipError_t launch_best_seed(double *run_e, int *run_i, double e0, int i0, hipStream_t st) {
+    best_seed_k<<<1, 64, 0, st>>>(run_e, run_i, e0, i0);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_merge(const double *e, const int *idx, double *run_e, int *run_i, hipStream_t st) {
+    best_merge_k<<<1, 64, 0, st>>>(e, idx, run_e, run_i);
+    return hipGetLastError();
+}
+
 hipError_t launch_small_energy(bool complex_mode, const DenseStepArgs &a, int readout, int q, double *E,
                                int *best, hipStream_t st) {
     if ((a.Np != 64 && a.Np != 128) || a.R < 1) return hipErrorInvalidValue;

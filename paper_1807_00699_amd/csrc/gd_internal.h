@@ -170,6 +170,10 @@ hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st)
 // SplitMix64(t0 + k)), as the step-by-step path does.
 hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps,
                               unsigned long long seed, long long t0, hipStream_t st);
+// Running best of a run's device checks: seed with (e0, i0); merge keeps
+// (*e, *idx) when *e < *run_e.
+hipError_t launch_best_seed(double *run_e, int *run_i, double e0, int i0, hipStream_t st);
+hipError_t launch_best_merge(const double *e, const int *idx, double *run_e, int *run_i, hipStream_t st);
 // Device energy check of a small problem (Np 64 or 128) from a.psi_in with
 // readout `readout`: E[r] (r < R), best = argmin, E[Rp] = E[best].
 hipError_t launch_small_energy(bool complex_mode, const DenseStepArgs &a, int readout, int q, double *E,

@@ -231,9 +231,10 @@ int alloc_state(gd_solver *s, int R) {
         if (rc == GD_OK) rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadowD), pl * P);
     }
     if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 32) * s->Rp);  // smallest row tile
-    if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp + 1);   // + E[best] of the last check
+    // + E[best] of the last check, + running best of a run's checks
+    if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp + 2);
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
-    if (rc == GD_OK) rc = dalloc(&s->dBest, 1);
+    if (rc == GD_OK) rc = dalloc(&s->dBest, 2);   // best of the last check, running best
     if (rc == GD_OK) rc = dalloc(&s->dCount, 1);
     if (rc != GD_OK) {
         free_state(s);
@@ -892,6 +893,11 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                           std::getenv("GD_DENSE_CONFIG") == nullptr;
     const bool graph_ok = !small_ok && !timed && s->prm.noise_D == 0.0 && !s->mod() &&
                           (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork;
+    // Without a target (nothing to stop on or to time) the best energy of
+    // the checks is kept on the device and read back with the run's end.
+    const bool deferred = ci > 0 && !s->prm.has_target && !s->track_target &&
+                          !(s->prm.flags & GD_F_ASYNC);
+    if (deferred) GD_HIP(launch_best_seed(s->dE + s->Rp + 1, s->dBest + 1, s->best_energy, s->best_index, s->stream));
     int64_t done = 0;
     while (done < steps) {
         int64_t chunk = steps - done;
@@ -951,6 +957,10 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
                                             s->stream));
             }
+            if (deferred) {
+                GD_HIP(launch_best_merge(s->dE + s->Rp, s->dBest, s->dE + s->Rp + 1, s->dBest + 1, s->stream));
+                continue;
+            }
             double emin = 0.0;
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
@@ -986,8 +996,16 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     GD_HIP(launch_count_flags(s->flags, s->R, s->dCount, s->stream));
     int cnt = 0;
     GD_HIP(hipMemcpyAsync(&cnt, s->dCount, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    double run_e = s->best_energy;
+    int run_i = s->best_index;
+    if (deferred) {
+        GD_HIP(hipMemcpyAsync(&run_e, s->dE + s->Rp + 1, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        GD_HIP(hipMemcpyAsync(&run_i, s->dBest + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    }
     GD_HIP(hipStreamSynchronize(s->stream));
     s->diverged = cnt;
+    s->best_energy = run_e;
+    s->best_index = run_i;
     if (cnt) {
         char buf[64];
         std::snprintf(buf, sizeof buf, "%d trajectories became non-finite", cnt);

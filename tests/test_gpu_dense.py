@@ -228,6 +228,30 @@ def test_small_problem_energy_check_matches_oracle(model, n, R, q):
     assert 0 <= st.best_index < R and Eo[st.best_index] - Eo.min() <= 2 * tol
 
 
+@pytest.mark.parametrize("n,R", [(64, 100), (300, 70)])
+def test_deferred_best_energy_matches_per_check_readback(n, R):
+    """Without a target the best energy of the device checks stays on the
+    device until the run ends; with a target (here one never reached) the
+    host reads every check back.  Both give the same best energy and index
+    after each of three runs (130, 75, 200 steps, checks every 25), for the
+    fused small-problem path and the GEMM path."""
+    J = I.dense_pm1(n, 31)
+    psi0 = I.psi0_real(n, R, 31)
+    out = []
+    for kw in ({}, dict(has_target=1, target_energy=-1e30)):
+        seen = []
+        with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1, check_interval=25, **kw) as S:
+            S.set_init(R, psi0)
+            for k in (130, 75, 200):
+                S.run(k)
+                st = S.stats()
+                seen.append((st.best_energy, st.best_index, st.steps_done, st.target_reached))
+        out.append(seen)
+    assert [s[:3] for s in out[0]] == [s[:3] for s in out[1]], out
+    assert all(s[3] == 0 for s in out[1])
+    assert all(np.isfinite(s[0]) and 0 <= s[1] < R for s in out[0])
+
+
 def test_xy3000_dense_uniform_sampled_parity():
     """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
     U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
