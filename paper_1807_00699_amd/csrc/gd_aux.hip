@@ -174,9 +174,11 @@ __global__ void energy_sum_k(const double *__restrict__ partial, int ntiles, int
 }
 
 // best = argmin_r E[r], ties -> lowest r (one workgroup); best_e = E[best]
-// (one read-back for the host's check)
+// (one read-back for the host's check).  With run_e: the running best of a
+// run's checks keeps (E[best], best) when E[best] < *run_e.
 __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__restrict__ best,
-                                double *__restrict__ best_e) {
+                                double *__restrict__ best_e, double *__restrict__ run_e,
+                                int *__restrict__ run_i) {
     __shared__ double sv[256];
     __shared__ int si[256];
     double bv = __builtin_inf();
@@ -203,6 +205,10 @@ __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__rest
         const int b = (si[0] == 0x7fffffff) ? 0 : si[0];
         if (best) best[0] = b;
         if (best_e) best_e[0] = E[b];
+        if (run_e && E[b] < run_e[0]) {
+            run_e[0] = E[b];
+            run_i[0] = b;
+        }
     }
 }
 
@@ -316,6 +322,42 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
     if (tid < E64_T) partial[(long long)mt * Rp + r0 + tid] = red[0][tid] + red[1][tid];
 }
 
+// Device energy check of a small problem, closing the launch of its steps:
+// trajectory r's Eq. (h) energy E_r = sum_i [-(d0_i T0_i + w d1_i T1_i) +
+// g_i d0_i], d the readout planes of the model (formed in FP64, held in FP32
+// as in the coupling kernels' energy mode), T = J d summed in FP32 in j
+// order, the Np terms added in FP64 in a fixed tree.  d0s, d1s, reds: this
+// trajectory's LDS rows; every thread of the workgroup calls it.
+template <bool CPLX, int NPX>
+__device__ inline void small_energy(const DenseStepArgs &a, const float *Js, float *d0s, float *d1s,
+                                    double *reds, int i, int r, float x, float y, int ro, int q,
+                                    double *__restrict__ E) {
+    double e0 = 0.0, e1 = 0.0;
+    if (r < a.R && i < a.n) {
+        int k;
+        readout_planes(x, y, ro, q, e0, e1, k);
+    }
+    const float d0 = float(e0), d1 = float(e1);
+    d0s[i] = d0;
+    if (CPLX) d1s[i] = d1;
+    __syncthreads();
+    float t0 = 0.0f, t1 = 0.0f;
+    for (int j = 0; j < NPX; ++j) {
+        const float w = Js[j * NPX + i];
+        t0 = fmaf(w, d0s[j], t0);
+        if (CPLX) t1 = fmaf(w, d1s[j], t1);
+    }
+    double term = -(double)d0 * (double)t0 + (double)a.g[i] * (double)d0;
+    if (CPLX) term -= (double)a.im_weight * ((double)d1 * (double)t1);
+    reds[i] = term;
+    __syncthreads();
+    for (int w = NPX / 2; w > 0; w >>= 1) {
+        if (i < w) reds[i] += reds[i + w];
+        __syncthreads();
+    }
+    if (i == 0 && r < a.R) E[r] = reds[0];
+}
+
 // Many integration steps of a small dense problem in one launch (Np <= 128,
 // FP32 operands): a workgroup holds J and the
 // amplitudes of 256 / Np trajectories in LDS for all the steps, one thread
@@ -325,14 +367,18 @@ energy_fp64_k(const float *__restrict__ J, const double *__restrict__ D64, const
 // Eq. (gamma) as in the dense kernels: an explicit Euler step, or the four
 // stages of the classical RK4 step on the joint state (Psi, gamma); then the
 // noise increment of step t0 + st (amplitude a.noise_amp, key derived from
-// `seed` and the step index as on the host).
+// `seed` and the step index as on the host).  With E: the energy check of
+// the final state (readout ro, clock order q) into E[r].
 template <bool CPLX, int NPX, bool RK4>
 __global__ void __launch_bounds__(256)
-small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0) {
+small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0, int ro, int q,
+             double *E) {
     constexpr int TR = 256 / NPX;
     constexpr int PL = CPLX ? 2 : 1;
     __shared__ float Js[NPX * NPX];
     __shared__ float xs[PL][TR][NPX];
+    __shared__ float ds[PL][TR][NPX];
+    __shared__ double red[TR][NPX];
     const int tid = threadIdx.x;
     const int i = tid % NPX, tl = tid / NPX;
     const int r = blockIdx.x * TR + tl;
@@ -448,51 +494,7 @@ small_step_k(DenseStepArgs a, int steps, unsigned long long seed, long long t0) 
     a.gam_out[idx] = g;
     // non-finite values persist once they appear, so the final state tells
     if (r < a.R && !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(g))) a.flags[r] = 1;
-}
-
-// Device energy check of a small problem (Np <= 128) in one launch: per
-// trajectory r, E_r = sum_i [-(d0_i T0_i + w d1_i T1_i) + g_i d0_i] with d
-// the readout planes of the model (formed in FP64, held in FP32 as in the
-// coupling kernels' energy mode) and T = J d summed in FP32 in j order; the
-// terms of the Np spins are added in FP64 in a fixed order.
-template <bool CPLX, int NPX>
-__global__ void __launch_bounds__(256)
-small_energy_k(DenseStepArgs a, int ro, int q, double *__restrict__ E) {
-    constexpr int TR = 256 / NPX;
-    constexpr int PL = CPLX ? 2 : 1;
-    __shared__ float Js[NPX * NPX];
-    __shared__ float ds[PL][TR][NPX];
-    __shared__ double red[TR][NPX];
-    const int tid = threadIdx.x;
-    const int i = tid % NPX, tl = tid / NPX;
-    const int r = blockIdx.x * TR + tl;
-    const long long idx = (long long)r * NPX + i;
-    const float *J = static_cast<const float *>(a.J);
-    for (int qq = tid; qq < NPX * NPX; qq += 256) Js[qq] = J[qq];
-    double e0 = 0.0, e1 = 0.0;
-    if (r < a.R && i < a.n) {
-        int k;
-        readout_planes(a.psi_in[idx], CPLX ? a.psi_in[a.plane_stride + idx] : 0.0f, ro, q, e0, e1, k);
-    }
-    const float d0 = float(e0), d1 = float(e1);
-    ds[0][tl][i] = d0;
-    if (CPLX) ds[PL - 1][tl][i] = d1;
-    __syncthreads();
-    float t0 = 0.0f, t1 = 0.0f;
-    for (int j = 0; j < NPX; ++j) {
-        const float w = Js[j * NPX + i];
-        t0 = fmaf(w, ds[0][tl][j], t0);
-        if (CPLX) t1 = fmaf(w, ds[PL - 1][tl][j], t1);
-    }
-    double term = -(double)d0 * (double)t0 + (double)a.g[i] * (double)d0;
-    if (CPLX) term -= (double)a.im_weight * ((double)d1 * (double)t1);
-    red[tl][i] = term;
-    __syncthreads();
-    for (int w = NPX / 2; w > 0; w >>= 1) {   // fixed-order tree over the spins
-        if (i < w) red[tl][i] += red[tl][i + w];
-        __syncthreads();
-    }
-    if (i == 0 && r < a.R) E[r] = red[tl][0];
+    if (E) small_energy<CPLX, NPX>(a, Js, ds[0][tl], ds[PL - 1][tl], red[tl], i, r, x, y, ro, q, E);
 }
 
 __global__ void make_shadow_k(const float *__restrict__ src, void *dst, long long count, int op) {
@@ -550,10 +552,17 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
 }
 
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
-                                int *best, hipStream_t st) {
+                                int *best, hipStream_t st, double *run_e, int *run_i) {
     if (R < 1) return hipErrorInvalidValue;
     energy_sum_k<<<(R + 255) / 256, 256, 0, st>>>(partial, ntiles, Rp, R, E);
-    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp);
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_argmin(double *E, int R, int Rp, int *best, double *run_e, int *run_i,
+                                hipStream_t st) {
+    if (R < 1 || R > Rp) return hipErrorInvalidValue;
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i);
     return hipGetLastError();
 }
 
@@ -575,12 +584,14 @@ hipError_t launch_energy_fp64(const float *J, const float *psi, const float *g, 
 }
 
 hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps,
-                              unsigned long long seed, long long t0, hipStream_t st) {
+                              unsigned long long seed, long long t0, int readout, int q, double *E,
+                              hipStream_t st) {
     if (steps < 1 || (a.Np != 64 && a.Np != 128)) return hipErrorInvalidValue;
+    if (E && readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
     const int tr = 256 / a.Np;
     if (a.Rp % tr) return hipErrorInvalidValue;
     const dim3 grid(a.Rp / tr);
-#define GD_SMALL(C, N, K) small_step_k<C, N, K><<<grid, 256, 0, st>>>(a, steps, seed, t0)
+#define GD_SMALL(C, N, K) small_step_k<C, N, K><<<grid, 256, 0, st>>>(a, steps, seed, t0, readout, q, E)
     if (a.Np == 64) {
         if (complex_mode) { if (rk4) GD_SMALL(true, 64, true); else GD_SMALL(true, 64, false); }
         else { if (rk4) GD_SMALL(false, 64, true); else GD_SMALL(false, 64, false); }
@@ -593,8 +604,8 @@ hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &
 }
 
 // Running best over the device checks of one run, kept on the device so that
-// a run with no target does not wait for every check: seed (e0, i0), then
-// per check keep the first strict minimum of E[best] (as the host rule does).
+// a run with no target does not wait for every check: seeded with (e0, i0);
+// energy_argmin_k keeps the first strict minimum of E[best] (the host rule).
 __global__ void best_seed_k(double *__restrict__ run_e, int *__restrict__ run_i, double e0, int i0) {
     if (threadIdx.x == 0) {
         run_e[0] = e0;
@@ -602,36 +613,8 @@ __global__ void best_seed_k(double *__restrict__ run_e, int *__restrict__ run_i,
     }
 }
 
-__global__ void best_merge_k(const double *__restrict__ e, const int *__restrict__ idx,
-                             double *__restrict__ run_e, int *__restrict__ run_i) {
-    if (threadIdx.x == 0 && e[0] < run_e[0]) {
-        run_e[0] = e[0];
-        run_i[0] = idx[0];
-    }
-}
-
 hipError_t launch_best_seed(double *run_e, int *run_i, double e0, int i0, hipStream_t st) {
     best_seed_k<<<1, 64, 0, st>>>(run_e, run_i, e0, i0);
-    return hipGetLastError();
-}
-
-hipError_t launch_best_merge(const double *e, const int *idx, double *run_e, int *run_i, hipStream_t st) {
-    best_merge_k<<<1, 64, 0, st>>>(e, idx, run_e, run_i);
-    return hipGetLastError();
-}
-
-hipError_t launch_small_energy(bool complex_mode, const DenseStepArgs &a, int readout, int q, double *E,
-                               int *best, hipStream_t st) {
-    if ((a.Np != 64 && a.Np != 128) || a.R < 1) return hipErrorInvalidValue;
-    if (readout == RO_CLOCK && (q < 2 || q > 8)) return hipErrorInvalidValue;
-    const int tr = 256 / a.Np;
-    if (a.Rp % tr) return hipErrorInvalidValue;
-    const dim3 grid(a.Rp / tr);
-#define GD_SE(C, N) small_energy_k<C, N><<<grid, 256, 0, st>>>(a, readout, q, E)
-    if (a.Np == 64) { if (complex_mode) GD_SE(true, 64); else GD_SE(false, 64); }
-    else { if (complex_mode) GD_SE(true, 128); else GD_SE(false, 128); }
-#undef GD_SE
-    energy_argmin_k<<<1, 256, 0, st>>>(E, a.R, best, E + a.Rp);
     return hipGetLastError();
 }
 

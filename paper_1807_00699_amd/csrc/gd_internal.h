@@ -150,9 +150,13 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
                              int8_t *spins8, float *angle, int32_t *states, int *flags, int n, int R,
                              int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st);
 // E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r),
-// E[Rp] = E[best] (E holds Rp + 1 doubles)
+// E[Rp] = E[best] (E holds Rp + 1 doubles); with run_e, the running best of a
+// run's checks (*run_e, *run_i) takes (E[best], best) when E[best] < *run_e
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
-                                int *best, hipStream_t st);
+                                int *best, hipStream_t st, double *run_e = nullptr, int *run_i = nullptr);
+// The argmin and running-best part of launch_energy_reduce for E[r] already formed
+hipError_t launch_energy_argmin(double *E, int R, int Rp, int *best, double *run_e, int *run_i,
+                                hipStream_t st);
 // FP64 re-score from the FP32 amplitudes (unit phasors / signs formed in FP64):
 // partial[t][r] = sum_{i in tile t} [-Re(conj(d_i) (J d)_i) + g_i Re(d_i)]
 // D64: scratch for the FP64 readout planes, nplanes * Rp * Np doubles
@@ -167,16 +171,12 @@ hipError_t launch_count_flags(const int *flags, int R, int *out, hipStream_t st)
 // launch: psi_in/gam_in -> psi_out/gam_out (gam_out
 // may alias gam_in), flags[r] set if trajectory r ends non-finite.  Noise
 // (a.noise_amp != 0): step t0 + k uses the key SplitMix64(seed ^
-// SplitMix64(t0 + k)), as the step-by-step path does.
+// SplitMix64(t0 + k)), as the step-by-step path does.  With E: the Eq. (h)
+// energies of the final state's readout (readout, q) into E[r], r < R.
 hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &a, int steps,
-                              unsigned long long seed, long long t0, hipStream_t st);
-// Running best of a run's device checks: seed with (e0, i0); merge keeps
-// (*e, *idx) when *e < *run_e.
+                              unsigned long long seed, long long t0, int readout, int q, double *E,
+                              hipStream_t st);
+// Running best of a run's device checks: (*run_e, *run_i) = (e0, i0)
 hipError_t launch_best_seed(double *run_e, int *run_i, double e0, int i0, hipStream_t st);
-hipError_t launch_best_merge(const double *e, const int *idx, double *run_e, int *run_i, hipStream_t st);
-// Device energy check of a small problem (Np 64 or 128) from a.psi_in with
-// readout `readout`: E[r] (r < R), best = argmin, E[Rp] = E[best].
-hipError_t launch_small_energy(bool complex_mode, const DenseStepArgs &a, int readout, int q, double *E,
-                               int *best, hipStream_t st);
 
 }  // namespace gd

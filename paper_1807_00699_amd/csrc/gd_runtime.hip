@@ -906,6 +906,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             chunk = std::min<int64_t>(chunk, to_check);
         }
         int64_t k = 0;
+        const bool check_due = ci > 0 && (s->steps_done + chunk) % ci == 0;
         if (small_ok) {
             // all steps of the chunk in LDS, a bounded number per launch
             while (k < chunk) {
@@ -917,8 +918,10 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 a.gam_out = s->gam;
                 if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
                 if (s->prm.noise_D != 0.0) a.noise_amp = float(s->prm.noise_D * std::sqrt(double(a.dt)));
+                // the launch that ends at a check also forms its energies
+                double *E = (check_due && k + m == chunk) ? s->dE : nullptr;
                 GD_HIP(launch_small_steps(s->complex_mode(), rk4, a, m, s->prm.noise_seed, s->steps_done + k,
-                                          s->stream));
+                                          s->ro, s->prm.q, E, s->stream));
                 if (timed && (rc = ev_end(s, m * (rk4 ? 4 : 1))) != GD_OK) return rc;
                 s->cur ^= 1;
                 k += m;
@@ -940,12 +943,12 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         s->spin_updates += (int64_t)s->n * s->R * chunk;
         if (ci > 0 && s->steps_done % ci == 0) {
             // device check: discretise, energy GEMM, deterministic reduction
-            // (small problems: one fused launch and the argmin)
+            // (small problems: energies from the last step launch, the argmin)
             const float *cur = s->psi[s->cur];
+            double *run_e = deferred ? s->dE + s->Rp + 1 : nullptr;
+            int *run_i = deferred ? s->dBest + 1 : nullptr;
             if (small_ok) {
-                DenseStepArgs a = base_args(s);
-                a.psi_in = cur;
-                GD_HIP(launch_small_energy(s->complex_mode(), a, s->ro, s->prm.q, s->dE, s->dBest, s->stream));
+                GD_HIP(launch_energy_argmin(s->dE, s->R, s->Rp, s->dBest, run_e, run_i, s->stream));
             } else {
                 GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr,
                                          nullptr, s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(),
@@ -955,12 +958,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 a.psi_in = s->D;
                 GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
                 GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
-                                            s->stream));
+                                            s->stream, run_e, run_i));
             }
-            if (deferred) {
-                GD_HIP(launch_best_merge(s->dE + s->Rp, s->dBest, s->dE + s->Rp + 1, s->dBest + 1, s->stream));
-                continue;
-            }
+            if (deferred) continue;
             double emin = 0.0;
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
