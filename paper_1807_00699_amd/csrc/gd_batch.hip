@@ -178,6 +178,46 @@ hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax) {
     return hipErrorInvalidValue;
 }
 
+// Running best of a batch run's checks, one workgroup per instance k: the
+// lowest E[k][r] (ties -> lowest r) replaces (best_E[k], best_r[k]) when it
+// is strictly lower, as when the host reads every check back.
+__global__ void __launch_bounds__(256)
+batch_best_k(const double *__restrict__ E, int R, double *__restrict__ best_E, int *__restrict__ best_r) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    double bv = __builtin_inf();
+    int bi = 0x7fffffff;
+    for (int r = tid; r < R; r += 256) {
+        const double s = E[(long long)k * R + r];
+        if (s < bv || (s == bv && r < bi)) { bv = s; bi = r; }
+    }
+    sv[tid] = bv;
+    si[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double ov = sv[tid + w];
+            const int oi = si[tid + w];
+            if (ov < sv[tid] || (ov == sv[tid] && oi < si[tid])) {
+                sv[tid] = ov;
+                si[tid] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && si[0] != 0x7fffffff && sv[0] < best_E[k]) {
+        best_E[k] = sv[0];
+        best_r[k] = si[0];
+    }
+}
+
+hipError_t launch_batch_best(const double *E, int K, int R, double *best_E, int *best_r, hipStream_t st) {
+    if (K < 1 || R < 1) return hipErrorInvalidValue;
+    batch_best_k<<<K, 256, 0, st>>>(E, R, best_E, best_r);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipStream_t st) {
     const size_t lds = batch_lds_bytes(c, a.nmax, a.dmax);
 #define GD_CASE(id, t, nt, e)                                           \

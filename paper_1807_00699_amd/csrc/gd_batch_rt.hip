@@ -81,6 +81,8 @@ struct BatchSolver {
     bool have_state = false;
     float *d_x = nullptr, *d_gam = nullptr, *d_D = nullptr;
     double *d_E = nullptr;
+    double *d_best_E = nullptr;   // running best of a run's checks (no targets)
+    int *d_best_r = nullptr;
     int *d_flags = nullptr;
     int8_t *d_spins = nullptr;
     // schedule
@@ -114,11 +116,12 @@ void free_schedule(BatchSolver *b) {
 
 void free_state(BatchSolver *b) {
     free_schedule(b);
-    void *ps[] = {b->d_x, b->d_gam, b->d_D, b->d_E, b->d_flags, b->d_spins};
+    void *ps[] = {b->d_x, b->d_gam, b->d_D, b->d_E, b->d_best_E, b->d_best_r, b->d_flags, b->d_spins};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     b->d_x = b->d_gam = b->d_D = nullptr;
-    b->d_E = nullptr;
+    b->d_E = b->d_best_E = nullptr;
+    b->d_best_r = nullptr;
     b->d_flags = nullptr;
     b->d_spins = nullptr;
     b->have_state = false;
@@ -273,6 +276,8 @@ int alloc_state(BatchSolver *b, int R) {
     if (rc == GD_OK) rc = dmalloc(&b->d_D, st);
     if (rc == GD_OK) rc = dmalloc(&b->d_spins, st);
     if (rc == GD_OK) rc = dmalloc(&b->d_E, (size_t)b->K * R);
+    if (rc == GD_OK) rc = dmalloc(&b->d_best_E, (size_t)b->K);
+    if (rc == GD_OK) rc = dmalloc(&b->d_best_r, (size_t)b->K);
     if (rc == GD_OK) rc = dmalloc(&b->d_flags, (size_t)b->K * R);
     if (rc != GD_OK) {
         free_state(b);
@@ -511,6 +516,15 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = b->prm.check_interval;
     const bool track = !b->targets.empty();
+    // Without targets (no time to record) the best of the checks is kept on
+    // the device and read back once, at the end of the run.
+    const bool deferred = ci > 0 && !track;
+    if (deferred) {
+        GD_TRY(hipMemcpyAsync(b->d_best_E, b->best_E.data(), b->K * sizeof(double), hipMemcpyHostToDevice,
+                              b->stream));
+        GD_TRY(hipMemcpyAsync(b->d_best_r, b->best_r.data(), b->K * sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
+    }
     int64_t done = 0;
     std::vector<double> E;
     while (done < steps) {
@@ -538,7 +552,9 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
         done += cs;
         b->steps_done += cs;
         b->spin_updates += (int64_t)b->total * b->R * cs;
-        if (ci > 0) {
+        if (deferred) {
+            GD_TRY(launch_batch_best(b->d_E, b->K, b->R, b->d_best_E, b->d_best_r, b->stream));
+        } else if (ci > 0) {
             E.resize((size_t)b->K * b->R);
             GD_TRY(hipMemcpyAsync(E.data(), b->d_E, E.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   b->stream));
@@ -561,6 +577,12 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
             }
             if (track && all && b->prm.has_target) break;   // every instance reached its target
         }
+    }
+    if (deferred) {
+        GD_TRY(hipMemcpyAsync(b->best_E.data(), b->d_best_E, b->K * sizeof(double), hipMemcpyDeviceToHost,
+                              b->stream));
+        GD_TRY(hipMemcpyAsync(b->best_r.data(), b->d_best_r, b->K * sizeof(int), hipMemcpyDeviceToHost,
+                              b->stream));
     }
     GD_TRY(hipStreamSynchronize(b->stream));
     b->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

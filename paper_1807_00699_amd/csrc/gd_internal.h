@@ -123,6 +123,9 @@ BatchConfig batch_config(int idx);
 size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax);
 hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax);   // once per variant, outside capture
 hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipStream_t st);
+// Per instance k < K: (best_E[k], best_r[k]) takes the lowest E[k * R + r]
+// (ties -> lowest r) when it is strictly lower
+hipError_t launch_batch_best(const double *E, int K, int R, double *best_E, int *best_r, hipStream_t st);
 
 // ---- auxiliary kernels (gd_aux.hip)
 // user [R][n] (or [R][n][2]) -> zero-padded planes [P][Rp][Np]

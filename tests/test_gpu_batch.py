@@ -218,3 +218,30 @@ def test_batch_errors():
         with pytest.raises(gd.GDError) as ei:
             B.energy()
         assert ei.value.code == gd.GD_E_STATE
+
+
+def test_batch_deferred_best_matches_per_check_readback():
+    """Without targets the per-instance best of the checks stays on the
+    device until the run ends; with targets (here never reached) the host
+    reads every check.  Same per-instance best energies and the same overall
+    best after each of three runs (130, 75, 200 steps, checks every 25: the
+    last chunk of a run is shorter and is checked too)."""
+    sizes = [64, 130, 258, 96]
+    R = 16
+    insts, _ = _instances(sizes, 41)
+    x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 41)])
+    out = []
+    for tracked in (False, True):
+        seen = []
+        with gd.BatchSolver(insts, check_interval=25) as B:
+            if tracked:
+                B.set_targets(np.full(len(sizes), -1e30))
+            B.set_init(R, x0)
+            for k in (130, 75, 200):
+                B.run(k)
+                _, _, be = B.ttt()
+                st = B.stats()
+                seen.append((be.tolist(), st.best_energy, st.best_index, st.steps_done))
+        out.append(seen)
+    assert out[0] == out[1], out
+    assert all(np.all(np.isfinite(s[0])) for s in out[0])
