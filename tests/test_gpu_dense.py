@@ -192,13 +192,15 @@ def test_step_graph_replay_matches_eager_bitwise(model, integrator, n, R):
 
 
 @pytest.mark.parametrize("model,n,R,q", [("ising", 64, 100, 2), ("xy", 100, 37, 0), ("potts", 90, 40, 3),
-                                         ("potts", 128, 24, 5)])
+                                         ("potts", 128, 24, 5), ("ising_complex", 100, 30, 2),
+                                         ("potts", 100, 33, 4), ("potts", 64, 50, 6)])
 def test_small_problem_energy_check_matches_oracle(model, n, R, q):
-    """Np <= 128 takes the fused one-launch energy check.  After a run of
-    exactly one check interval its best energy equals the oracle's Eq. (h)
-    energy of the state's readout minimised over the trajectories: exactly
-    for integer couplings and fields with Ising / q = 3 clock planes, to
-    1e-5 of sum |J| + sum |g| otherwise; its index attains that minimum."""
+    """Np <= 128: the launch of the steps that ends at a check also forms the
+    energies.  After a run of exactly one check interval the best energy
+    equals the oracle's Eq. (h) energy of the state's readout minimised over
+    the trajectories: exactly for integer couplings and fields with sign
+    readouts or q in {3, 4, 6} clock planes, to 1e-5 of sum |J| + sum |g|
+    otherwise; its index attains that minimum."""
     rng = I.rng(n, 77)
     g = None
     if model == "xy":
@@ -207,6 +209,9 @@ def test_small_problem_energy_check_matches_oracle(model, n, R, q):
     elif model == "ising":
         J, psi0 = I.dense_pm1(n, 77), I.psi0_real(n, R, 77)
         kw = dict(model=gd.GD_ISING)
+    elif model == "ising_complex":
+        J, psi0 = I.dense_pm1(n, 77), I.psi0_complex(n, R, 77)
+        kw = dict(model=gd.GD_ISING_COMPLEX)      # automatic h_2
     else:
         J, psi0 = I.sparse_pm1(n, 77), I.psi0_complex(n, R, 77)
         g = rng.integers(-2, 3, n).astype(np.float32)
@@ -217,13 +222,14 @@ def test_small_problem_energy_check_matches_oracle(model, n, R, q):
         st = S.stats()
         sp = S.spins()
     J64 = J.astype(np.float64)
-    if model == "ising":
+    if model in ("ising", "ising_complex"):
         Eo = O.energy_ising(J64, sp).astype(np.float64)
     elif model == "xy":
         Eo = O.energy_xy(J64, sp.astype(np.float64))
     else:
         Eo = O.energy_potts(J64, sp, q, g.astype(np.float64))
-    tol = 0.0 if model == "ising" or q == 3 else 1e-5 * (np.abs(J64).sum() + (0 if g is None else np.abs(g).sum()))
+    scale = np.abs(J64).sum() + (0 if g is None else np.abs(g).sum())
+    tol = 0.0 if model in ("ising", "ising_complex") or q in (3, 4, 6) else 1e-5 * scale
     assert abs(st.best_energy - Eo.min()) <= tol, (st.best_energy, Eo.min())
     assert 0 <= st.best_index < R and Eo[st.best_index] - Eo.min() <= 2 * tol
 
