@@ -750,7 +750,8 @@ def main():
     flops_launch = 2.0 * n * n * P * R          # coupling GEMM of one launch
     # padded sizes of at most 128 spins, FP32: the runtime runs many steps per
     # launch of its fused small-problem kernel (FP32 vector ALUs); its events
-    # then bracket whole launches and count their coupling evaluations
+    # then bracket whole launches and count their coupling evaluations (the
+    # J d of an energy check closing a launch is one more)
     small = (-(-n // 64) * 64 <= 128 and prec_name == "fp32")
     achieved = flops_launch / avg_s / 1e12
     out = {

@@ -105,7 +105,10 @@ typedef enum gd_variant { GD_VARIANT_GD = 0, GD_VARIANT_MOD = 1 } gd_variant;
 #define GD_F_DEVICE_PTRS 0x1u  /* array arguments are device pointers */
 #define GD_F_ASYNC 0x2u        /* gd_run returns without synchronising the stream */
 #define GD_F_PROFILE 0x4u      /* time the coupling launches of every 8th step with one HIP event
-                                  pair per step (kernel_ms / kernel_launches = mean launch time) */
+                                  pair per step (kernel_ms / kernel_launches = mean launch time);
+                                  the fused small-problem kernel is timed per launch and counts
+                                  its coupling evaluations (steps x stages, + 1 for an energy
+                                  check that closes the launch) as launches */
 
 /* Parameters of a solver.  Fill with gd_default_params(), then override.
  * struct_size must be sizeof(gd_params) of the caller's header. */

@@ -884,8 +884,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = s->prm.check_interval;
     // Np <= 128, FP32 (no pinned variant): the fused multi-step kernel, one
-    // event pair per launch when profiled, counting its steps' coupling
-    // evaluations as launches.  Otherwise small problems replay captured
+    // event pair per launch when profiled, counting its coupling evaluations
+    // (those of its steps, and J d of an energy check that closes it) as
+    // launches.  Otherwise small problems replay captured
     // graphs, except with profiling events, noise (its key changes every
     // step) or GD-mod.
     const bool rk4 = s->integrator() == GD_RK4;
@@ -922,7 +923,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 double *E = (check_due && k + m == chunk) ? s->dE : nullptr;
                 GD_HIP(launch_small_steps(s->complex_mode(), rk4, a, m, s->prm.noise_seed, s->steps_done + k,
                                           s->ro, s->prm.q, E, s->stream));
-                if (timed && (rc = ev_end(s, m * (rk4 ? 4 : 1))) != GD_OK) return rc;
+                if (timed && (rc = ev_end(s, m * (rk4 ? 4 : 1) + (E ? 1 : 0))) != GD_OK) return rc;
                 s->cur ^= 1;
                 k += m;
             }
