@@ -523,6 +523,16 @@ inline int grid_for(long long total) {
     return int(b);
 }
 
+// Running best over the device checks of one run, kept on the device so that
+// a run with no target does not wait for every check: seeded with (e0, i0);
+// energy_argmin_k keeps the first strict minimum of E[best] (the host rule).
+__global__ void best_seed_k(double *__restrict__ run_e, int *__restrict__ run_i, double e0, int i0) {
+    if (threadIdx.x == 0) {
+        run_e[0] = e0;
+        run_i[0] = i0;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pack_planes(const float *user, float *planes, int n, int R, int Np, int Rp,
@@ -601,16 +611,6 @@ hipError_t launch_small_steps(bool complex_mode, bool rk4, const DenseStepArgs &
     }
 #undef GD_SMALL
     return hipGetLastError();
-}
-
-// Running best over the device checks of one run, kept on the device so that
-// a run with no target does not wait for every check: seeded with (e0, i0);
-// energy_argmin_k keeps the first strict minimum of E[best] (the host rule).
-__global__ void best_seed_k(double *__restrict__ run_e, int *__restrict__ run_i, double e0, int i0) {
-    if (threadIdx.x == 0) {
-        run_e[0] = e0;
-        run_i[0] = i0;
-    }
 }
 
 hipError_t launch_best_seed(double *run_e, int *run_i, double e0, int i0, hipStream_t st) {
