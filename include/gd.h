@@ -228,8 +228,10 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
  * continue.  With check_interval > 0 the discretised energies are evaluated
  * on the device every check_interval steps; with has_target the run stops at
  * the first check where min_r E_r <= target_energy (gd_stats.ttt_*).  The
- * host waits for each check only with a target (has_target or
- * gd_set_targets) or GD_F_ASYNC; otherwise the best energy of the checks is
+ * host waits for each check only with has_target or GD_F_ASYNC.  A target
+ * recorded by gd_set_targets is compared one check later, while the next
+ * steps run, and its ttt_seconds are device time from the start of the
+ * gd_run call (HIP events); with no target the best energy of the checks is
  * kept on the device and reaches gd_stats when the run ends.
  * Returns GD_E_DIVERGED if any trajectory is non-finite at the end.
  */

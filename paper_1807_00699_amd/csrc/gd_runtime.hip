@@ -143,6 +143,15 @@ struct gd_solver {
     double ttt_seconds = 0.0, best_energy = HUGE_VAL;
     int64_t ttt_steps = 0;
     std::vector<hipEvent_t> events;
+    // time-to-target recording without a stop: each check's (E[best], best)
+    // lands in pinned host slots behind an event, read one check later
+    struct CheckSlot {
+        double e;
+        int i;
+    };
+    CheckSlot *hchk = nullptr;            // 2 slots (hipHostMalloc)
+    hipEvent_t ev_chk[2] = {nullptr, nullptr};
+    hipEvent_t ev_run0 = nullptr;         // start of the current gd_run
     int64_t ev_used = 0;       // event pairs recorded by the current gd_run call
     int64_t ev_launches = 0;   // coupling launches bracketed by those pairs
     // small problems: kGraphSteps steps captured once in a hipGraph (launch
@@ -785,6 +794,9 @@ void gd_destroy(gd_solver *s) {
     if (s->dG) (void)hipFree(s->dG);
     if (s->dJlp) (void)hipFree(s->dJlp);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {s->ev_chk[0], s->ev_chk[1], s->ev_run0})
+        if (e) (void)hipEventDestroy(e);
+    if (s->hchk) (void)hipHostFree(s->hchk);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -899,6 +911,44 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const bool deferred = ci > 0 && !s->prm.has_target && !s->track_target &&
                           !(s->prm.flags & GD_F_ASYNC);
     if (deferred) GD_HIP(launch_best_seed(s->dE + s->Rp + 1, s->dBest + 1, s->best_energy, s->best_index, s->stream));
+    // Recording the time to target without stopping: each check is read back
+    // one check later (the next chunk is queued meanwhile) and timed by
+    // events from the start of the run.
+    const bool lookahead = ci > 0 && s->track_target && !s->prm.has_target &&
+                           !(s->prm.flags & GD_F_ASYNC);
+    int pend = -1;              // slot of the check not yet read, or -1
+    int64_t pend_step = 0;
+    if (lookahead) {
+        if (!s->hchk) GD_HIP(hipHostMalloc(reinterpret_cast<void **>(&s->hchk), 2 * sizeof(gd_solver::CheckSlot)));
+        for (hipEvent_t *e : {&s->ev_chk[0], &s->ev_chk[1], &s->ev_run0})
+            if (!*e) GD_HIP(hipEventCreate(e));
+        GD_HIP(hipEventRecord(s->ev_run0, s->stream));
+    }
+    const double run_s0 = s->run_seconds;
+    // host rule of a check read back: best energy, first check at the
+    // target (returns true at that check)
+    auto take_check = [&](double emin, int bi, int64_t step, double seconds) -> bool {
+        if (emin < s->best_energy) {
+            s->best_energy = emin;
+            s->best_index = bi;
+        }
+        if ((s->prm.has_target || s->track_target) && !s->target_reached && emin <= s->prm.target_energy) {
+            s->target_reached = 1;
+            s->ttt_steps = step;
+            s->ttt_seconds = seconds;
+            return true;
+        }
+        return false;
+    };
+    auto read_pending = [&]() -> int {
+        if (pend < 0) return GD_OK;
+        GD_HIP(hipEventSynchronize(s->ev_chk[pend]));
+        float ms = 0.0f;
+        GD_HIP(hipEventElapsedTime(&ms, s->ev_run0, s->ev_chk[pend]));
+        take_check(s->hchk[pend].e, s->hchk[pend].i, pend_step, run_s0 + ms * 1e-3);
+        pend = -1;
+        return GD_OK;
+    };
     int64_t done = 0;
     while (done < steps) {
         int64_t chunk = steps - done;
@@ -962,26 +1012,30 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                                             s->stream, run_e, run_i));
             }
             if (deferred) continue;
+            if (lookahead) {
+                const int slot = pend == 0 ? 1 : 0;
+                GD_HIP(hipMemcpyAsync(&s->hchk[slot].e, s->dE + s->Rp, sizeof(double), hipMemcpyDeviceToHost,
+                                      s->stream));
+                GD_HIP(hipMemcpyAsync(&s->hchk[slot].i, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+                GD_HIP(hipEventRecord(s->ev_chk[slot], s->stream));
+                if ((rc = read_pending()) != GD_OK) return rc;
+                pend = slot;
+                pend_step = s->steps_done;
+                continue;
+            }
             double emin = 0.0;
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
             GD_HIP(hipMemcpyAsync(&emin, s->dE + s->Rp, sizeof(double), hipMemcpyDeviceToHost, s->stream));
             GD_HIP(hipStreamSynchronize(s->stream));
-            if (emin < s->best_energy) {
-                s->best_energy = emin;
-                s->best_index = bi;
-            }
-            if ((s->prm.has_target || s->track_target) && !s->target_reached &&
-                emin <= s->prm.target_energy) {
-                s->target_reached = 1;
-                s->ttt_steps = s->steps_done;
-                s->ttt_seconds = s->run_seconds +
-                                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                if (s->prm.has_target) break;
-            }
+            const bool hit = take_check(emin, bi, s->steps_done,
+                                        s->run_seconds +
+                                            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            if (hit && s->prm.has_target) break;
         }
     }
     if (s->prm.flags & GD_F_ASYNC) return GD_OK;
+    if ((rc = read_pending()) != GD_OK) return rc;
     GD_HIP(hipStreamSynchronize(s->stream));
     s->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (timed) {

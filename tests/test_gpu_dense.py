@@ -258,6 +258,37 @@ def test_deferred_best_energy_matches_per_check_readback(n, R):
     assert all(np.isfinite(s[0]) and 0 <= s[1] < R for s in out[0])
 
 
+@pytest.mark.parametrize("n,R", [(64, 100), (300, 70)])
+def test_recorded_target_read_one_check_later(n, R):
+    """With a recorded target (gd_set_targets, no stop) each check is read
+    back one check later, timed by events.  Against the per-check minima of
+    the FP64 re-score (exact for +-1 couplings) taken every 25 steps: the
+    best energy is their minimum and the time-to-target step is the first
+    check at the target, also when that check is the last of a run and is
+    read at the run's end (runs of 130 and 170 steps)."""
+    J = I.dense_pm1(n, 57)
+    psi0 = I.psi0_real(n, R, 57)
+    mins = []
+    with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1) as S:
+        S.set_init(R, psi0)
+        for _ in range(12):
+            S.run(25)
+            E, b = S.energy()
+            mins.append(float(E[b]))
+    mins = np.array(mins)
+    for target in (mins[4], mins.min()):
+        first = int(np.argmax(mins <= target))
+        with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1, check_interval=25) as S:
+            S.set_init(R, psi0)
+            gd.gd_set_targets(S.h, [target])
+            S.run(130)
+            S.run(170)
+            st = S.stats()
+        assert st.best_energy == mins.min()
+        assert st.target_reached == 1 and st.ttt_steps == 25 * (first + 1), (st.ttt_steps, first)
+        assert 0 < st.ttt_seconds <= st.run_seconds
+
+
 def test_xy3000_dense_uniform_sampled_parity():
     """N = 3000 (ragged: 3000 = 46 x 64 + 56) with the paper's 'dense'
     U[-10, 10] couplings, R = 20 (padded to one trajectory tile), RK4
