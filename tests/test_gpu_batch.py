@@ -1,8 +1,10 @@
 """Batched uneven instances (sparse couplings, one persistent launch, hipGraph
 replay, autotuned variant) against the FP64 oracle, instance by instance.
 
-The amplitude/gain bar is the one of the dense tests (per trajectory
-max(1e-4, 4 x the oracle's own float32-vs-float64 distance), >= 90% under 1e-4).
+The amplitude/gain bar is the one of the dense tests (tests/_parity.py: per
+trajectory 1e-4, or 4x the oracle's own float32-vs-float64 distance where the
+dynamics amplify rounding; >= 90% of all trajectories under 1e-4; the count
+reported).  The oracle computes each instance's coupling scale itself.
 Energies of the discretised state are integer-exact.  A trajectory's result
 must not depend on the rest of the batch, on the kernel variant or on how the
 steps are chunked into graph replays: those comparisons are bitwise.
@@ -15,6 +17,8 @@ import pytest
 from oracle import oracle as O
 from paper_1807_00699_amd import gd
 from paper_1807_00699_amd import inputs as I
+
+import _parity as P
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -76,10 +80,10 @@ def test_batch_parity_against_oracle_per_instance():
                 fx[k], fg[k] = O.run_f32(J, fx[k], fg[k], model="ising", steps=st - prev, dt=0.05, eps=0.1)
                 ep = _rel(B.split(xs)[k], ox[k])
                 eg = _rel(B.split(gs)[k], og[k])
-                bound = np.maximum(TOL, 4 * np.maximum(_rel(fx[k], ox[k]), _rel(fg[k], og[k])))
-                assert np.all(ep <= bound) and np.all(eg <= bound), (st, k, ep.max(), eg.max())
+                floor = np.maximum(_rel(fx[k], ox[k]), _rel(fg[k], og[k]))
+                P.check(ep, eg, floor, min_strict=0.0, label=f"instance {k} n={sizes[k]} step {st}")
                 strict.append((ep <= TOL) & (eg <= TOL))
-            assert np.mean(np.concatenate(strict)) >= 0.85, st
+            assert np.mean(np.concatenate(strict)) >= 0.9, st
             prev = st
         E, best = B.energy()
         sp = B.split(B.spins())

@@ -1,16 +1,13 @@
 """GPU parity of the dense path (libgd.so through its C ABI) against the FP64
 oracle on the same seeded inputs.
 
-Amplitude/gain parity (reading of the 1e-4 relative bar): per trajectory,
-  max_i |psi_gpu - psi_orc| / max_i |psi_orc| <= 1e-4, same for gamma,
-at steps {1, 10, 50, 100, 200}.  The GPU integrates in FP32 and the oracle in
-FP64, so the bar measures the FP32 rounding carried by the dynamics.  Some
-trajectories pass close to an unstable point where the dynamics amplify any
-single-precision rounding past 1e-4; for those the oracle's own float32
-integration (oracle.run_f32, a different summation order) shows the same
-excursion.  Each trajectory r is therefore held to max(1e-4, 4 * floor_r),
-with floor_r the float32-vs-float64 distance of the oracle, and at least 90%
-of the trajectories must meet 1e-4 itself.
+Amplitude/gain parity follows tests/_parity.py: per trajectory, max-norm
+relative error <= 1e-4 of psi and gamma at steps {1, 10, 50, 100, 200}; a
+trajectory whose FP32 rounding the dynamics amplify (the oracle's own float32
+run shows it) may be held to 4x that floor, and every check reports how many
+needed it.  The Ising N = 64, R = 100 workload and the sampled XY N = 1024,
+R = 1024 workload are held to 1e-4 outright.  The coupling scale s is the
+oracle's own (checked against the library's).
 Integer results (discretised spins, integer-J energies) are compared
 bit-exactly, with both sides deciding from the same FP32 state.
 """
@@ -23,62 +20,64 @@ from oracle import oracle as O
 from paper_1807_00699_amd import gd
 from paper_1807_00699_amd import inputs as I
 
+import _parity as P
+
 pytestmark = pytest.mark.gpu
 
 SNAP = (1, 10, 50, 100, 200)
-TOL = 1e-4
+TOL = P.TOL
+_rel = P.rel
 
 
-def _rel(a, b):
-    """per-trajectory max-norm relative error, arrays [R][...]"""
-    R = a.shape[0]
-    a = a.reshape(R, -1).astype(np.float64)
-    b = b.reshape(R, -1).astype(np.float64)
-    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-30)
+def oracle_scale(J, S):
+    """the oracle's coupling scale, checked against the one the library uses"""
+    s = O.coupling_scale(np.asarray(J, np.float64))
+    assert abs(s - S.scale) <= 1e-12 * s, (s, S.scale)
+    return s
 
 
 def _parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, g=None, eps=0.1, R_sub=None,
-                oracle_threads=None, **kw):
+                oracle_threads=None, strict=False, max_used=None, **kw):
     n = J.shape[0]
     mdl = gd.GD_ISING if model == "ising" else gd.GD_XY
+    okw = {k: v for k, v in kw.items() if k in ("rho_th", "gamma_c")}
     with gd.Solver(J, g, model=mdl, integrator=integrator, dt=dt, eps=0.1 if np.ndim(eps) else eps,
                    **kw) as S:
+        s = oracle_scale(J, S)
         R = psi0.shape[0]
         S.set_init(R, psi0, None, None if np.ndim(eps) == 0 else np.asarray(eps, np.float32))
         sub = np.arange(R) if R_sub is None else np.asarray(R_sub)
         op = psi0[sub].astype(np.float64)
         og = np.zeros((len(sub), n))
         fp, fg = psi0[sub].copy(), np.zeros((len(sub), n), np.float32)
-        prev = prev_f = 0
+        prev = 0
         worst = []
         for st in steps_list:
             S.run(st - prev)
             op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=eps, g=g,
-                           integrator=integrator, nthreads=oracle_threads, s=S.scale,
-                           **{k: v for k, v in kw.items() if k in ("rho_th", "gamma_c")})
+                           integrator=integrator, nthreads=oracle_threads, s=s, **okw)
+            if not strict:
+                fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=eps, g=g,
+                                   integrator=integrator, s=s, **okw)
             prev = st
-            fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev_f, dt=dt, eps=eps, g=g,
-                               integrator=integrator, s=S.scale,
-                               **{k: v for k, v in kw.items() if k in ("rho_th", "gamma_c")})
-            prev_f = st
             p, gm, step = S.state()
             assert step == st
             ep = _rel(p[sub], op)
             eg = _rel(gm[sub], og)
-            bound = np.maximum(TOL, 4 * np.maximum(_rel(fp, op), _rel(fg, og)))
             worst.append((st, float(ep.max()), float(eg.max())))
-            assert np.all(ep <= bound) and np.all(eg <= bound), (st, ep.max(), eg.max(), np.argmax(ep), bound)
-            strict = np.mean((ep <= TOL) & (eg <= TOL))
-            assert strict >= 0.9, (st, strict)
+            floor = None if strict else np.maximum(_rel(fp, op), _rel(fg, og))
+            P.check(ep, eg, floor, strict=strict, max_used=max_used, label=f"{model} n={n} step {st}")
         print("worst per snapshot (step, psi, gamma):", worst)
         return S, worst
 
 
 @pytest.mark.parametrize("n,R", [(64, 100), (100, 37), (200, 130)])
 def test_ising_euler_parity(n, R):
+    """Dense +-1 couplings, Euler dt = 0.05; N = 64, R = 100 is the Ising
+    parity workload and is held to 1e-4 on every trajectory."""
     J = I.dense_pm1(n, 1)
     psi0 = I.psi0_real(n, R, 1)
-    _parity_run(J, psi0, "ising", gd.GD_EULER, 0.05)
+    _parity_run(J, psi0, "ising", gd.GD_EULER, 0.05, strict=(n, R) == (64, 100))
 
 
 @pytest.mark.parametrize("n,R", [(64, 40), (130, 50)])
@@ -112,7 +111,7 @@ def test_xy1024_full_size_sampled_parity():
     J = I.dense_gaussian(n, 1)
     psi0 = I.psi0_complex(n, R, 1)
     sub = [0, 1, 63, 64, 511, 777, 1000, 1023]
-    _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=sub, steps_list=(1, 50, 200))
+    _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=sub, steps_list=(1, 50, 200), strict=True)
 
 
 # every FP32 coupling-kernel variant of the runtime's table (tile shapes, K
@@ -141,20 +140,19 @@ def test_every_fp32_variant_parity_n1000(monkeypatch, model, integrator, dt):
         op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
         fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
         prev = st
-        ref.append((op, og, np.maximum(TOL, 4 * np.maximum(_rel(fp, op), _rel(fg, og)))))
+        ref.append((op, og, np.maximum(_rel(fp, op), _rel(fg, og))))
     mdl = gd.GD_XY if cx else gd.GD_ISING
     for cid in FP32_VARIANTS:
         monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))
         with gd.Solver(J, model=mdl, integrator=integrator, dt=dt, eps=0.1) as S:
             S.set_init(R, psi0)
             prev = 0
-            for st, (op, og, bound) in zip(steps, ref):
+            assert abs(S.scale - s) <= 1e-12 * s
+            for st, (op, og, floor) in zip(steps, ref):
                 S.run(st - prev)
                 prev = st
                 p, gm, _ = S.state()
-                ep, eg = _rel(p, op), _rel(gm, og)
-                assert np.all(ep <= bound) and np.all(eg <= bound), (cid, st, ep.max(), eg.max())
-                assert np.mean((ep <= TOL) & (eg <= TOL)) >= 0.9, (cid, st)
+                P.check(_rel(p, op), _rel(gm, og), floor, label=f"variant {cid} {model} step {st}")
             Ed, _ = S.energy(device_path=True)
             sp = S.spins()
         Eo = O.energy_xy(J, sp) if cx else O.energy_ising(J, sp).astype(np.float64)

@@ -38,6 +38,8 @@ def _parity(J, psi0, model, dt, eps_hat, k_sample, **kw):
     om = "ising" if model == gd.GD_ISING else "xy"
     okw = {k: v for k, v in kw.items() if k in ("gamma_c", "noise_D", "noise_seed", "eps")}
     with gd.Solver(J, model=model, dt=dt, variant=gd.GD_VARIANT_MOD, eps_hat=eps_hat, **kw) as S:
+        s = O.coupling_scale(np.asarray(J, np.float64))
+        assert abs(s - S.scale) <= 1e-12 * s, (s, S.scale)
         S.set_init(R, psi0)
         for r in k_sample:
             assert np.array_equal(S.mod_couplings(r), J * (1 - np.eye(n, dtype=np.float32)))
@@ -49,7 +51,7 @@ def _parity(J, psi0, model, dt, eps_hat, k_sample, **kw):
         for st in SNAP:
             S.run(st - prev)
             op, og, oK = O.run_mod(J, op, og, oK, model=om, steps=st - prev, dt=dt, eps_hat=eps_hat,
-                                   s=S.scale, t0=prev, **okw)
+                                   s=s, t0=prev, **okw)
             prev = st
             p, gm, step = S.state()
             assert step == st

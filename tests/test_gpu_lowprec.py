@@ -29,7 +29,8 @@ def _one_step_check(J, x, gam, prec, model="ising", sub=None, dt=0.05, eps=0.1, 
         S.set_state(x, gam)
         S.run(1)
         xg, gg, _ = S.state()
-        s = S.scale
+        s = O.coupling_scale(np.asarray(J, np.float64))
+        assert abs(s - S.scale) <= 1e-12 * s
     sub = np.arange(R) if sub is None else np.asarray(sub)
     xo, go = O.run(J, x[sub], gam[sub], model=model, steps=1, dt=dt, eps=eps, s=s,
                    integrator=O.RK4 if integrator == gd.GD_RK4 else O.EULER)

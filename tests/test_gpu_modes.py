@@ -2,9 +2,11 @@
 rising from below) and of the resonant complex models (Ising through h_2,
 q-state clock model through h_q, Eq. (hs)) against the FP64 oracle.
 
-Amplitude bar as for the plain dense path: per trajectory, max-norm relative
-error <= max(1e-4, 4 x the oracle's own FP32-vs-FP64 distance), with at least
-90% of the trajectories within 1e-4 itself, at steps {1, 10, 50, 100, 200}.
+Amplitude bar as for the plain dense path (tests/_parity.py): per trajectory,
+max-norm relative error <= 1e-4 at steps {1, 10, 50, 100, 200}, or 4x the
+oracle's own FP32-vs-FP64 distance where the dynamics amplify rounding (at
+least 90% of the trajectories within 1e-4 itself; the count reported).  The
+coupling scale s is the oracle's own, checked against the library's.
 The noise numbers are drawn in FP32 on the GPU (logf, sqrtf, sincospif of
 the same 24-bit uniforms) and in FP64 by the oracle: they agree to a few
 FP32 ulps, checked directly on the first increment.
@@ -19,18 +21,16 @@ from oracle import oracle as O
 from paper_1807_00699_amd import gd
 from paper_1807_00699_amd import inputs as I
 
+import _parity as P
+
 pytestmark = pytest.mark.gpu
 
 SNAP = (1, 10, 50, 100, 200)
-TOL = 1e-4
+TOL = P.TOL
 ORACLE_MODEL = {gd.GD_ISING: "ising", gd.GD_XY: "xy", gd.GD_ISING_COMPLEX: "xy", gd.GD_POTTS: "xy"}
 
 
-def _rel(a, b):
-    R = a.shape[0]
-    a = a.reshape(R, -1).astype(np.float64)
-    b = b.reshape(R, -1).astype(np.float64)
-    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-30)
+_rel = P.rel
 
 
 def _hq_rows(model, q, hq, n):
@@ -50,7 +50,7 @@ def default_hq(J, s):
     return 1.1 * np.abs(J).sum(1).max() / s
 
 
-def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, **kw):
+def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, strict=False, max_used=None, **kw):
     n = J.shape[0]
     om = ORACLE_MODEL[model]
     okw = {k: v for k, v in kw.items() if k in ("rho_th", "gamma_c", "noise_D", "noise_seed")}
@@ -58,10 +58,12 @@ def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, **kw):
         okw["eps"] = kw["eps"]
     S = gd.Solver(J, None, model=model, integrator=integrator, dt=dt, **kw)
     try:
+        s = O.coupling_scale(np.asarray(J, np.float64))
+        assert abs(s - S.scale) <= 1e-12 * s, (s, S.scale)
         R = psi0.shape[0]
         S.set_init(R, psi0)
         q = kw.get("q", 2)
-        h = _hq_rows(model, q, kw.get("h_q") or default_hq(J, S.scale), n)
+        h = _hq_rows(model, q, kw.get("h_q") or default_hq(J, s), n)
         op = psi0.astype(np.float64)
         og = np.zeros((R, n))
         fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
@@ -70,17 +72,16 @@ def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, **kw):
         for st in steps_list:
             S.run(st - prev)
             op, og = O.run(J, op, og, model=om, steps=st - prev, dt=dt, integrator=integrator,
-                           s=S.scale, h=h, t0=prev, **okw)
+                           s=s, h=h, t0=prev, **okw)
             fp, fg = O.run_f32(J, fp, fg, model=om, steps=st - prev, dt=dt, integrator=integrator,
-                               s=S.scale, h=h, t0=prev, **okw)
+                               s=s, h=h, t0=prev, **okw)
             prev = st
             p, gm, step = S.state()
             assert step == st
             ep, eg = _rel(p, op), _rel(gm, og)
-            bound = np.maximum(TOL, 4 * np.maximum(_rel(fp, op), _rel(fg, og)))
             worst.append((st, float(ep.max()), float(eg.max())))
-            assert np.all(ep <= bound) and np.all(eg <= bound), (st, ep.max(), eg.max(), bound.max())
-            assert np.mean((ep <= TOL) & (eg <= TOL)) >= 0.9, st
+            P.check(ep, eg, np.maximum(_rel(fp, op), _rel(fg, og)), strict=strict, max_used=max_used,
+                    label=f"model {model} n={n} step {st}")
         print("worst per snapshot (step, psi, gamma):", worst)
     except BaseException:
         S.close()
@@ -293,6 +294,8 @@ def test_noise_xy1024_full_size_sampled():
     sub = [0, 500, 1023]
     with gd.Solver(J, model=gd.GD_XY, integrator=gd.GD_RK4, dt=0.02, gamma_c=gc, noise_D=0.01,
                    noise_seed=12, init_amp=0.0) as S:
+        s = O.coupling_scale(np.asarray(J, np.float64))
+        assert abs(s - S.scale) <= 1e-12 * s
         S.set_init(R)
         prev = 0
         op = np.zeros((len(sub), n, 2))
@@ -303,7 +306,7 @@ def test_noise_xy1024_full_size_sampled():
             # trajectories are keyed by their global index r: run them one by one
             for k, r in enumerate(sub):
                 a, b = O.run(J, op[k:k + 1], og[k:k + 1], model="xy", steps=st - prev, dt=0.02,
-                             integrator=O.RK4, s=S.scale, gamma_c=gc, noise_D=0.01, noise_seed=12,
+                             integrator=O.RK4, s=s, gamma_c=gc, noise_D=0.01, noise_seed=12,
                              t0=prev, r0=r)
                 op[k], og[k] = a[0], b[0]
             prev = st
