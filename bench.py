@@ -44,6 +44,16 @@ WORKLOADS = {
                      desc="256 Ising instances, N_k even uniform in [50,2000], random 3-regular "
                           "max-cut couplings (J=-1 on edges, gauged by a random s*), R=64, "
                           "Euler dt=0.05, FP32, one persistent launch per chunk (hipGraph)"),
+    "gemv4096": dict(model="ising", n=4096, R=1, integrator="euler", dt=0.05, steps=20000,
+                     J="sparse_pm1", desc="Ising, N=4096, J in {-1,0,1} density 0.5, one trajectory "
+                                          "(R=1), Euler dt=0.05, FP32 J streamed per step"),
+    "gemv4096_fp8": dict(model="ising", n=4096, R=1, integrator="euler", dt=0.05, steps=20000,
+                         J="sparse_pm1", precision="bf16",
+                         desc="Ising, N=4096, J in {-1,0,1} density 0.5 stored FP8, one trajectory "
+                              "(R=1), Euler dt=0.05, BF16 operand, FP32 sums and state"),
+    "gemv16384": dict(model="ising", n=16384, R=1, integrator="euler", dt=0.05, steps=2000,
+                      J="sparse_pm1", desc="Ising, N=16384, J in {-1,0,1} density 0.5, one trajectory "
+                                           "(R=1), Euler dt=0.05, FP32 J (1 GiB) streamed per step"),
     "gdmod1024": dict(model="xy", n=1024, R=256, integrator="euler", dt=0.02, steps=2000,
                       J="dense_gaussian", gdmod=True,
                       desc="GD-mod (Delta_ij = gamma_i + gamma_j, couplings adapted by Eq. (gamma2)), "
@@ -753,7 +763,16 @@ def main():
     # then bracket whole launches and count their coupling evaluations (the
     # J d of an energy check closing a launch is one more)
     small = (-(-n // 64) * 64 <= 128 and prec_name == "fp32")
+    gemv = st.kernel_config >= 100 and not small
     achieved = flops_launch / avg_s / 1e12
+    if gemv:
+        # J-streaming matrix-vector kernel: algorithmic HBM bytes of one launch
+        # = the couplings once (FP32, or FP8 when stored so) + the state of R
+        # trajectories (Euler: amplitudes and gains read and written, FP32;
+        # reduced precision adds the 16-bit operand copy, read and written)
+        jb = 4 if prec_name == "fp32" else 1
+        bytes_launch = n * n * jb + R * n * (8 * P + 8) + (0 if prec_name == "fp32" else R * n * P * 4)
+        hbm_gbs = bytes_launch / avg_s / 1e9
     out = {
         "metric": "spin-updates/s (N*R*steps/s)",
         "value": n * R * steps / el,
@@ -769,7 +788,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "R": R, "integrator": wl["integrator"],
                    "dt": wl["dt"], "energy_check_every": args.check, "kernel_config": st.kernel_config},
-        "roofline": ({"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_F32,
+        "roofline": ({"bound": "hbm", "achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": hbm_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "gemv_step_k",
+                      "launches": int(launches), "avg_launch_us": avg_s * 1e6,
+                      "bytes_per_launch": bytes_launch}
+                     if gemv else
+                     {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_F32,
                       "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_F32, "traffic": None,
                       "kernel": "small_step_k", "coupling_evaluations": int(launches),
                       "avg_evaluation_us": avg_s * 1e6, "flops_per_evaluation": flops_launch}

@@ -86,6 +86,21 @@ DenseConfig dense_lp_config(bool complex_mode, int idx);
 hipError_t launch_dense_step_lp(const DenseConfig &cfg, bool complex_mode, int mode, int op,
                                 bool j_fp8, const DenseStepArgs &a, hipStream_t st);
 
+// ---- small-R coupling product (gd_gemv.hip): a J-streaming matrix-vector
+// kernel for at most kGemvMaxCols GEMM columns (R real or 2R complex), with
+// the same modes and epilogue as the dense kernels.  Its variants carry ids
+// kGemvBase + index next to the dense ones; bm = rows per workgroup (16 or
+// 32, the row tile of its energy partials).
+constexpr int kGemvBase = 100;
+constexpr int kGemvMaxCols = 16;
+int gemv_config_count();
+DenseConfig gemv_config(int idx);
+// variant idx runs C = R (real) or 2R (complex) columns at Np spins with
+// operand kind op and FP8-stored J
+bool gemv_fits(int idx, int Np, int R, bool complex_mode, int op, bool j_fp8);
+hipError_t launch_gemv_step(const DenseConfig &cfg, bool complex_mode, int mode, int op, bool j_fp8,
+                            const DenseStepArgs &a, hipStream_t st);
+
 // ---- GD-mod (gd_mod.hip): one Euler step with per-trajectory couplings K
 // [R][Np][Np] (updated in place); c_hat = dt * eps_hat.  Needs Np % 16 == 0
 // and gdmod_lds_bytes <= 64 KiB.

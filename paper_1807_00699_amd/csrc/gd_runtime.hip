@@ -70,12 +70,20 @@ inline float e4m3_decode(uint8_t c) {
 }
 inline bool e4m3_encode_exact(float v, uint8_t *out) {
     if (v == 0.0f) { *out = std::signbit(v) ? 0x80 : 0x00; return true; }
-    for (int c = 0; c < 256; ++c) {
-        const int e = (c >> 3) & 15;
-        if (e == 0) continue;   // subnormals are not used for storage
-        if (e4m3_decode(uint8_t(c)) == v) { *out = uint8_t(c); return true; }
-    }
-    return false;
+    if (!std::isfinite(v)) return false;
+    // normal numbers only: |v| = (1 + m/8) 2^(e-7), 1 <= e <= 15, 0 <= m <= 7
+    // (e = 15, m = 7 is NaN); frexp gives |v| = f 2^x with f in [0.5, 1)
+    int x = 0;
+    const double f = std::frexp(std::fabs(double(v)), &x);
+    const int e = x + 6;
+    const double m8 = (2.0 * f - 1.0) * 8.0;
+    if (e < 1 || e > 15 || m8 != std::floor(m8)) return false;
+    const int m = int(m8);
+    if (e == 15 && m == 7) return false;
+    const uint8_t c = uint8_t((std::signbit(v) ? 0x80 : 0x00) | (e << 3) | m);
+    if (e4m3_decode(c) != v) return false;
+    *out = c;
+    return true;
 }
 inline bool bf16_exact(float v, uint16_t *out) {
     uint32_t b;
@@ -92,7 +100,9 @@ inline bool f16_exact(float v, uint16_t *out) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (complex, Np, Rp, integrator) -> cfg
+// (complex + 2 precision + 8 FP8-stored J, Np, Rp, integrator, R if the
+// matrix-vector kernels compete else 0) -> kernel variant id
+std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;
 
 }  // namespace
 
@@ -239,7 +249,7 @@ int alloc_state(gd_solver *s, int R) {
             rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadow[k]), pl * P);
         if (rc == GD_OK) rc = dalloc(reinterpret_cast<uint16_t **>(&s->shadowD), pl * P);
     }
-    if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 32) * s->Rp);  // smallest row tile
+    if (rc == GD_OK) rc = dalloc(&s->partial, (size_t)(s->Np / 16) * s->Rp);  // smallest row tile
     // + E[best] of the last check, + running best of a run's checks
     if (rc == GD_OK) rc = dalloc(&s->dE, (size_t)s->Rp + 2);
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
@@ -296,9 +306,10 @@ DenseStepArgs base_args(gd_solver *s) {
 }
 
 hipError_t launch_coupling(gd_solver *s, const DenseConfig &cfg, int mode, const DenseStepArgs &a) {
-    if (s->op == OP_F32) return launch_dense_step(cfg, s->complex_mode(), mode, OP_F32, a, s->stream);
     DenseStepArgs b = a;
-    b.J = s->dJlp;
+    if (s->op != OP_F32) b.J = s->dJlp;
+    if (cfg.id >= kGemvBase) return launch_gemv_step(cfg, s->complex_mode(), mode, s->op, s->jfp8, b, s->stream);
+    if (s->op == OP_F32) return launch_dense_step(cfg, s->complex_mode(), mode, OP_F32, b, s->stream);
     return launch_dense_step_lp(cfg, s->complex_mode(), mode, s->op, s->jfp8, b, s->stream);
 }
 
@@ -395,22 +406,41 @@ int enqueue_step(gd_solver *s, const DenseConfig &cfg, float dt_override, bool t
     return GD_OK;
 }
 
-// Pick the dense kernel variant: GD_DENSE_CONFIG forces one; otherwise each
-// variant is timed on the live buffers with dt = 0 (state unchanged) and the
-// fastest is cached per (model, Np, Rp, integrator).
+// Pick the coupling kernel variant: GD_DENSE_CONFIG forces one; otherwise each
+// variant that fits (the GEMM tiles, and for at most kGemvMaxCols GEMM columns
+// also the J-streaming matrix-vector kernels, ids kGemvBase + k) is timed on
+// the live buffers with dt = 0 (state unchanged) and the fastest is cached per
+// (model, precision, J storage, Np, Rp, integrator, R when the matrix-vector
+// kernels compete).
 int choose_config(gd_solver *s) {
     const bool cx = s->complex_mode();
     const bool lp = s->op != OP_F32;
     const int nc = lp ? dense_lp_config_count() : dense_config_count(cx);
-    auto cfg_of = [&](int id) { return lp ? dense_lp_config(cx, id) : dense_config(cx, id); };
+    auto gemv_ok = [&](int k) { return !s->mod() && gemv_fits(k, s->Np, s->R, cx, s->op, s->jfp8); };
+    const bool gv = gemv_ok(0);
+    const int ng = gv ? gemv_config_count() : 0;
+    auto cfg_of = [&](int id) {
+        if (id >= kGemvBase) return gemv_config(id - kGemvBase);
+        return lp ? dense_lp_config(cx, id) : dense_config(cx, id);
+    };
+    auto fits = [&](int id) {
+        if (id >= kGemvBase) return gemv_ok(id - kGemvBase);
+        return id >= 0 && id < nc && dense_config_fits(cfg_of(id), s->Np, s->Rp);
+    };
     if (const char *env = std::getenv("GD_DENSE_CONFIG")) {
         int id = std::atoi(env);
-        if (id < 0 || id >= nc || !dense_config_fits(cfg_of(id), s->Np, s->Rp))
+        if (!fits(id))
             return fail(GD_E_INVALID_ARG, "GD_DENSE_CONFIG out of range or does not tile the problem");
         s->cfg = cfg_of(id);
         return GD_OK;
     }
-    auto key = std::make_tuple(int(cx) + 2 * s->op + 8 * int(s->jfp8), s->Np, s->Rp, s->integrator());
+    std::vector<int> ids;
+    for (int id = 0; id < nc; ++id)
+        if (fits(id)) ids.push_back(id);
+    for (int k = 0; k < ng; ++k)
+        if (gemv_ok(k)) ids.push_back(kGemvBase + k);
+    auto key = std::make_tuple(int(cx) + 2 * s->op + 8 * int(s->jfp8), s->Np, s->Rp, s->integrator(),
+                               gv ? s->R : 0);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -428,11 +458,10 @@ int choose_config(gd_solver *s) {
         GD_HIP(hipEventCreate(&e0));
         GD_HIP(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        std::vector<float> ms_of(nc, 1e30f);
+        std::vector<float> ms_of(ids.size(), 1e30f);
         const int reps = 3;
-        for (int id = 0; id < nc; ++id) {
-            DenseConfig c = cfg_of(id);
-            if (!dense_config_fits(c, s->Np, s->Rp)) continue;
+        for (size_t v = 0; v < ids.size(); ++v) {
+            DenseConfig c = cfg_of(ids[v]);
             int rc = enqueue_step(s, c, 0.0f, false, 0);  // warm-up
             if (rc != GD_OK) return rc;
             GD_HIP(hipEventRecord(e0, s->stream));
@@ -442,21 +471,24 @@ int choose_config(gd_solver *s) {
             GD_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
             GD_HIP(hipEventElapsedTime(&ms, e0, e1));
-            ms_of[id] = ms;
+            ms_of[v] = ms;
             best_ms = std::min(best_ms, ms);
         }
-        // near-ties (within 1%, below the timing noise) go to the lowest id,
-        // so repeated tunings of one problem settle on the same variant
-        for (int id = 0; id < nc && best < 0; ++id)
-            if (ms_of[id] <= 1.01f * best_ms) best = id;
+        // near-ties (within 1%, below the timing noise) go to the first
+        // candidate, so repeated tunings of one problem settle on the same variant
+        for (size_t v = 0; v < ids.size() && best < 0; ++v)
+            if (ms_of[v] <= 1.01f * best_ms) best = ids[v];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         GD_HIP(hipMemsetAsync(s->flags, 0, (size_t)s->Rp * sizeof(int), s->stream));
+    } else if (gv) {
+        // small problems with few trajectories: the matrix-vector kernel reads
+        // J once instead of multiplying Rp padded columns
+        best = kGemvBase;
     } else {
         long long most = -1;
-        for (int id = 0; id < nc; ++id) {
+        for (int id : ids) {
             DenseConfig c = cfg_of(id);
-            if (!dense_config_fits(c, s->Np, s->Rp)) continue;
             const long long nblk = (long long)(s->Np / c.bm) * (s->Rp / c.traj_tile) * (c.threads / 64);
             if (nblk > most) { most = nblk; best = id; }
         }
@@ -904,8 +936,12 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
     const bool rk4 = s->integrator() == GD_RK4;
     const bool small_ok = !s->mod() && s->op == OP_F32 && s->Np <= 128 &&
                           std::getenv("GD_DENSE_CONFIG") == nullptr;
-    const bool graph_ok = !small_ok && !timed && s->prm.noise_D == 0.0 && !s->mod() &&
-                          (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork;
+    // The matrix-vector kernels of few trajectories run for microseconds, so
+    // they are always replayed from graphs (with GD_F_PROFILE one event pair
+    // brackets each replay and its launches, in-graph dispatch gaps included).
+    const bool gemv_path = s->cfg.id >= kGemvBase;
+    const bool graph_ok = !small_ok && s->prm.noise_D == 0.0 && !s->mod() &&
+                          (gemv_path || (!timed && (long long)s->Np * s->Np * s->Rp * s->P < kGraphWork));
     // Without a target (nothing to stop on or to time) the best energy of
     // the checks is kept on the device and read back with the run's end.
     const bool deferred = ci > 0 && !s->prm.has_target && !s->track_target &&
@@ -980,7 +1016,9 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         }
         if (graph_ok) {
             for (; chunk - k >= kGraphSteps; k += kGraphSteps) {
+                if (timed && (rc = ev_begin(s)) != GD_OK) return rc;
                 if ((rc = launch_step_graph(s)) != GD_OK) return rc;
+                if (timed && (rc = ev_end(s, kGraphSteps * (rk4 ? 4 : 1))) != GD_OK) return rc;
             }
         }
         for (; k < chunk; ++k) {
