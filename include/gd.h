@@ -259,6 +259,19 @@ int gd_energy_device(gd_solver *s, double *E, int32_t *best);
  * GD_POTTS). */
 int gd_spins(gd_solver *s, void *out, int32_t fmt);
 
+/*
+ * gd_spins_noalloc: gd_spins for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same output as gd_spins, staged through a fixed device array
+ * of 16 MiB (one per GPU, held until the process ends) instead of a buffer
+ * allocated per call; it calls no hipMalloc, hipFree or allocating routine.
+ * Single-instance solvers only (GD_E_UNSUPPORTED for batches).  Errors as
+ * gd_spins, plus GD_E_INVALID_ARG when batch * n * (1 byte for GD_SPINS_I8,
+ * 4 otherwise) exceeds 16 MiB.  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other threads, other streams) race.
+ */
+int gd_spins_noalloc(gd_solver *s, void *out, int32_t fmt);
+
 /* gd_get_state / gd_set_state: amplitudes ([batch][n] or [batch][n][2]),
  * gains [batch][n] and step counter; NULL pointers are skipped on get.
  * gd_set_state needs both psi and gamma and keeps the per-spin eps. */

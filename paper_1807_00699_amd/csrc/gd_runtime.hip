@@ -99,6 +99,36 @@ inline bool f16_exact(float v, uint16_t *out) {
     return true;
 }
 
+// Staging memory of gd_spins_noalloc: one fixed array per device for callers
+// that cannot allocate.  In host code `scratch` names a host-side stand-in,
+// not device memory: the device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is used.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;   // device -> address of its scratch
+
+// Device address of `scratch` on device `dev` (looked up on first use).
+int scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return GD_OK;
+    }
+    int cur = 0;
+    GD_HIP(hipGetDevice(&cur));
+    if (cur != dev) GD_HIP(hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) GD_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || !ptr)
+        return fail(GD_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+    *out = ptr;
+    return GD_OK;
+}
+
 std::mutex g_tune_mu;
 // (complex + 2 precision + 8 FP8-stored J, Np, Rp, integrator, R if the
 // matrix-vector kernels compete else 0) -> kernel variant id
@@ -1177,6 +1207,41 @@ int gd_spins(gd_solver *s, void *out, int32_t fmt) {
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(GD_E_DEVICE, std::string("gd_spins: ") + hipGetErrorString(e));
+    return GD_OK;
+}
+
+int gd_spins_noalloc(gd_solver *s, void *out, int32_t fmt) {
+    if (!s) return fail(GD_E_INVALID_ARG, "solver is NULL");
+    if (s->batch) return fail(GD_E_UNSUPPORTED, "gd_spins_noalloc serves single-instance solvers");
+    if (!s->have_state) return fail(GD_E_STATE, "no state");
+    if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+    if (fmt != GD_SPINS_I8 && fmt != GD_SPINS_ANGLE_F32 && fmt != GD_SPINS_STATE_I32)
+        return fail(GD_E_INVALID_ARG, "unknown format");
+    if (fmt == GD_SPINS_I8 && s->ro != RO_SIGN && s->ro != RO_SIGN_RE)
+        return fail(GD_E_INVALID_ARG, "int8 spins need an Ising model");
+    if (fmt == GD_SPINS_STATE_I32 && s->ro != RO_CLOCK)
+        return fail(GD_E_INVALID_ARG, "int32 states need the Potts model");
+    const size_t bytes = (size_t)s->R * s->n * (fmt == GD_SPINS_I8 ? 1 : 4);
+    if (bytes > kScratchBytes) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "gd_spins_noalloc: %zu bytes of spins exceed its %zu-byte staging array",
+                      bytes, kScratchBytes);
+        return fail(GD_E_INVALID_ARG, buf);
+    }
+    void *stage = nullptr;
+    int rc = scratch_address(s->device, &stage);
+    if (rc != GD_OK) return rc;
+    // the readout kernel writes every one of the R x n entries, so nothing
+    // left over from an earlier call is read back
+    GD_HIP(launch_discretise(s->psi[s->cur], s->D, nullptr, OP_F32, s->ro, s->prm.q,
+                             fmt == GD_SPINS_I8 ? static_cast<int8_t *>(stage) : nullptr,
+                             fmt == GD_SPINS_ANGLE_F32 ? static_cast<float *>(stage) : nullptr,
+                             fmt == GD_SPINS_STATE_I32 ? static_cast<int32_t *>(stage) : nullptr,
+                             s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(), s->stream));
+    GD_HIP(hipMemcpyAsync(out, stage, bytes,
+                          (s->prm.flags & GD_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
     return GD_OK;
 }
 

@@ -34,6 +34,7 @@ EXPORTS = (
     "gd_coupling_scale", "gd_error_string", "gd_last_error", "gd_create_batch", "gd_set_targets",
     "gd_ttt", "gd_features", "gd_mlp_create", "gd_mlp_destroy", "gd_mlp_set_params",
     "gd_mlp_get_params", "gd_mlp_forward", "gd_mlp_train_step", "gd_propose", "gd_mod_couplings",
+    "gd_spins_noalloc",
 )
 GD_NFEAT = 20
 GD_MLP_NPARAM = 5634
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.gd_energy.argtypes = [vp, vp, vp]
     lib.gd_energy_device.argtypes = [vp, vp, vp]
     lib.gd_spins.argtypes = [vp, vp, i32]
+    lib.gd_spins_noalloc.argtypes = [vp, vp, i32]
     lib.gd_get_state.argtypes = [vp, vp, vp, vp]
     lib.gd_set_state.argtypes = [vp, i32, vp, vp, i64]
     lib.gd_stats.argtypes = [vp, C.POINTER(gd_run_stats)]
@@ -204,6 +206,13 @@ def gd_spins(h, batch, n, fmt=GD_SPINS_I8):
     dtype = {GD_SPINS_I8: np.int8, GD_SPINS_STATE_I32: np.int32}.get(fmt, np.float32)
     out = np.empty((int(batch), int(n)), dtype)
     _check(load().gd_spins(h, out.ctypes.data_as(C.c_void_p), int(fmt)), "gd_spins")
+    return out
+
+
+def gd_spins_noalloc(h, batch, n, fmt=GD_SPINS_I8):
+    dtype = {GD_SPINS_I8: np.int8, GD_SPINS_STATE_I32: np.int32}.get(fmt, np.float32)
+    out = np.empty((int(batch), int(n)), dtype)
+    _check(load().gd_spins_noalloc(h, out.ctypes.data_as(C.c_void_p), int(fmt)), "gd_spins_noalloc")
     return out
 
 
