@@ -1,16 +1,27 @@
-"""Throughput benchmark of the gain-dissipative solver on one MI355X.
+"""Throughput and time-to-target benchmark of the gain-dissipative solver on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload xy1024|ising64|...]
+    python bench.py [--steps K] [--warmup W] [--workload ising4096|xy1024|...]
 
 A step is one integration step (one RK4 step = four coupling launches) of
-all R trajectories, including the device energy check (discretise, energy
-GEMM, best-of-R) every `check` steps.  Default workload: XY model, N = 1024,
-J_ij ~ N(0, 1/N), R = 1024 complex trajectories, RK4 dt = 0.02, FP32, 5000
-steps.  Prints one JSON line with spin-updates/s (N * R * steps / s), the
-roofline position of the dominant kernel (device time per launch from one
-pair of HIP events recorded on the solver's stream around all coupling
-launches of every 8th step of the timed run) and the
-FP64 oracle timed on the host CPU over a bounded sample of the same workload.
+all R trajectories; the timed steps end on a device energy check
+(discretise, energy product, best-of-R), every min(check, K) steps.
+
+Default workload (the dense Ising instance of Sec. 3 at N = 4096): density-0.5
+{-1, 0, +1} couplings, R = 4096 random restarts, Euler dt = 0.05, inputs
+resident in HBM.  One JSON line:
+  * value: spin-updates/s (N * R * steps / s) of the plain FP32 form over K
+    timed steps, and the same for the BF16-operand / FP8-stored-J form under
+    "legs", each with the roofline position of its coupling kernel (device time
+    per launch from one HIP event pair around the coupling launches of every
+    8th step of the timed run, on the solver's stream);
+  * ttt: time to a target energy (best-known + 0.1%) for both forms, 8 seeds
+    each, a 10 000-step budget independent of K, checks every 100 steps;
+    best-known from longer reference runs made here first;
+  * cpu_baseline: the FP64 oracle timed on the host over a bounded sample of
+    the same workload, on all cores and on one thread, with the CPU model;
+    this leg also scores the returned spins with the oracle's Eq. (h) energies
+    (energy error of each form against the oracle).
+Other workloads (--workload) print the single-form line of that workload.
 """
 from __future__ import annotations
 
@@ -64,17 +75,20 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_F32 = 78.6    # FP32 vector FMA without packed math (256 CUs, 2.4 GHz)
 
 
-def kernel_traffic(config_id):
-    """HBM bytes per launch of the FP32 coupling kernel from the committed
-    counter summary, or None when the kernel sources changed since the
-    counters were taken or another variant runs."""
+def kernel_traffic(config_id, fp32=True, workload="xy1024"):
+    """HBM bytes per launch of a coupling kernel from its committed counter
+    summary (profiles/<kernel>_<workload>_counters.txt), or None when there is
+    none, the kernel sources changed since the counters were taken or another
+    variant runs."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "dense_step_f32_xy1024_counters.txt")
+    kern = "dense_step_f32" if fp32 else "dense_step_lp"
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
     csrc = os.path.join(ROOT, "paper_1807_00699_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("gd_dense.hip", "gd_epilogue.h"))
+    files = ("gd_dense.hip", "gd_epilogue.h") if fp32 else ("gd_dense_lp.hip", "gd_epilogue.h")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in files)
     if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_source_sha256_16"):
         return None
     if int(kv.get("kernel_config_id", -1)) != int(config_id):
@@ -87,8 +101,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="xy1024", choices=sorted(WORKLOADS))
-    ap.add_argument("--check", type=int, default=50, help="steps between device energy checks")
+    ap.add_argument("--workload", default="ising4096", choices=sorted(WORKLOADS) + ["ising4096"])
+    ap.add_argument("--check", type=int, default=50,
+                    help="steps between device energy checks (the timed steps end on one)")
+    ap.add_argument("--ttt-seeds", type=int, default=8, help="starts per form in the time-to-target runs")
+    ap.add_argument("--ttt-budget", type=int, default=10000, help="step budget of a time-to-target run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target reference run")
@@ -148,7 +165,7 @@ def cpu_baseline(wl, J, psi0, target_s):
         if el >= 0.5 * target_s or steps >= cap:
             break
         steps = min(cap, int(steps * target_s / max(el, 1e-6)))
-    return {"value": n * R_s * steps / el, "unit": "spin-updates/s", "cores": threads,
+    return {"value": n * R_s * steps / el, "unit": "spin-updates/s", "cores": min(threads, R_s),
             "kind": "oracle",
             "sample": f"{R_s} of {wl['R']} trajectories x {steps} steps, {el:.1f} s"}
 
@@ -679,6 +696,198 @@ def maxcut800(args):
                       "summary": summ, "rows": out}), flush=True)
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_rate(J, psi0, model, integrator, dt, threads, target_s, steps_cap):
+    """Oracle spin-updates/s on len(psi0) trajectories with `threads` OpenMP
+    threads (over trajectories), run long enough to take about target_s."""
+    from oracle import oracle as O
+    n, Rs = J.shape[0], psi0.shape[0]
+    integ = O.RK4 if integrator == "rk4" else O.EULER
+    steps = 2
+    t0 = time.perf_counter()
+    O.run(J, psi0, model=model, steps=steps, dt=dt, eps=0.1, integrator=integ, nthreads=threads)
+    pilot = time.perf_counter() - t0
+    steps = int(max(2, min(steps_cap, target_s * steps / max(pilot, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(J, psi0, model=model, steps=steps, dt=dt, eps=0.1, integrator=integ, nthreads=threads)
+    el = time.perf_counter() - t0
+    return n * Rs * steps / el, steps, el
+
+
+def headline(args):
+    """Dense Ising N = 4096, R = 4096: plain FP32 vs BF16 operand with FP8 J,
+    throughput, time to target and the oracle baseline (see the module
+    docstring)."""
+    import torch
+
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    n, R, dt = 4096, 4096, 0.05
+    K = args.steps if args.steps is not None else 200
+    check = max(1, min(args.check, K))
+    J = I.sparse_pm1(n, 1)
+    x0 = I.psi0_real(n, R, 1)
+    torch.cuda.init()
+    forms = (("fp32", gd.GD_PREC_FP32, "f32"), ("bf16_fp8j", gd.GD_PREC_BF16, "bf16xf32"))
+    legs, results = {}, {}
+    for name, prec, dtype in forms:
+        S = gd.Solver(J, model=gd.GD_ISING, dt=dt, eps=0.1, precision=prec, check_interval=check,
+                      flags=gd.GD_F_PROFILE)
+        S.set_init(R, x0)
+        if args.warmup:
+            S.run(args.warmup)
+        S.set_init(R, x0)            # the timed run starts from the initial state
+        torch.cuda.synchronize()
+        st0 = S.stats()
+        t0 = time.perf_counter()
+        S.run(K)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = S.stats()
+        E, best = S.energy()                       # FP64 re-score of the readout
+        Ed, best_d = S.energy(device_path=True)    # the device check's FP32 product, FP64 sums
+        spins = S.spins()
+        S.close()
+        launches = st.kernel_launches - st0.kernel_launches
+        avg_s = (st.kernel_ms - st0.kernel_ms) / 1e3 / max(launches, 1)
+        flops_launch = 2.0 * n * n * R
+        peak = PEAKS_TFLOPS["fp32" if prec == gd.GD_PREC_FP32 else "bf16"]
+        achieved = flops_launch / avg_s / 1e12
+        legs[name] = {
+            "value": n * R * K / el, "ms_per_step": el / K * 1e3, "dtype": dtype,
+            "kernel_config": st.kernel_config, "best_energy": float(E[best]),
+            "device_check_equals_fp64_rescore": bool(np.array_equal(E, Ed) and best == best_d),
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak,
+                         "traffic": kernel_traffic(st.kernel_config, prec == gd.GD_PREC_FP32, "ising4096"),
+                         "kernel": "dense_step_f32" if prec == gd.GD_PREC_FP32 else "dense_step_lp",
+                         "launches": int(launches), "avg_launch_us": avg_s * 1e6,
+                         "flops_per_launch": flops_launch},
+        }
+        results[name] = (E, Ed, spins, best)
+        print(json.dumps({"progress": name, "ms_per_step": legs[name]["ms_per_step"]}), file=sys.stderr,
+              flush=True)
+
+    ttt = None if args.no_ttt else headline_ttt(args, J, x0, n, R, dt)
+
+    fp = legs["fp32"]
+    out = {
+        "metric": "spin-updates/s (N*R*steps/s)", "value": fp["value"], "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": fp["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Ising, N=4096, J in {-1,0,1} density 0.5 (signs equiprobable), R=4096 "
+                               "random restarts, Euler dt=0.05, plain FP32 form (legs: BF16 operand "
+                               "with FP8-stored J)",
+                   "n": n, "R": R, "integrator": "euler", "dt": dt, "energy_check_every": check,
+                   "kernel_config": fp["kernel_config"]},
+        "roofline": fp["roofline"],
+        "legs": {"bf16_fp8j": legs["bf16_fp8j"]},
+        "best_energy": fp["best_energy"],
+    }
+    if ttt is not None:
+        out["ttt"] = ttt
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["energy_vs_oracle"] = headline_cpu_leg(args, J, x0, results)
+    print(json.dumps(out), flush=True)
+
+
+def headline_ttt(args, J, x0, n, R, dt):
+    """Time to target for both forms.  Best-known energy: the lowest energy of
+    the device checks (every 500 steps) of reference runs from other starts:
+    four BF16 batches of R trajectories over twice the TTT budget and one FP32
+    batch over the budget.  Target = best-known + 0.1% of its magnitude.
+    Each form then runs from `ttt_seeds` other starts with checks every 100
+    steps and stops at the first check at the target; time = device time from
+    the start of the run to the event after that check (HIP events on the
+    solver's stream); runs that do not reach it within the budget are
+    censored and counted in the success fraction."""
+    from paper_1807_00699_amd import gd
+    from paper_1807_00699_amd import inputs as I
+
+    budget, chk = args.ttt_budget, 100
+    t_ref = time.perf_counter()
+    ref = []
+    for prec, seeds, steps in ((gd.GD_PREC_BF16, (101, 102, 103, 104), 2 * budget),
+                               (gd.GD_PREC_FP32, (105,), budget)):
+        for sd in seeds:
+            with gd.Solver(J, model=gd.GD_ISING, dt=dt, eps=0.1, precision=prec, check_interval=500) as S:
+                S.set_init(R, I.psi0_real(n, R, sd))
+                S.run(steps)
+                ref.append(S.stats().best_energy)
+            print(json.dumps({"progress": "reference", "seed": sd, "best": ref[-1]}), file=sys.stderr,
+                  flush=True)
+    ref_s = time.perf_counter() - t_ref
+    best_known = float(min(ref))
+    target = best_known + 1e-3 * abs(best_known)
+    forms = {}
+    for name, prec in (("fp32", gd.GD_PREC_FP32), ("bf16_fp8j", gd.GD_PREC_BF16)):
+        secs, steps_at, finals = [], [], []
+        for k in range(args.ttt_seeds):
+            with gd.Solver(J, model=gd.GD_ISING, dt=dt, eps=0.1, precision=prec, check_interval=chk,
+                           has_target=1, target_energy=target) as S:
+                S.set_init(R, I.psi0_real(n, R, 1 + k))
+                S.run(budget)
+                st = S.stats()
+            secs.append(st.ttt_seconds if st.target_reached else None)
+            steps_at.append(int(st.ttt_steps) if st.target_reached else None)
+            finals.append(float(st.best_energy))
+        ok = [x for x in secs if x is not None]
+        srt = sorted(x if x is not None else np.inf for x in secs)
+        med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
+        forms[name] = {"seconds": secs, "steps": steps_at, "best_energy": finals,
+                       "median_seconds": None if not np.isfinite(med) else float(med),
+                       "success_fraction": len(ok) / len(secs)}
+        print(json.dumps({"progress": "ttt", "form": name, **forms[name]}), file=sys.stderr, flush=True)
+    med = {k: v["median_seconds"] for k, v in forms.items()}
+    return {"target": target, "best_known": best_known,
+            "rule": "best-known = lowest device-checked energy of 4 BF16 reference batches x "
+                    f"{2 * budget} steps and 1 FP32 batch x {budget} steps (R={R} each, other starts); "
+                    "target = best-known + 0.1%",
+            "reference_seconds": ref_s, "budget_steps": budget, "check_every": chk,
+            "clock": "device time (HIP events) from the start of gd_run to the check",
+            "seeds": args.ttt_seeds, **forms,
+            "speedup_bf16_over_fp32": (med["fp32"] / med["bf16_fp8j"]
+                                       if med["fp32"] and med["bf16_fp8j"] else None)}
+
+
+def headline_cpu_leg(args, J, x0, results):
+    """The oracle on the host: its throughput on a sample of the workload (all
+    cores: one trajectory per thread; one thread: one trajectory), and its
+    Eq. (h) energies of the spins each form returned (the best trajectory and
+    seven others), against the library's FP64 re-score and device check."""
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    v_all, st_all, el_all = oracle_rate(J, x0[:threads], "ising", "euler", 0.05, threads, args.cpu_seconds, 2000)
+    v_one, st_one, el_one = oracle_rate(J, x0[:1], "ising", "euler", 0.05, 1, args.cpu_seconds / 2, 2000)
+    cpu = {"value": v_all, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{threads} of {x0.shape[0]} trajectories x {st_all} steps, {el_all:.1f} s",
+           "single_thread": {"value": v_one, "cores": 1,
+                             "sample": f"1 trajectory x {st_one} steps, {el_one:.1f} s"},
+           "host_cpu": host_cpu_model()}
+    errs = {}
+    for name, (E, Ed, spins, best) in results.items():
+        R = spins.shape[0]
+        sub = sorted({int(best), 0, 1, R // 3, R // 2, 2 * R // 3, R - 2, R - 1})
+        Eo = O.energy_ising(J, spins[sub]).astype(np.float64)
+        errs[name] = {"trajectories": sub,
+                      "max_abs_fp64_rescore_minus_oracle": float(np.abs(E[sub] - Eo).max()),
+                      "max_abs_device_check_minus_oracle": float(np.abs(Ed[sub] - Eo).max()),
+                      "best_energy_oracle": float(Eo[sub.index(int(best))]),
+                      "max_rel_fp64_rescore_minus_oracle": float((np.abs(E[sub] - Eo) / np.abs(Eo)).max())}
+    return cpu, errs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -709,6 +918,8 @@ def main():
     from paper_1807_00699_amd import gd
     from paper_1807_00699_amd import inputs as I
 
+    if args.workload == "ising4096":
+        return headline(args)
     wl = WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else wl["steps"]
     if wl.get("batch"):

@@ -164,7 +164,9 @@ typedef struct gd_run_stats {
     int64_t kernel_launches;  /* number of coupling launches timed in kernel_ms */
     int32_t diverged;         /* trajectories whose state became non-finite */
     int32_t target_reached;   /* 1 once a check met the target */
-    double ttt_seconds;       /* wall time from the start of gd_run to that check */
+    double ttt_seconds;       /* device time (HIP events on the solver's stream) of the gd_run
+                                 calls since gd_set_init / gd_set_state, counted from the start
+                                 of each call, up to the event recorded after that check */
     int64_t ttt_steps;        /* steps done at that check */
     double best_energy;       /* lowest device-checked energy so far (+inf if none) */
     int32_t best_index;       /* its trajectory */
@@ -230,9 +232,9 @@ int gd_set_init(gd_solver *s, int32_t batch, const float *psi0, const float *gam
  * the first check where min_r E_r <= target_energy (gd_stats.ttt_*).  The
  * host waits for each check only with has_target or GD_F_ASYNC.  A target
  * recorded by gd_set_targets is compared one check later, while the next
- * steps run, and its ttt_seconds are device time from the start of the
- * gd_run call (HIP events); with no target the best energy of the checks is
- * kept on the device and reaches gd_stats when the run ends.
+ * steps run.  Times to target are device time (HIP events) in both cases;
+ * with no target the best energy of the checks is kept on the device and
+ * reaches gd_stats when the run ends.
  * Returns GD_E_DIVERGED if any trajectory is non-finite at the end.
  */
 int gd_run(gd_solver *s, int32_t batch, int64_t steps);
@@ -334,10 +336,11 @@ int gd_create_batch(gd_solver **out, int32_t count, const gd_instance *inst, int
 int gd_set_targets(gd_solver *s, const double *targets);
 
 /*
- * gd_ttt: per instance [count]: seconds from the start of gd_run calls (summed
- * over calls) to the check that met the target (-1 if not reached), the step
- * count at that check (-1), and the best checked energy so far (+inf).  Any
- * pointer may be NULL.
+ * gd_ttt: per instance [count]: seconds to the check that met the target (-1
+ * if not reached) on the clock of gd_run_stats.ttt_seconds (device time of
+ * the gd_run calls since the last set-up, from the start of each call), the
+ * step count at that check (-1), and the best checked energy so far (+inf).
+ * Any pointer may be NULL.
  */
 int gd_ttt(gd_solver *s, double *seconds, int64_t *steps, double *best_energy);
 

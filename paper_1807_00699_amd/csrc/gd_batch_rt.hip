@@ -100,6 +100,10 @@ struct BatchSolver {
     std::vector<int64_t> ttt_steps;
     std::vector<double> best_E;
     std::vector<int> best_r;
+    // time to target: device time of the gd_run calls since the last set-up
+    // (an event at the start of each call, one after each check, one at the end)
+    hipEvent_t ev_run0 = nullptr, ev_chk = nullptr, ev_end = nullptr;
+    double clock_s = 0.0;
 };
 
 namespace {
@@ -296,6 +300,7 @@ int alloc_state(BatchSolver *b, int R) {
 void reset_stats(BatchSolver *b) {
     b->steps_done = b->spin_updates = 0;
     b->run_seconds = 0.0;
+    b->clock_s = 0.0;
     b->diverged = 0;
     b->ttt.assign(b->K, -1.0);
     b->ttt_steps.assign(b->K, -1);
@@ -452,6 +457,8 @@ void batch_destroy(BatchSolver *b) {
     void *ps[] = {b->d_n, b->d_spin, b->d_state, b->d_inv_s, b->d_w, b->d_eps, b->d_h1, b->d_g, b->d_idx};
     for (void *p : ps)
         if (p) (void)hipFree(p);
+    for (hipEvent_t e : {b->ev_run0, b->ev_chk, b->ev_end})
+        if (e) (void)hipEventDestroy(e);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -516,6 +523,13 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
     const auto t0 = std::chrono::steady_clock::now();
     const int ci = b->prm.check_interval;
     const bool track = !b->targets.empty();
+    const bool clocked = track && ci > 0;
+    if (clocked) {
+        for (hipEvent_t *e : {&b->ev_run0, &b->ev_chk, &b->ev_end})
+            if (!*e) GD_TRY(hipEventCreate(e));
+        GD_TRY(hipEventRecord(b->ev_run0, b->stream));
+    }
+    const double clock0 = b->clock_s;
     // Without targets (no time to record) the best of the checks is kept on
     // the device and read back once, at the end of the run.
     const bool deferred = ci > 0 && !track;
@@ -558,9 +572,11 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
             E.resize((size_t)b->K * b->R);
             GD_TRY(hipMemcpyAsync(E.data(), b->d_E, E.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   b->stream));
+            if (clocked) GD_TRY(hipEventRecord(b->ev_chk, b->stream));
             GD_TRY(hipStreamSynchronize(b->stream));
-            const double now = b->run_seconds +
-                               std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            float ms = 0.0f;
+            if (clocked) GD_TRY(hipEventElapsedTime(&ms, b->ev_run0, b->ev_chk));
+            const double now = clock0 + ms * 1e-3;
             bool all = true;
             for (int k = 0; k < b->K; ++k) {
                 for (int r = 0; r < b->R; ++r) {
@@ -584,8 +600,14 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
         GD_TRY(hipMemcpyAsync(b->best_r.data(), b->d_best_r, b->K * sizeof(int), hipMemcpyDeviceToHost,
                               b->stream));
     }
+    if (clocked) GD_TRY(hipEventRecord(b->ev_end, b->stream));
     GD_TRY(hipStreamSynchronize(b->stream));
     b->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (clocked) {
+        float ms = 0.0f;
+        GD_TRY(hipEventElapsedTime(&ms, b->ev_run0, b->ev_end));
+        b->clock_s += ms * 1e-3;
+    }
     std::vector<int> fl((size_t)b->K * b->R);
     GD_TRY(hipMemcpy(fl.data(), b->d_flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost));
     b->diverged = int(std::count_if(fl.begin(), fl.end(), [](int v) { return v != 0; }));

@@ -192,6 +192,10 @@ struct gd_solver {
     CheckSlot *hchk = nullptr;            // 2 slots (hipHostMalloc)
     hipEvent_t ev_chk[2] = {nullptr, nullptr};
     hipEvent_t ev_run0 = nullptr;         // start of the current gd_run
+    hipEvent_t ev_end = nullptr;          // end of the current gd_run
+    // device time of the gd_run calls since gd_set_init / gd_set_state
+    // (start to end event of each), the clock of the time to target
+    double clock_s = 0.0;
     int64_t ev_used = 0;       // event pairs recorded by the current gd_run call
     int64_t ev_launches = 0;   // coupling launches bracketed by those pairs
     // small problems: kGraphSteps steps captured once in a hipGraph (launch
@@ -239,6 +243,7 @@ void reset_stats(gd_solver *s) {
     s->ttt_seconds = 0.0;
     s->ttt_steps = 0;
     s->best_energy = HUGE_VAL;
+    s->clock_s = 0.0;
 }
 
 template <class T>
@@ -856,7 +861,7 @@ void gd_destroy(gd_solver *s) {
     if (s->dG) (void)hipFree(s->dG);
     if (s->dJlp) (void)hipFree(s->dJlp);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {s->ev_chk[0], s->ev_chk[1], s->ev_run0})
+    for (hipEvent_t e : {s->ev_chk[0], s->ev_chk[1], s->ev_run0, s->ev_end})
         if (e) (void)hipEventDestroy(e);
     if (s->hchk) (void)hipHostFree(s->hchk);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -984,13 +989,17 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                            !(s->prm.flags & GD_F_ASYNC);
     int pend = -1;              // slot of the check not yet read, or -1
     int64_t pend_step = 0;
-    if (lookahead) {
-        if (!s->hchk) GD_HIP(hipHostMalloc(reinterpret_cast<void **>(&s->hchk), 2 * sizeof(gd_solver::CheckSlot)));
-        for (hipEvent_t *e : {&s->ev_chk[0], &s->ev_chk[1], &s->ev_run0})
+    // a time to target (recorded, or a stop) is device time: events at the
+    // start of each call and after each check
+    const bool clocked = ci > 0 && (s->prm.has_target || s->track_target);
+    if (lookahead && !s->hchk)
+        GD_HIP(hipHostMalloc(reinterpret_cast<void **>(&s->hchk), 2 * sizeof(gd_solver::CheckSlot)));
+    if (clocked) {
+        for (hipEvent_t *e : {&s->ev_chk[0], &s->ev_chk[1], &s->ev_run0, &s->ev_end})
             if (!*e) GD_HIP(hipEventCreate(e));
         GD_HIP(hipEventRecord(s->ev_run0, s->stream));
     }
-    const double run_s0 = s->run_seconds;
+    const double clock0 = s->clock_s;
     // host rule of a check read back: best energy, first check at the
     // target (returns true at that check)
     auto take_check = [&](double emin, int bi, int64_t step, double seconds) -> bool {
@@ -1011,7 +1020,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
         GD_HIP(hipEventSynchronize(s->ev_chk[pend]));
         float ms = 0.0f;
         GD_HIP(hipEventElapsedTime(&ms, s->ev_run0, s->ev_chk[pend]));
-        take_check(s->hchk[pend].e, s->hchk[pend].i, pend_step, run_s0 + ms * 1e-3);
+        take_check(s->hchk[pend].e, s->hchk[pend].i, pend_step, clock0 + ms * 1e-3);
         pend = -1;
         return GD_OK;
     };
@@ -1095,17 +1104,24 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             int bi = 0;
             GD_HIP(hipMemcpyAsync(&bi, s->dBest, sizeof(int), hipMemcpyDeviceToHost, s->stream));
             GD_HIP(hipMemcpyAsync(&emin, s->dE + s->Rp, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+            if (clocked) GD_HIP(hipEventRecord(s->ev_chk[0], s->stream));
             GD_HIP(hipStreamSynchronize(s->stream));
-            const bool hit = take_check(emin, bi, s->steps_done,
-                                        s->run_seconds +
-                                            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            float ms = 0.0f;
+            if (clocked) GD_HIP(hipEventElapsedTime(&ms, s->ev_run0, s->ev_chk[0]));
+            const bool hit = take_check(emin, bi, s->steps_done, clock0 + ms * 1e-3);
             if (hit && s->prm.has_target) break;
         }
     }
     if (s->prm.flags & GD_F_ASYNC) return GD_OK;
     if ((rc = read_pending()) != GD_OK) return rc;
+    if (clocked) GD_HIP(hipEventRecord(s->ev_end, s->stream));
     GD_HIP(hipStreamSynchronize(s->stream));
     s->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (clocked) {
+        float ms = 0.0f;
+        GD_HIP(hipEventElapsedTime(&ms, s->ev_run0, s->ev_end));
+        s->clock_s += ms * 1e-3;
+    }
     if (timed) {
         for (int64_t k = 0; k < s->ev_used; ++k) {
             float ms = 0.0f;
