@@ -179,6 +179,7 @@ def batch_instances(K, seed=1):
 # 2 per neighbour (multiply-add) + 12 for the pointwise update of Eq. (main, gamma)
 SPARSE_FLOPS_PER_UPDATE = lambda d: 2 * d + 12
 PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_LDS_GBS = 78643.2         # 256 CU x 128 B per clock x 2.4 GHz
 
 
 def bench_batch(args, wl, steps):
@@ -191,21 +192,28 @@ def bench_batch(args, wl, steps):
     sizes, insts = batch_instances(K)
     x0 = np.concatenate([I.psi0_real(int(n), R, 5000 + k).ravel() for k, n in enumerate(sizes)])
     torch.cuda.init()
-    B = gd.BatchSolver(insts, dt=wl["dt"], eps=0.1, check_interval=args.check)
+    B = gd.BatchSolver(insts, dt=wl["dt"], eps=0.1, check_interval=args.check, flags=gd.GD_F_PROFILE)
     B.set_init(R, x0)
     if args.warmup:
         B.run(args.warmup)
     torch.cuda.synchronize()
+    st0 = B.stats()
     t0 = time.perf_counter()
     B.run(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st = B.stats()
+    # device time of the timed persistent launches (HIP events around each)
+    kern_s = (st.kernel_ms - st0.kernel_ms) / 1e3
     E, best = B.energy()
     B.close()
     total = int(np.sum(sizes))
     upd = total * R * steps
     flops = upd * SPARSE_FLOPS_PER_UPDATE(3)
+    # roofline of the kernel: the LDS traffic of a spin-update (three neighbour
+    # amplitudes read, its own written: 16 B) against the LDS bandwidth of the
+    # chip (128 B per clock per CU, 256 CUs, 2.4 GHz = 78.6 TB/s)
+    lds_bytes = 16.0 * upd
     out = {
         "metric": "spin-updates/s (N*R*steps/s)", "value": upd / el, "unit": "spin-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": el / steps * 1e3,
@@ -213,10 +221,12 @@ def bench_batch(args, wl, steps):
         "data": "synthetic",
         "config": {"workload": wl["desc"], "instances": K, "sum_n": total, "R": R,
                    "energy_check_every": args.check, "kernel_config": st.kernel_config},
-        "roofline": {"bound": "alu", "achieved": flops / el / 1e12, "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flops / el / 1e12 / PEAK_FP32_VALU_TFLOPS,
+        "roofline": {"bound": "lds", "achieved": lds_bytes / kern_s / 1e9, "peak": PEAK_LDS_GBS,
+                     "unit": "GB/s", "frac": lds_bytes / kern_s / 1e9 / PEAK_LDS_GBS,
                      "traffic": None, "kernel": "batch_ell_euler",
-                     "flops_per_update": SPARSE_FLOPS_PER_UPDATE(3)},
+                     "launches": int(st.kernel_launches - st0.kernel_launches),
+                     "kernel_seconds": kern_s, "lds_bytes_per_update": 16,
+                     "alu_tflops": flops / kern_s / 1e12, "alu_peak_tflops": PEAK_FP32_VALU_TFLOPS},
         "best_energy_sum": float(E.min(1).sum()),
     }
     if not args.no_cpu_baseline:

@@ -108,7 +108,10 @@ typedef enum gd_variant { GD_VARIANT_GD = 0, GD_VARIANT_MOD = 1 } gd_variant;
                                   pair per step (kernel_ms / kernel_launches = mean launch time);
                                   the fused small-problem kernel is timed per launch and counts
                                   its coupling evaluations (steps x stages, + 1 for an energy
-                                  check that closes the launch) as launches */
+                                  check that closes the launch) as launches; steps replayed from
+                                  a captured graph (few-trajectory matrix-vector kernels) are
+                                  timed per replay and count their launches; batch solvers time
+                                  every persistent launch (a chunk of steps) and count it once */
 
 /* Parameters of a solver.  Fill with gd_default_params(), then override.
  * struct_size must be sizeof(gd_params) of the caller's header. */

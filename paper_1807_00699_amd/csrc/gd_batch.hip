@@ -27,9 +27,33 @@ namespace gd {
 
 namespace {
 
-template <int T, int NT, int E>
+// Coupling term d of a spin from its packed words (word 0: idx0 | idx1 << 16;
+// word 1: idx2 | sign2 << 29 | sign1 << 30 | sign0 << 31; a missing coupling
+// points at the all-zero row n_max): the neighbour's amplitude with the
+// coupling's sign applied.  mag * (+-x) equals the ELL product (+-mag) * x
+// bit for bit, so fma(+-x, mag, c) reproduces the list's sum.
+template <int D, int T>
+__device__ inline float signed_nb(const unsigned char *xlb, const uint2 w, int rb) {
+    constexpr int SH = T == 1 ? 2 : (T == 2 ? 3 : (T == 4 ? 4 : (T == 8 ? 5 : 6)));   // log2(4 T)
+    const unsigned int idx = D == 0 ? (w.x & 0xFFFFu) : (D == 1 ? (w.x >> 16) : (w.y & 0xFFFFu));
+    const float v = *reinterpret_cast<const float *>(xlb + (idx << SH) + rb);
+    const unsigned int sgn = (w.y << D) & 0x80000000u;      // bit 31 - D
+    return __uint_as_float(__float_as_uint(v) ^ sgn);
+}
+
+// PK: the neighbours of the thread's spins live in registers (two words per
+// slot, read once per item from the packed form) instead of LDS, so a
+// coupling term costs one LDS read (the neighbour's amplitude) and a few
+// integer operations instead of three LDS reads; the products and their
+// order are those of the ELL list (three terms; padding reads the zero row).
+// UNI: every spin has the rate eps0 and no field term (h_1 = -0, the value
+// a zero field maps to), so the slots carry no per-spin constants.
+// DB (with PK): the amplitudes are double-buffered in LDS, step t reads one
+// copy and writes the other, so a step needs one barrier instead of two.
+template <int T, int NT, int E, bool PK, bool UNI, bool DB>
 __global__ void __launch_bounds__(NT)
 batch_ell_euler(BatchArgs a) {
+    static_assert(!DB || PK, "double buffering is a variant of the packed form");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int tid = threadIdx.x;
     const int r = tid % T;
@@ -37,9 +61,10 @@ batch_ell_euler(BatchArgs a) {
     constexpr int ISTR = NT / T;
     const int dmax = a.dmax;
     float *xl = reinterpret_cast<float *>(smem);                               // [nmax][T]
-    float *wl = xl + (size_t)a.nmax * T;                                        // [nmax][dmax]
+    float *wl = xl + (size_t)a.nmax * T;                                        // [nmax][dmax] (not PK)
     unsigned short *il = reinterpret_cast<unsigned short *>(wl + (size_t)a.nmax * dmax);
     double *red = reinterpret_cast<double *>(smem);                             // reuse after the run
+    const uint2 *pk = reinterpret_cast<const uint2 *>(a.ell_pack);
 
     for (int it = a.wg_off[blockIdx.x]; it < a.wg_off[blockIdx.x + 1]; ++it) {
         const int item = a.items[it];
@@ -49,48 +74,83 @@ batch_ell_euler(BatchArgs a) {
         const long long spin0 = a.inst_spin[k];
         const long long st0 = a.inst_state[k] + (long long)rr * n;   // [R][n] block of instance k
         const float inv_s = a.inst_inv_s[k];
-        // couplings of instance k into LDS
-        for (int q = tid; q < n * dmax; q += NT) {
-            wl[q] = a.ell_w[spin0 * dmax + q];
-            il[q] = (unsigned short)a.ell_idx[spin0 * dmax + q];
+        const float mag = PK ? a.inst_wmag[k] : 0.0f;
+        // couplings of instance k into LDS (PK: only the zero row n_max, which
+        // the reduction of the previous item may have overwritten)
+        if constexpr (!PK) {
+            for (int q = tid; q < n * dmax; q += NT) {
+                wl[q] = a.ell_w[spin0 * dmax + q];
+                il[q] = (unsigned short)a.ell_idx[spin0 * dmax + q];
+            }
+        } else {
+            for (int q = tid; q < T; q += NT) xl[(size_t)a.nmax * T + q] = 0.0f;
+            if constexpr (DB)
+                for (int q = tid; q < T; q += NT) xl[(size_t)(2 * a.nmax + 1) * T + q] = 0.0f;
         }
-        float xo[E], go[E], ep[E], hh[E];
+        // DB: buffer b at xl + b (n_max + 1) T; step t reads buffer t % 2
+        float *xl1 = xl + (size_t)(a.nmax + 1) * T;
+        const unsigned char *xlb = reinterpret_cast<const unsigned char *>(xl);
+        const int rb = r * 4;
+        float xo[E], go[E], ep[UNI ? 1 : E], hh[UNI ? 1 : E];
+        uint2 nb[PK ? E : 1];
+        if constexpr (UNI) {
+            ep[0] = a.eps0;
+            hh[0] = -0.0f;
+        }
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const int i = ibase + s * ISTR;
-            xo[s] = go[s] = ep[s] = hh[s] = 0.0f;
+            xo[s] = go[s] = 0.0f;
+            if constexpr (!UNI) ep[s] = hh[s] = 0.0f;
+            if constexpr (PK) nb[s] = uint2{0u, 0u};
             if (i < n) {
                 xo[s] = a.x[st0 + i];
                 go[s] = a.gam[st0 + i];
-                ep[s] = a.eps[spin0 + i];
-                hh[s] = a.h1[spin0 + i];
+                if constexpr (!UNI) {
+                    ep[s] = a.eps[spin0 + i];
+                    hh[s] = a.h1[spin0 + i];
+                }
+                if constexpr (PK) nb[s] = pk[spin0 + i];
                 xl[i * T + r] = xo[s];
             }
         }
         __syncthreads();
         const float dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
         for (int step = 0; step < a.steps; ++step) {
+            const unsigned char *src = DB && (step & 1) ? reinterpret_cast<const unsigned char *>(xl1) : xlb;
+            float *dst = DB && !(step & 1) ? xl1 : xl;
 #pragma unroll
             for (int s = 0; s < E; ++s) {
                 const int i = ibase + s * ISTR;
                 if (i < n) {
                     float c = 0.0f;
-                    for (int d = 0; d < dmax; ++d) c += wl[i * dmax + d] * xl[il[i * dmax + d] * T + r];
+                    if constexpr (PK) {
+                        c = __builtin_fmaf(signed_nb<0, T>(src, nb[s], rb), mag, c);
+                        c = __builtin_fmaf(signed_nb<1, T>(src, nb[s], rb), mag, c);
+                        c = __builtin_fmaf(signed_nb<2, T>(src, nb[s], rb), mag, c);
+                    } else {
+                        for (int d = 0; d < dmax; ++d) c += wl[i * dmax + d] * xl[il[i * dmax + d] * T + r];
+                    }
                     const float x = xo[s];
                     const float rho = x * x;
-                    const float f = x * (go[s] - gc - rho) + c * inv_s + hh[s];
+                    const float f = x * (go[s] - gc - rho) + c * inv_s + hh[UNI ? 0 : s];
                     xo[s] = x + dt * f;
-                    go[s] = go[s] + dt * (ep[s] * (rho_th - rho));
+                    go[s] = go[s] + dt * (ep[UNI ? 0 : s] * (rho_th - rho));
+                    if constexpr (DB) dst[i * T + r] = xo[s];
                 }
             }
             __syncthreads();
+            if constexpr (!DB) {
 #pragma unroll
-            for (int s = 0; s < E; ++s) {
-                const int i = ibase + s * ISTR;
-                if (i < n) xl[i * T + r] = xo[s];
+                for (int s = 0; s < E; ++s) {
+                    const int i = ibase + s * ISTR;
+                    if (i < n) xl[i * T + r] = xo[s];
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
+        // the buffer that holds the final amplitudes (DB: written by the last step)
+        const float *xf = DB && (a.steps & 1) ? xl1 : xl;
         // write back the state, flag non-finite trajectories
         bool bad = false;
 #pragma unroll
@@ -110,19 +170,38 @@ batch_ell_euler(BatchArgs a) {
             if (i < n) {
                 const double si = xo[s] < 0.0f ? -1.0 : 1.0;
                 double h = 0.0;
-                for (int d = 0; d < dmax; ++d) {
-                    const float xj = xl[il[i * dmax + d] * T + r];
-                    h += (double)wl[i * dmax + d] * (xj < 0.0f ? -1.0 : 1.0);
+                if constexpr (PK) {
+                    // sign(x_j) times the coupling's sign, times mag; the zero row reads +0 (sign +1)
+                    // with weight 0, so padding is skipped by its index
+                    const uint2 w = nb[s];
+                    const unsigned int idx[3] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if ((int)idx[d] == a.nmax) continue;
+                        const float xj = xf[idx[d] * T + r];
+                        const double sg = ((w.y << d) & 0x80000000u) ? -1.0 : 1.0;
+                        h += (double)mag * sg * (xj < 0.0f ? -1.0 : 1.0);
+                    }
+                } else {
+                    for (int d = 0; d < dmax; ++d) {
+                        const float xj = xf[il[i * dmax + d] * T + r];
+                        h += (double)wl[i * dmax + d] * (xj < 0.0f ? -1.0 : 1.0);
+                    }
                 }
                 e += -si * h + (double)a.g[spin0 + i] * si;
             }
         }
+        // per trajectory: lanes of one trajectory (tid % T) within a wave by a
+        // butterfly over the lane bits above T, then the waves in order
+        // (a fixed order: the result does not depend on timing)
+#pragma unroll
+        for (int m = 32; m >= T; m >>= 1) e += __shfl_xor(e, m);
         __syncthreads();                       // all reads of xl / wl are done
-        red[tid] = e;
+        if ((tid & 63) < T) red[(tid >> 6) * T + (tid & 63)] = e;
         __syncthreads();
         if (tid < T) {
             double tot = 0.0;
-            for (int q = tid; q < NT; q += T) tot += red[q];   // fixed order
+            for (int w = 0; w < NT / 64; ++w) tot += red[w * T + tid];
             a.E[(long long)k * a.R + (item % a.nslices) * T + tid] = tot;
         }
         if (bad) a.flags[(long long)k * a.R + rr] = 1;
@@ -130,19 +209,31 @@ batch_ell_euler(BatchArgs a) {
     }
 }
 
-// Variants {T, NT, E}: T trajectories per item, NT threads, E slots per thread
-// (n_max <= E * NT / T).
-#define GD_BATCH_VARIANTS(X) \
-    X(0, 8, 1024, 16)        \
-    X(1, 4, 512, 16)         \
-    X(2, 2, 256, 16)         \
-    X(3, 8, 512, 32)         \
-    X(4, 16, 1024, 16)       \
-    X(5, 4, 1024, 8)         \
-    X(6, 1, 256, 16)
+// Variants {T, NT, E, PK, UNI, DB}: T trajectories per item, NT threads, E
+// slots per thread (n_max <= E * NT / T), PK neighbours in registers (packed
+// form; two more registers per slot), UNI uniform eps and no field (two
+// fewer), DB amplitudes double-buffered in LDS (one barrier per step); the
+// slot count keeps each variant within the register budget of its
+// workgroup size.
+#define GD_BATCH_VARIANTS(X)                 \
+    X(0, 8, 1024, 16, false, false, false)   \
+    X(1, 4, 512, 16, false, false, false)    \
+    X(2, 2, 256, 16, false, false, false)    \
+    X(3, 8, 512, 32, false, false, false)    \
+    X(4, 16, 1024, 16, false, false, false)  \
+    X(5, 4, 1024, 8, false, false, false)    \
+    X(6, 1, 256, 16, false, false, false)    \
+    X(7, 4, 512, 16, true, false, false)     \
+    X(8, 4, 1024, 8, true, false, false)     \
+    X(9, 2, 512, 8, true, false, false)      \
+    X(10, 2, 256, 16, true, false, false)    \
+    X(11, 4, 1024, 8, true, true, false)     \
+    X(12, 4, 1024, 8, true, true, true)      \
+    X(13, 4, 1024, 8, true, false, true)     \
+    X(14, 2, 512, 8, true, false, true)
 
-constexpr int kBatchCfg[][3] = {
-#define GD_ROW(id, t, nt, e) {t, nt, e},
+constexpr int kBatchCfg[][6] = {
+#define GD_ROW(id, t, nt, e, pk, uni, db) {t, nt, e, pk, uni, db},
     GD_BATCH_VARIANTS(GD_ROW)
 #undef GD_ROW
 };
@@ -157,11 +248,15 @@ BatchConfig batch_config(int idx) {
     c.traj = kBatchCfg[idx][0];
     c.threads = kBatchCfg[idx][1];
     c.slots = kBatchCfg[idx][2];
+    c.packed = kBatchCfg[idx][3] != 0;
+    c.uniform = kBatchCfg[idx][4] != 0;
+    c.dbuf = kBatchCfg[idx][5] != 0;
     return c;
 }
 
 size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax) {
-    size_t b = (size_t)nmax * c.traj * 4 + (size_t)nmax * dmax * 4 + (size_t)nmax * dmax * 2;
+    size_t b = (size_t)(nmax + 1) * c.traj * 4 * (c.dbuf ? 2 : 1);   // + the zero row(s) of the packed form
+    if (!c.packed) b += (size_t)nmax * dmax * 4 + (size_t)nmax * dmax * 2;
     b = (b + 15) / 16 * 16;
     const size_t red = (size_t)c.threads * 8;
     return b > red ? b : red;
@@ -169,9 +264,9 @@ size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax) {
 
 hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax) {
     const int lds = int(batch_lds_bytes(c, nmax, dmax));
-#define GD_CASE(id, t, nt, e)                                                                   \
-    case id:                                                                                    \
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_ell_euler<t, nt, e>), \
+#define GD_CASE(id, t, nt, e, pk, uni, db)                                                                   \
+    case id:                                                                                                 \
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_ell_euler<t, nt, e, pk, uni, db>), \
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     switch (c.id) { GD_BATCH_VARIANTS(GD_CASE) }
 #undef GD_CASE
@@ -220,10 +315,11 @@ hipError_t launch_batch_best(const double *E, int K, int R, double *best_E, int 
 
 hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipStream_t st) {
     const size_t lds = batch_lds_bytes(c, a.nmax, a.dmax);
-#define GD_CASE(id, t, nt, e)                                           \
+#define GD_CASE(id, t, nt, e, pk, uni, db)                              \
     case id:                                                            \
         if (a.nmax > e * nt / t) return hipErrorInvalidValue;           \
-        batch_ell_euler<t, nt, e><<<nwg, nt, lds, st>>>(a);             \
+        if (pk && (!a.ell_pack || !a.inst_wmag || a.dmax > 3 || a.nmax > 65535)) return hipErrorInvalidValue; \
+        batch_ell_euler<t, nt, e, pk, uni, db><<<nwg, nt, lds, st>>>(a); \
         return hipGetLastError();
     switch (c.id) { GD_BATCH_VARIANTS(GD_CASE) }
 #undef GD_CASE

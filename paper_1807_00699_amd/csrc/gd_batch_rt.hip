@@ -56,7 +56,8 @@ int upload(T **p, const std::vector<T> &v) {
 }
 
 std::mutex g_btune_mu;
-std::map<std::tuple<int, int, int, int, long long>, int> g_btune;  // (K, R, nmax, dmax, total) -> cfg
+// (K, R, nmax, dmax, total, packed form + 2 uniform rates) -> cfg
+std::map<std::tuple<int, int, int, int, long long, int>, int> g_btune;
 
 }  // namespace
 
@@ -76,6 +77,12 @@ struct BatchSolver {
     long long *d_spin = nullptr, *d_state = nullptr;
     float *d_inv_s = nullptr, *d_w = nullptr, *d_eps = nullptr, *d_h1 = nullptr, *d_g = nullptr;
     int *d_idx = nullptr;
+    // packed neighbours (dmax <= 3, one coupling magnitude per instance):
+    // [total][2] words and [K] magnitudes, or null when the batch does not qualify
+    unsigned int *d_pack = nullptr;
+    float *d_wmag = nullptr;
+    bool packable = false;
+    bool no_field = true;             // every g_i = 0
     // state
     int R = 0;
     bool have_state = false;
@@ -104,6 +111,10 @@ struct BatchSolver {
     // (an event at the start of each call, one after each check, one at the end)
     hipEvent_t ev_run0 = nullptr, ev_chk = nullptr, ev_end = nullptr;
     double clock_s = 0.0;
+    // GD_F_PROFILE: an event pair around every persistent launch
+    std::vector<hipEvent_t> prof_ev;
+    double kernel_ms = 0.0;
+    int64_t kernel_launches = 0;
 };
 
 namespace {
@@ -140,6 +151,8 @@ BatchArgs make_args(BatchSolver *b, int steps, float dt) {
     a.inst_inv_s = b->d_inv_s;
     a.ell_idx = b->d_idx;
     a.ell_w = b->d_w;
+    a.ell_pack = b->d_pack;
+    a.inst_wmag = b->d_wmag;
     a.eps = b->d_eps;
     a.h1 = b->d_h1;
     a.g = b->d_g;
@@ -157,11 +170,22 @@ BatchArgs make_args(BatchSolver *b, int steps, float dt) {
     a.dt = dt;
     a.gamma_c = float(b->prm.gamma_c);
     a.rho_th = float(b->prm.rho_th);
+    a.eps0 = b->eps_host.empty() ? 0.0f : b->eps_host[0];
     return a;
+}
+
+// one eps for every spin and no field: the variants without per-spin constants apply
+bool uniform_rates(const BatchSolver *b) {
+    if (!b->no_field || b->eps_host.empty()) return false;
+    for (float e : b->eps_host)
+        if (std::memcmp(&e, &b->eps_host[0], sizeof(float)) != 0) return false;
+    return true;
 }
 
 bool config_fits(const BatchSolver *b, const BatchConfig &c) {
     if (b->R % c.traj) return false;
+    if (c.packed && !b->packable) return false;
+    if (c.uniform && !uniform_rates(b)) return false;
     if ((long long)b->nmax * c.traj > (long long)c.slots * c.threads) return false;
     return batch_lds_bytes(c, b->nmax, b->dmax) <= 160 * 1024;
 }
@@ -221,7 +245,7 @@ int choose_config(BatchSolver *b) {
             return gd_fail(GD_E_INVALID_ARG, "GD_BATCH_CONFIG does not fit this batch");
         return build_schedule(b, batch_config(id));
     }
-    auto key = std::make_tuple(b->K, b->R, b->nmax, b->dmax, b->total);
+    auto key = std::make_tuple(b->K, b->R, b->nmax, b->dmax, b->total, int(b->packable) + 2 * int(uniform_rates(b)));
     {
         std::lock_guard<std::mutex> lk(g_btune_mu);
         auto it = g_btune.find(key);
@@ -301,6 +325,8 @@ void reset_stats(BatchSolver *b) {
     b->steps_done = b->spin_updates = 0;
     b->run_seconds = 0.0;
     b->clock_s = 0.0;
+    b->kernel_ms = 0.0;
+    b->kernel_launches = 0;
     b->diverged = 0;
     b->ttt.assign(b->K, -1.0);
     b->ttt_steps.assign(b->K, -1);
@@ -413,6 +439,7 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
         } else {
             gk.assign(n, 0.0f);
         }
+        for (float v : gk) b->no_field = b->no_field && v == 0.0f;
         gvec.insert(gvec.end(), gk.begin(), gk.end());
     }
     b->dmax = std::max(b->dmax, 1);
@@ -428,6 +455,41 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
             const long long q = b->spin_off[k] + i;
             h1[q] = float(-double(gvec[q]) * std::sqrt(p->rho_th) / b->scale[k]);
         }
+    // packed neighbours: at most 3 per spin, indices below 2^16 - 1 and every
+    // nonzero coupling of an instance of one magnitude (e.g. +-1 max-cut
+    // couplings); each coupling becomes a neighbour index and a sign bit, a
+    // missing one the index n_max of an all-zero amplitude row
+    std::vector<unsigned int> pack;
+    std::vector<float> wmag(count, 1.0f);
+    b->packable = b->dmax <= 3 && b->nmax < 65535;
+    for (int k = 0; k < count && b->packable; ++k) {
+        float mag = 0.0f;
+        for (int i = 0; i < b->n[k] && b->packable; ++i)
+            for (int d = 0; d < b->dmax; ++d) {
+                const float v = w[(size_t)(b->spin_off[k] + i) * b->dmax + d];
+                if (v == 0.0f) continue;
+                if (mag == 0.0f) mag = std::fabs(v);
+                else if (std::fabs(v) != mag) b->packable = false;
+            }
+        if (mag > 0.0f) wmag[k] = mag;
+    }
+    if (b->packable) {
+        pack.assign((size_t)b->total * 2, 0u);
+        for (int k = 0; k < count; ++k)
+            for (int i = 0; i < b->n[k]; ++i) {
+                const long long q = b->spin_off[k] + i;
+                const unsigned int zero_row = (unsigned int)b->nmax;
+                unsigned int id[3] = {zero_row, zero_row, zero_row}, neg[3] = {0u, 0u, 0u};
+                for (int d = 0; d < b->dmax; ++d) {
+                    const float v = w[(size_t)q * b->dmax + d];
+                    if (v == 0.0f) continue;
+                    id[d] = (unsigned int)idx[(size_t)q * b->dmax + d];
+                    neg[d] = v < 0.0f ? 1u : 0u;
+                }
+                pack[(size_t)q * 2] = id[0] | (id[1] << 16);
+                pack[(size_t)q * 2 + 1] = id[2] | (neg[2] << 29) | (neg[1] << 30) | (neg[0] << 31);
+            }
+    }
     b->eps_host.assign(b->total, float(p->eps));
     if (p->stream) {
         b->stream = static_cast<hipStream_t>(p->stream);
@@ -441,6 +503,8 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
     if (rc == GD_OK) rc = upload(&b->d_inv_s, b->inv_s);
     if (rc == GD_OK) rc = upload(&b->d_idx, idx);
     if (rc == GD_OK) rc = upload(&b->d_w, w);
+    if (rc == GD_OK && b->packable) rc = upload(&b->d_pack, pack);
+    if (rc == GD_OK && b->packable) rc = upload(&b->d_wmag, wmag);
     if (rc == GD_OK) rc = upload(&b->d_eps, b->eps_host);
     if (rc == GD_OK) rc = upload(&b->d_h1, h1);
     if (rc == GD_OK) rc = upload(&b->d_g, gvec);
@@ -454,11 +518,13 @@ void batch_destroy(BatchSolver *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     free_state(b);
-    void *ps[] = {b->d_n, b->d_spin, b->d_state, b->d_inv_s, b->d_w, b->d_eps, b->d_h1, b->d_g, b->d_idx};
+    void *ps[] = {b->d_n, b->d_spin, b->d_state, b->d_inv_s, b->d_w, b->d_eps, b->d_h1, b->d_g, b->d_idx,
+                  b->d_pack, b->d_wmag};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : {b->ev_run0, b->ev_chk, b->ev_end})
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -539,6 +605,8 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
         GD_TRY(hipMemcpyAsync(b->d_best_r, b->best_r.data(), b->K * sizeof(int), hipMemcpyHostToDevice,
                               b->stream));
     }
+    const bool timed = (b->prm.flags & GD_F_PROFILE) != 0;
+    size_t nprof = 0;   // event pairs used by this call
     int64_t done = 0;
     std::vector<double> E;
     while (done < steps) {
@@ -562,7 +630,16 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
             if (ie != hipSuccess) return gd_fail(GD_E_DEVICE, hipGetErrorString(ie));
             b->graph_steps = cs;
         }
+        if (timed) {
+            while (b->prof_ev.size() < 2 * nprof + 2) {
+                hipEvent_t e;
+                GD_TRY(hipEventCreate(&e));
+                b->prof_ev.push_back(e);
+            }
+            GD_TRY(hipEventRecord(b->prof_ev[2 * nprof], b->stream));
+        }
         GD_TRY(hipGraphLaunch(b->graph, b->stream));
+        if (timed) GD_TRY(hipEventRecord(b->prof_ev[2 * nprof++ + 1], b->stream));
         done += cs;
         b->steps_done += cs;
         b->spin_updates += (int64_t)b->total * b->R * cs;
@@ -607,6 +684,12 @@ int batch_run(BatchSolver *b, int R, int64_t steps) {
         float ms = 0.0f;
         GD_TRY(hipEventElapsedTime(&ms, b->ev_run0, b->ev_end));
         b->clock_s += ms * 1e-3;
+    }
+    for (size_t q = 0; q < nprof; ++q) {
+        float ms = 0.0f;
+        GD_TRY(hipEventElapsedTime(&ms, b->prof_ev[2 * q], b->prof_ev[2 * q + 1]));
+        b->kernel_ms += ms;
+        b->kernel_launches += 1;
     }
     std::vector<int> fl((size_t)b->K * b->R);
     GD_TRY(hipMemcpy(fl.data(), b->d_flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost));
@@ -697,8 +780,8 @@ int batch_stats(BatchSolver *b, gd_run_stats *out) {
     out->steps_done = b->steps_done;
     out->spin_updates = b->spin_updates;
     out->run_seconds = b->run_seconds;
-    out->kernel_ms = 0.0;
-    out->kernel_launches = 0;
+    out->kernel_ms = b->kernel_ms;
+    out->kernel_launches = b->kernel_launches;
     out->diverged = b->diverged;
     int reached = !b->targets.empty();
     double t = 0.0;

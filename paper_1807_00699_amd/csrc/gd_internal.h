@@ -116,6 +116,12 @@ struct BatchArgs {
     const float *inst_inv_s;      // [K] 1 / coupling scale
     const int *ell_idx;           // [sum n][dmax] local neighbour indices (padding: 0)
     const float *ell_w;           // [sum n][dmax] couplings (padding: 0)
+    // packed form (dmax <= 3, one coupling magnitude per instance, n_max < 2^16 - 1):
+    // [sum n][2] words, word 0 = idx0 | idx1 << 16, word 1 = idx2 | neg2 << 29 |
+    // neg1 << 30 | neg0 << 31 (neg: coupling -mag, else +mag); a missing
+    // coupling has index n_max, an amplitude row that holds zeros
+    const unsigned int *ell_pack;
+    const float *inst_wmag;       // [K] the magnitude of instance k's couplings
     const float *eps, *h1, *g;    // [sum n]
     float *x, *gam;               // state [sum_k R n_k]
     double *E;                    // [K][R] energies after the launch
@@ -124,6 +130,7 @@ struct BatchArgs {
     const int *items;             // item = k * nslices + slice
     int nslices, R, dmax, nmax, steps;
     float dt, gamma_c, rho_th;
+    float eps0;                   // the rate of every spin, for variants that need uniform eps and no field
 };
 
 struct BatchConfig {
@@ -131,6 +138,9 @@ struct BatchConfig {
     int traj;     // trajectories per work item
     int threads;  // workgroup size
     int slots;    // spins per thread (n_max <= slots * threads / traj)
+    bool packed;  // neighbours in registers from the packed form (LDS: amplitudes only)
+    bool uniform; // one eps for every spin and no field (eps0, h_1 = 0): no per-slot constants
+    bool dbuf;    // amplitudes double-buffered in LDS (packed form): one barrier per step
 };
 
 int batch_config_count();

@@ -101,7 +101,9 @@ def test_batch_independence_variants_and_graph_chunks_bitwise():
     insts, _ = _instances(sizes, 20)
     x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 20)])
     ref = None
-    for cfg in ("0", "1", "2", "6"):
+    # 0-6: couplings in LDS; 7-14: neighbours in registers (packed form),
+    # 11-12 uniform rates, 12-14 double-buffered amplitudes
+    for cfg in ("0", "1", "2", "6", "7", "8", "9", "10", "11", "12", "13", "14"):
         os.environ["GD_BATCH_CONFIG"] = cfg
         try:
             with gd.BatchSolver(insts, check_interval=25) as B:
@@ -249,3 +251,42 @@ def test_batch_deferred_best_matches_per_check_readback():
         out.append(seen)
     assert out[0] == out[1], out
     assert all(np.all(np.isfinite(s[0])) for s in out[0])
+
+
+def test_packed_variants_need_one_coupling_magnitude_per_instance():
+    """A batch whose instance mixes coupling magnitudes (+-1 and +-2) has no
+    packed form: pinning a packed variant is refused, a general one runs and
+    matches the oracle's energies of its readout."""
+    sizes = [80, 96]
+    R = 8
+    insts, dense = _instances(sizes, 40)
+    v = insts[1]["val"].copy()
+    v[::5] *= 2.0                       # symmetric: both (i, j) and (j, i) come from one edge value
+    rp, col = insts[1]["row_ptr"], insts[1]["col"]
+    Jm = np.zeros((96, 96), np.float32)
+    for i in range(96):
+        for q in range(rp[i], rp[i + 1]):
+            Jm[i, col[q]] = v[q]
+    if not np.array_equal(Jm, Jm.T):    # keep it symmetric: rebuild values from the dense matrix
+        Jm = np.triu(Jm, 1)
+        Jm = Jm + Jm.T
+        v = np.array([Jm[i, col[q]] for i in range(96) for q in range(rp[i], rp[i + 1])], np.float32)
+    insts[1] = dict(n=96, row_ptr=rp, col=col, val=v)
+    dense[1] = Jm
+    x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 40)])
+    os.environ["GD_BATCH_CONFIG"] = "7"
+    try:
+        with pytest.raises(gd.GDError) as ei:
+            with gd.BatchSolver(insts) as B:
+                B.set_init(R, x0)
+        assert ei.value.code == gd.GD_E_INVALID_ARG
+    finally:
+        del os.environ["GD_BATCH_CONFIG"]
+    with gd.BatchSolver(insts) as B:
+        B.set_init(R, x0)
+        B.run(100)
+        assert B.stats().kernel_config < 7
+        E, _ = B.energy()
+        sp = B.split(B.spins())
+    for k, J in enumerate(dense):
+        assert np.array_equal(E[k], O.energy_ising(J, sp[k]).astype(np.float64))
