@@ -75,20 +75,23 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_F32 = 78.6    # FP32 vector FMA without packed math (256 CUs, 2.4 GHz)
 
 
-def kernel_traffic(config_id, fp32=True, workload="xy1024"):
+KERNEL_SOURCES = {"dense_step_f32": ("gd_dense.hip", "gd_epilogue.h"),
+                  "dense_step_lp": ("gd_dense_lp.h", "gd_epilogue.h"),
+                  "gemv_step_k": ("gd_gemv.h", "gd_epilogue.h")}
+
+
+def kernel_traffic(config_id, kern="dense_step_f32", workload="xy1024"):
     """HBM bytes per launch of a coupling kernel from its committed counter
     summary (profiles/<kernel>_<workload>_counters.txt), or None when there is
     none, the kernel sources changed since the counters were taken or another
     variant runs."""
     import hashlib
-    kern = "dense_step_f32" if fp32 else "dense_step_lp"
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
     csrc = os.path.join(ROOT, "paper_1807_00699_amd", "csrc")
-    files = ("gd_dense.hip", "gd_epilogue.h") if fp32 else ("gd_dense_lp.hip", "gd_epilogue.h")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in files)
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES[kern])
     if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_source_sha256_16"):
         return None
     if int(kv.get("kernel_config_id", -1)) != int(config_id):
@@ -779,7 +782,8 @@ def headline(args):
             "device_check_equals_fp64_rescore": bool(np.array_equal(E, Ed) and best == best_d),
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved / peak,
-                         "traffic": kernel_traffic(st.kernel_config, prec == gd.GD_PREC_FP32, "ising4096"),
+                         "traffic": kernel_traffic(st.kernel_config, "dense_step_f32" if prec == gd.GD_PREC_FP32
+                                                    else "dense_step_lp", "ising4096"),
                          "kernel": "dense_step_f32" if prec == gd.GD_PREC_FP32 else "dense_step_lp",
                          "launches": int(launches), "avg_launch_us": avg_s * 1e6,
                          "flops_per_launch": flops_launch},
@@ -1010,7 +1014,10 @@ def main():
         "config": {"workload": wl["desc"], "n": n, "R": R, "integrator": wl["integrator"],
                    "dt": wl["dt"], "energy_check_every": args.check, "kernel_config": st.kernel_config},
         "roofline": ({"bound": "hbm", "achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                      "frac": hbm_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "gemv_step_k",
+                      "frac": hbm_gbs / PEAK_HBM_GBS,
+                      "traffic": (kernel_traffic(st.kernel_config, "gemv_step_k", "ising4096_r1")
+                                  if args.workload == "gemv4096" else None),
+                      "kernel": "gemv_step_k",
                       "launches": int(launches), "avg_launch_us": avg_s * 1e6,
                       "bytes_per_launch": bytes_launch}
                      if gemv else
@@ -1021,7 +1028,7 @@ def main():
                      if small else
                      {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[prec_name],
                       "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS[prec_name],
-                      "traffic": (kernel_traffic(st.kernel_config)
+                      "traffic": (kernel_traffic(st.kernel_config, "dense_step_f32")
                                   if args.workload == "xy1024" else None),
                       "kernel": "dense_step_f32" if prec_name == "fp32" else "dense_step_lp",
                       "launches": int(launches),
