@@ -335,31 +335,12 @@ def bench_gdmod(args, wl, steps):
     print(json.dumps(out), flush=True)
 
 
-def _dense_ttt(J, x0, prec, steps, check, target):
-    """seconds and steps to the first check with best energy <= target"""
-    from paper_1807_00699_amd import gd
-    with gd.Solver(J, model=gd.GD_ISING, dt=0.05, eps=0.1, precision=prec, check_interval=check) as S:
-        S.set_init(x0.shape[0], x0)
-        S.run(check)              # warm-up and kernel choice
-        S.set_init(x0.shape[0], x0)
-        gd.gd_set_targets(S.h, [target])
-        t0 = time.perf_counter()
-        S.run(steps)
-        wall = time.perf_counter() - t0
-        st = S.stats()
-        E, b = S.energy()
-    return (st.ttt_seconds if st.target_reached else None,
-            st.ttt_steps if st.target_reached else None, float(E[b]), wall)
-
-
 def compare_ttt(args):
-    """Time-to-target comparisons on one GPU (one JSON line):
-    (a) Ising N=4096 density-0.5 {-1,0,1}, R=4096, Euler: FP32 operands vs
-        BF16 operands with FP8-stored J, both with FP32 state;
-    (b) 256 held-out random 3-regular max-cut instances, N in [512,2048],
-        R=64: random start vs the learned proposal.
-    Targets: best-known energy + 0.1%, best-known = best over the runs made
-    here with a longer budget."""
+    """Time to target, random vs learned start (one JSON line): 256 held-out
+    random 3-regular max-cut instances, N in [512, 2048], R = 64, Euler.
+    Target per instance: best-known energy + 0.1%, best-known = best over two
+    12 000-step runs from other starts.  (FP32 vs BF16/FP8-J time to target
+    is part of the default bench line, over several starts.)"""
     import torch
 
     from paper_1807_00699_amd import gd
@@ -368,25 +349,6 @@ def compare_ttt(args):
 
     torch.cuda.init()
     out = {"compare": "time-to-target within 0.1% of best-known energy"}
-    # (a) precision
-    n, R, steps, check = 4096, 4096, 10000, 100
-    J = I.sparse_pm1(n, 1)
-    x0 = I.psi0_real(n, R, 1)
-    ref = []
-    for prec in (gd.GD_PREC_FP32, gd.GD_PREC_BF16):
-        with gd.Solver(J, model=gd.GD_ISING, precision=prec) as S:
-            S.set_init(R, I.psi0_real(n, R, 2))
-            S.run(steps)
-            E, b = S.energy()
-            ref.append(float(E[b]))
-    best_known = min(ref)
-    target = best_known + 1e-3 * abs(best_known)
-    res = {}
-    for name, prec in (("fp32", gd.GD_PREC_FP32), ("bf16_fp8j", gd.GD_PREC_BF16)):
-        sec, stp, eb, wall = _dense_ttt(J, x0, prec, steps, check, target)
-        res[name] = {"ttt_s": sec, "ttt_steps": stp, "final_best": eb, "run_s": wall}
-    out["ising4096"] = {"best_known": best_known, "target": target, "budget_steps": steps, **res}
-    # (b) learned start
     here = os.path.join(ROOT, "paper_1807_00699_amd")
     params = np.load(os.path.join(here, "proposal_weights.npy"))
     meta = json.load(open(os.path.join(here, "proposal_meta.json")))

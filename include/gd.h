@@ -292,6 +292,27 @@ int gd_mod_couplings(gd_solver *s, int32_t traj, float *K);
 /* gd_stats: copy the counters (out->struct_size must be set). */
 int gd_stats(gd_solver *s, gd_run_stats *out);
 
+/* gd_trajectory_status: which trajectories diverged.  out[r] = 1 when the
+ * amplitudes or gains of trajectory r became non-finite during a gd_run since
+ * gd_set_init / gd_set_state (Eq. (main) and Eq. (gamma) carry a NaN or Inf
+ * into every later step, so the state stays so), else 0; gd_stats.diverged is
+ * the count of ones.  out: caller's host array of `count` int32, count = R
+ * (batch solvers: instances x R, out[k * R + r] for trajectory r of instance
+ * k).  GD_E_STATE without a state, GD_E_INVALID_ARG on a NULL pointer or a
+ * count that differs. */
+int gd_trajectory_status(gd_solver *s, int32_t *out, int64_t count);
+
+/* gd_best_trace: the best-so-far energy (Eq. (h)) at each device check of
+ * gd_run since gd_set_init / gd_set_state.  *count = number of checks
+ * recorded (the first 65536 are kept); the first min(*count, cap) entries
+ * are written: steps[k] = steps done at check k, best[k] = lowest device-
+ * checked energy over checks 0..k (min_r E_r at each check, as for the
+ * target of time-to-target).  steps and best: caller's host arrays of cap
+ * entries (may be NULL when cap is 0, to query the count).  Dense solvers
+ * only (batches of instances report per-instance results through gd_ttt:
+ * GD_E_INVALID_ARG). */
+int gd_best_trace(gd_solver *s, int64_t *steps, double *best, int32_t cap, int32_t *count);
+
 /* gd_coupling_scale: the scale s in use (batch solvers: of instance 0). */
 int gd_coupling_scale(gd_solver *s, double *scale);
 

@@ -5,8 +5,8 @@ test-suite, the smoke check and the benchmark's CPU-baseline leg may import
 this module.  It shares no code with the HIP library; both sides receive the
 same seeded inputs from ``paper_1807_00699_amd.inputs`` as data.
 
-Thin numpy front-end over ``gd_oracle.c`` (built into ``liboracle.so`` by
-``oracle/build.py``).  Notation follows the paper:
+Thin numpy front-end over ``gd_oracle.c`` (compiled into ``liboracle.so`` by
+``build()`` below, with gcc).  Notation follows the paper:
 
 * ``run`` integrates Eq. (main) (GD form, Delta_ij = 1, K_ij = J_ij) together
   with Eq. (gamma), by explicit Euler or the 4th-order Runge-Kutta scheme of
@@ -28,7 +28,10 @@ Thin numpy front-end over ``gd_oracle.c`` (built into ``liboracle.so`` by
   Eq. (main) and Eq. (hs).
 
 Parity pins: see tests/test_oracle_pins.py (closed forms, brute force,
-fixed point Eq. (pth), symmetries).
+fixed point Eq. (pth), symmetries) and tests/test_oracle_f32_floor.py (the
+float32 run ``run_f32`` that sets the rounding floor of the GPU parity
+bounds: closed forms, a one-step rounding envelope, and a band around FP64
+runs kicked by FP32-sized perturbations).
 """
 from __future__ import annotations
 

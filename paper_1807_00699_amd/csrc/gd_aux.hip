@@ -173,12 +173,26 @@ __global__ void energy_sum_k(const double *__restrict__ partial, int ntiles, int
     E[r] = s;
 }
 
+// The same sums for few trajectories and many row tiles: one wave per
+// trajectory, lane l adds tiles l, l + 64, ... in order, then a butterfly
+// over the wave (a fixed order, so repeated checks give the same sums).
+__global__ void __launch_bounds__(64) energy_sum_wide_k(const double *__restrict__ partial, int ntiles,
+                                                        int Rp, double *__restrict__ E) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    double s = 0.0;
+    for (int t = lane; t < ntiles; t += 64) s += partial[(long long)t * Rp + r];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) E[r] = s;
+}
+
 // best = argmin_r E[r], ties -> lowest r (one workgroup); best_e = E[best]
 // (one read-back for the host's check).  With run_e: the running best of a
-// run's checks keeps (E[best], best) when E[best] < *run_e.
+// run's checks keeps (E[best], best) when E[best] < *run_e.  With trace:
+// E[best] is also written there (the check's entry of the energy trace).
 __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__restrict__ best,
                                 double *__restrict__ best_e, double *__restrict__ run_e,
-                                int *__restrict__ run_i) {
+                                int *__restrict__ run_i, double *__restrict__ trace) {
     __shared__ double sv[256];
     __shared__ int si[256];
     double bv = __builtin_inf();
@@ -205,6 +219,7 @@ __global__ void energy_argmin_k(const double *__restrict__ E, int R, int *__rest
         const int b = (si[0] == 0x7fffffff) ? 0 : si[0];
         if (best) best[0] = b;
         if (best_e) best_e[0] = E[b];
+        if (trace) trace[0] = E[b];
         if (run_e && E[b] < run_e[0]) {
             run_e[0] = E[b];
             run_i[0] = b;
@@ -562,17 +577,20 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
 }
 
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
-                                int *best, hipStream_t st, double *run_e, int *run_i) {
+                                int *best, hipStream_t st, double *run_e, int *run_i, double *trace) {
     if (R < 1) return hipErrorInvalidValue;
-    energy_sum_k<<<(R + 255) / 256, 256, 0, st>>>(partial, ntiles, Rp, R, E);
-    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i);
+    if (R <= 512 && ntiles >= 32)
+        energy_sum_wide_k<<<R, 64, 0, st>>>(partial, ntiles, Rp, E);
+    else
+        energy_sum_k<<<(R + 255) / 256, 256, 0, st>>>(partial, ntiles, Rp, R, E);
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i, trace);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_argmin(double *E, int R, int Rp, int *best, double *run_e, int *run_i,
-                                hipStream_t st) {
+                                hipStream_t st, double *trace) {
     if (R < 1 || R > Rp) return hipErrorInvalidValue;
-    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i);
+    energy_argmin_k<<<1, 256, 0, st>>>(E, R, best, E + Rp, run_e, run_i, trace);
     return hipGetLastError();
 }
 

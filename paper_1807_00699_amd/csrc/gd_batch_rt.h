@@ -20,6 +20,8 @@ int batch_spins(BatchSolver *b, void *out, int fmt);
 int batch_get_state(BatchSolver *b, float *psi, float *gamma, int64_t *step);
 int batch_set_state(BatchSolver *b, int R, const float *psi, const float *gamma, int64_t step);
 int batch_stats(BatchSolver *b, gd_run_stats *out);
+// out[k * R + r] = 1 if trajectory r of instance k became non-finite, else 0
+int batch_trajectory_status(BatchSolver *b, int32_t *out, int64_t count);
 int batch_set_targets(BatchSolver *b, const double *targets);
 int batch_ttt(BatchSolver *b, double *seconds, int64_t *steps, double *best_energy);
 int batch_count(const BatchSolver *b);

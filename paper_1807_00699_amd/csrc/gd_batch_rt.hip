@@ -775,6 +775,17 @@ int batch_set_state(BatchSolver *b, int R, const float *psi, const float *gamma,
     return GD_OK;
 }
 
+int batch_trajectory_status(BatchSolver *b, int32_t *out, int64_t count) {
+    if (b->R < 1) return gd_fail(GD_E_STATE, "no state: call gd_set_init first");
+    if (count != (int64_t)b->K * b->R)
+        return gd_fail(GD_E_INVALID_ARG, "count must be instances x trajectories");
+    static_assert(sizeof(int) == sizeof(int32_t), "flag words are 32-bit");
+    GD_TRY(hipStreamSynchronize(b->stream));
+    GD_TRY(hipMemcpy(out, b->d_flags, (size_t)count * sizeof(int), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) out[i] = out[i] != 0;
+    return GD_OK;
+}
+
 int batch_stats(BatchSolver *b, gd_run_stats *out) {
     out->batch = b->R;
     out->steps_done = b->steps_done;

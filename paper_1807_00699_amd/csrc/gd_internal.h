@@ -179,12 +179,14 @@ hipError_t launch_discretise(const float *psi, float *D, void *shadowD, int op, 
                              int Np, int Rp, int nplanes, long long plane_stride, hipStream_t st);
 // E[r] = sum_t partial[t][r] (fixed order), best = argmin (ties -> lowest r),
 // E[Rp] = E[best] (E holds Rp + 1 doubles); with run_e, the running best of a
-// run's checks (*run_e, *run_i) takes (E[best], best) when E[best] < *run_e
+// run's checks (*run_e, *run_i) takes (E[best], best) when E[best] < *run_e;
+// with trace, *trace = E[best] as well
 hipError_t launch_energy_reduce(const double *partial, int ntiles, int Rp, int R, double *E,
-                                int *best, hipStream_t st, double *run_e = nullptr, int *run_i = nullptr);
+                                int *best, hipStream_t st, double *run_e = nullptr, int *run_i = nullptr,
+                                double *trace = nullptr);
 // The argmin and running-best part of launch_energy_reduce for E[r] already formed
 hipError_t launch_energy_argmin(double *E, int R, int Rp, int *best, double *run_e, int *run_i,
-                                hipStream_t st);
+                                hipStream_t st, double *trace = nullptr);
 // FP64 re-score from the FP32 amplitudes (unit phasors / signs formed in FP64):
 // partial[t][r] = sum_{i in tile t} [-Re(conj(d_i) (J d)_i) + g_i Re(d_i)]
 // D64: scratch for the FP64 readout planes, nplanes * Rp * Np doubles

@@ -45,6 +45,7 @@ inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m
 
 constexpr int kTrajAlign = 128;  // Rp granularity: every dense variant tiles it
 constexpr int kProfileEvery = 8;  // GD_F_PROFILE samples the launches of every 8th step
+constexpr int kTraceChecks = 1 << 16;  // device checks kept in the energy trace (512 KiB)
 
 // SplitMix64 (Steele, Lea, Flood 2014) -> uniform double in [0, 1).
 inline uint64_t splitmix64(uint64_t x) {
@@ -175,6 +176,10 @@ struct gd_solver {
     double *D64 = nullptr;     // FP64 readout planes of the re-score (allocated on first use)
     double *partial = nullptr, *dE = nullptr;
     int *flags = nullptr, *dBest = nullptr, *dCount = nullptr;
+    // minimum energy of each device check since gd_set_init / gd_set_state
+    // (the first kTraceChecks checks) and the step of each
+    double *dTrace = nullptr;
+    std::vector<int64_t> trace_steps;
     int cur = 0;
     // stats
     int64_t steps_done = 0, spin_updates = 0, launches_timed = 0;
@@ -229,6 +234,8 @@ void free_state(gd_solver *s) {
     if (s->flags) (void)hipFree(s->flags);
     if (s->dBest) (void)hipFree(s->dBest);
     if (s->dCount) (void)hipFree(s->dCount);
+    if (s->dTrace) (void)hipFree(s->dTrace);
+    s->dTrace = nullptr;
     s->partial = s->dE = nullptr;
     s->flags = s->dBest = s->dCount = nullptr;
     s->have_state = false;
@@ -244,6 +251,7 @@ void reset_stats(gd_solver *s) {
     s->ttt_steps = 0;
     s->best_energy = HUGE_VAL;
     s->clock_s = 0.0;
+    s->trace_steps.clear();
 }
 
 template <class T>
@@ -290,6 +298,7 @@ int alloc_state(gd_solver *s, int R) {
     if (rc == GD_OK) rc = dalloc(&s->flags, (size_t)s->Rp);
     if (rc == GD_OK) rc = dalloc(&s->dBest, 2);   // best of the last check, running best
     if (rc == GD_OK) rc = dalloc(&s->dCount, 1);
+    if (rc == GD_OK) rc = dalloc(&s->dTrace, (size_t)kTraceChecks);
     if (rc != GD_OK) {
         free_state(s);
         return rc;
@@ -1075,8 +1084,13 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
             const float *cur = s->psi[s->cur];
             double *run_e = deferred ? s->dE + s->Rp + 1 : nullptr;
             int *run_i = deferred ? s->dBest + 1 : nullptr;
+            double *trace = nullptr;
+            if (s->trace_steps.size() < (size_t)kTraceChecks) {
+                trace = s->dTrace + s->trace_steps.size();
+                s->trace_steps.push_back(s->steps_done);
+            }
             if (small_ok) {
-                GD_HIP(launch_energy_argmin(s->dE, s->R, s->Rp, s->dBest, run_e, run_i, s->stream));
+                GD_HIP(launch_energy_argmin(s->dE, s->R, s->Rp, s->dBest, run_e, run_i, s->stream, trace));
             } else {
                 GD_HIP(launch_discretise(cur, s->D, s->shadowD, s->op, s->ro, s->prm.q, nullptr, nullptr,
                                          nullptr, s->flags, s->n, s->R, s->Np, s->Rp, s->P, s->plane(),
@@ -1086,7 +1100,7 @@ int gd_run(gd_solver *s, int32_t batch, int64_t steps) {
                 a.psi_in = s->D;
                 GD_HIP(launch_coupling(s, s->cfg, MODE_ENERGY, a));
                 GD_HIP(launch_energy_reduce(s->partial, s->Np / s->cfg.bm, s->Rp, s->R, s->dE, s->dBest,
-                                            s->stream, run_e, run_i));
+                                            s->stream, run_e, run_i, trace));
             }
             if (deferred) continue;
             if (lookahead) {
@@ -1285,9 +1299,9 @@ int gd_set_state(gd_solver *s, int32_t batch, const float *psi, const float *gam
     if (!all_finite(chk)) return fail(GD_E_NONFINITE, "gamma has non-finite entries");
     if (!s->have_state || batch != s->R) {
         if ((rc = alloc_state(s, batch)) != GD_OK) return rc;
-        reset_stats(s);
         if ((rc = choose_config(s)) != GD_OK) return rc;
     }
+    reset_stats(s);
     s->cur = 0;
     if ((rc = upload_planes(s, psi, s->psi[0], batch)) != GD_OK) return rc;
     const int savedP = s->P;
@@ -1334,6 +1348,36 @@ int gd_stats(gd_solver *s, gd_run_stats *out) {
     out->best_energy = s->best_energy;
     out->best_index = s->best_index;
     out->kernel_config = s->cfg.id;
+    return GD_OK;
+}
+
+int gd_trajectory_status(gd_solver *s, int32_t *out, int64_t count) {
+    if (!s || !out) return fail(GD_E_INVALID_ARG, "NULL argument");
+    if (s->batch) return batch_trajectory_status(s->batch, out, count);
+    if (!s->have_state) return fail(GD_E_STATE, "no state: call gd_set_init or gd_run first");
+    if (count != s->R) return fail(GD_E_INVALID_ARG, "count must equal the number of trajectories");
+    static_assert(sizeof(int) == sizeof(int32_t), "flag words are 32-bit");
+    GD_HIP(hipMemcpyAsync(out, s->flags, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t r = 0; r < count; ++r) out[r] = out[r] != 0;
+    return GD_OK;
+}
+
+int gd_best_trace(gd_solver *s, int64_t *steps, double *best, int32_t cap, int32_t *count) {
+    if (!s || !count) return fail(GD_E_INVALID_ARG, "NULL argument");
+    if (s->batch) return fail(GD_E_INVALID_ARG, "no energy trace for a batch of instances (see gd_ttt)");
+    if (cap < 0) return fail(GD_E_INVALID_ARG, "cap must be >= 0");
+    const int32_t n = (int32_t)s->trace_steps.size();
+    *count = n;
+    const int32_t m = std::min(n, cap);
+    if (m == 0) return GD_OK;
+    if (!steps || !best) return fail(GD_E_INVALID_ARG, "NULL argument");
+    GD_HIP(hipMemcpyAsync(best, s->dTrace, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    GD_HIP(hipStreamSynchronize(s->stream));
+    for (int32_t k = 0; k < m; ++k) {
+        steps[k] = s->trace_steps[(size_t)k];
+        if (k > 0 && best[k - 1] < best[k]) best[k] = best[k - 1];
+    }
     return GD_OK;
 }
 

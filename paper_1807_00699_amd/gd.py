@@ -34,7 +34,7 @@ EXPORTS = (
     "gd_coupling_scale", "gd_error_string", "gd_last_error", "gd_create_batch", "gd_set_targets",
     "gd_ttt", "gd_features", "gd_mlp_create", "gd_mlp_destroy", "gd_mlp_set_params",
     "gd_mlp_get_params", "gd_mlp_forward", "gd_mlp_train_step", "gd_propose", "gd_mod_couplings",
-    "gd_spins_noalloc",
+    "gd_spins_noalloc", "gd_trajectory_status", "gd_best_trace",
 )
 GD_NFEAT = 20
 GD_MLP_NPARAM = 5634
@@ -108,6 +108,8 @@ def load(path: str = LIB_PATH):
     lib.gd_get_state.argtypes = [vp, vp, vp, vp]
     lib.gd_set_state.argtypes = [vp, i32, vp, vp, i64]
     lib.gd_stats.argtypes = [vp, C.POINTER(gd_run_stats)]
+    lib.gd_trajectory_status.argtypes = [vp, vp, i64]
+    lib.gd_best_trace.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32)]
     lib.gd_coupling_scale.argtypes = [vp, C.POINTER(C.c_double)]
     lib.gd_create_batch.argtypes = [C.POINTER(vp), i32, vp, i32, C.POINTER(gd_params)]
     lib.gd_set_targets.argtypes = [vp, vp]
@@ -238,6 +240,25 @@ def gd_stats(h) -> gd_run_stats:
     return st
 
 
+def gd_trajectory_status(h, count):
+    """int32 [count]: 1 for each trajectory that became non-finite"""
+    out = np.empty(count, np.int32)
+    _check(load().gd_trajectory_status(h, out.ctypes.data_as(C.c_void_p), int(count)),
+           "gd_trajectory_status")
+    return out
+
+
+def gd_best_trace(h):
+    """(steps int64 [m], best-so-far energy float64 [m]) of the device checks"""
+    n = C.c_int32()
+    _check(load().gd_best_trace(h, None, None, 0, C.byref(n)), "gd_best_trace")
+    steps = np.empty(n.value, np.int64)
+    best = np.empty(n.value, np.float64)
+    _check(load().gd_best_trace(h, steps.ctypes.data_as(C.c_void_p), best.ctypes.data_as(C.c_void_p),
+                                n.value, C.byref(n)), "gd_best_trace")
+    return steps, best
+
+
 def gd_coupling_scale(h) -> float:
     v = C.c_double()
     _check(load().gd_coupling_scale(h, C.byref(v)), "gd_coupling_scale")
@@ -300,6 +321,14 @@ class Solver:
 
     def stats(self):
         return gd_stats(self.h)
+
+    def trajectory_status(self):
+        """1 for each trajectory that became non-finite, else 0"""
+        return gd_trajectory_status(self.h, gd_stats(self.h).batch)
+
+    def best_trace(self):
+        """steps and best-so-far energy of each device check since set_init"""
+        return gd_best_trace(self.h)
 
     def mod_couplings(self, traj):
         """GD-mod: K [n][n] of trajectory `traj`."""
@@ -398,6 +427,10 @@ class BatchSolver:
     def set_state(self, psi, gamma, R, step=0):
         gd_set_state(self.h, R, np.ravel(psi), np.ravel(gamma), step)
         self.R = int(R)
+
+    def trajectory_status(self):
+        """[instances][R]: 1 for each trajectory that became non-finite"""
+        return gd_trajectory_status(self.h, len(self.ns) * self.R).reshape(len(self.ns), self.R)
 
     def split(self, flat):
         """concatenated [sum_k R n_k] -> list of [R][n_k]"""
