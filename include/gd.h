@@ -80,7 +80,10 @@ typedef enum gd_integrator { GD_EULER = 0, GD_RK4 = 1 } gd_integrator;
  * the amplitude/gain update and the energies are FP32 (energies are also
  * re-scored in FP64) in every mode. */
 typedef enum gd_precision {
-    GD_PREC_FP32 = 0,  /* J and Psi in FP32 */
+    GD_PREC_FP32 = 0,  /* J and Psi in FP32 (when every coupling is exact in FP8 E4M3 the
+                          few-trajectory kernels stream a one-byte copy of J, widened exactly
+                          and summed in the FP32 order: the same results bit for bit;
+                          the environment variable GD_J8_COPY=0 turns the copy off) */
     GD_PREC_BF16 = 1,  /* Psi operand rounded to BF16; J in BF16 (FP8 storage when exact) */
     GD_PREC_FP16 = 2   /* Psi operand rounded to FP16; J in FP16 (FP8 storage when exact) */
 } gd_precision;
@@ -181,7 +184,15 @@ typedef struct gd_run_stats {
                                  pins one instead (the set-up call then fails with
                                  GD_E_INVALID_ARG if that id does not fit).  Problems of
                                  at most 128 padded spins (FP32, no pinned variant) use a
-                                 fused multi-step kernel instead of the variants */
+                                 fused multi-step kernel instead of the variants.  Batches
+                                 of instances: the same with GD_BATCH_CONFIG=<id>.  With
+                                 GD_AUTOTUNE_CACHE=<file> the picks persist across
+                                 processes: the file names the device and library build
+                                 in its first line (a file of another device or build is
+                                 ignored, and rewritten at the next pick), a set-up looks
+                                 its problem up there first (the file is read again when
+                                 it changed) and uses an id from it only when that id fits
+                                 the problem */
 } gd_run_stats;
 
 typedef struct gd_solver gd_solver;

@@ -279,8 +279,17 @@ def run_f32(J, psi, gamma=None, *, model: str, steps: int, dt: float, eps=0.1,
 
     hq = None if h is None else np.asarray(h, f32).reshape(-1, n)
 
+    Jt = np.ascontiguousarray(J.T)
+
     def F(y, gm):
-        c = (y @ J.T) * inv_s
+        # complex amplitudes: the real and imaginary planes through the real
+        # float32 product (J is real), without a complex copy of J per call
+        if cx:
+            # contiguous planes: numpy multiplies strided views without BLAS
+            yr, yi = np.ascontiguousarray(y.real), np.ascontiguousarray(y.imag)
+            c = ((yr @ Jt) + np.complex64(1j) * (yi @ Jt)) * inv_s
+        else:
+            c = (y @ Jt) * inv_s
         rho = (y.real * y.real + y.imag * y.imag) if cx else y * y
         f = y * (gm - f32(gamma_c) - rho) + c + h1
         if hq is not None:

@@ -29,7 +29,7 @@ namespace {
 
 // Coupling term d of a spin from its packed words (word 0: idx0 | idx1 << 16;
 // word 1: idx2 | sign2 << 29 | sign1 << 30 | sign0 << 31; a missing coupling
-// points at the all-zero row n_max): the neighbour's amplitude with the
+// points at the all-zero row n of its instance): the neighbour's amplitude with the
 // coupling's sign applied.  mag * (+-x) equals the ELL product (+-mag) * x
 // bit for bit, so fma(+-x, mag, c) reproduces the list's sum.
 template <int D, int T>
@@ -83,9 +83,9 @@ batch_ell_euler(BatchArgs a) {
                 il[q] = (unsigned short)a.ell_idx[spin0 * dmax + q];
             }
         } else {
-            for (int q = tid; q < T; q += NT) xl[(size_t)a.nmax * T + q] = 0.0f;
+            for (int q = tid; q < T; q += NT) xl[(size_t)n * T + q] = 0.0f;
             if constexpr (DB)
-                for (int q = tid; q < T; q += NT) xl[(size_t)(2 * a.nmax + 1) * T + q] = 0.0f;
+                for (int q = tid; q < T; q += NT) xl[(size_t)(a.nmax + 1 + n) * T + q] = 0.0f;
         }
         // DB: buffer b at xl + b (n_max + 1) T; step t reads buffer t % 2
         float *xl1 = xl + (size_t)(a.nmax + 1) * T;
@@ -177,7 +177,7 @@ batch_ell_euler(BatchArgs a) {
                     const unsigned int idx[3] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu};
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        if ((int)idx[d] == a.nmax) continue;
+                        if ((int)idx[d] == n) continue;
                         const float xj = xf[idx[d] * T + r];
                         const double sg = ((w.y << d) & 0x80000000u) ? -1.0 : 1.0;
                         h += (double)mag * sg * (xj < 0.0f ? -1.0 : 1.0);
@@ -209,6 +209,157 @@ batch_ell_euler(BatchArgs a) {
     }
 }
 
+// Per-instance trajectory width (packed form, double-buffered amplitudes):
+// instance k runs in items of T_k = 2^tlog_k trajectories, T_k chosen by the
+// host so that T_k (n_k + 1) <= E NT + 64 -- small instances get wide items,
+// large ones narrow items, every item holds about E NT spin-trajectories.
+// The amplitudes of an item sit in LDS as [i][T_k], so one wave instruction
+// of the neighbour gathers reads 64 / T_k rows of T_k consecutive words (T_k
+// >= 32: whole bank sweeps), and every thread updates E slots per barrier.
+// The item's state is staged through LDS at its start and end so that the
+// global reads and writes run along the [R][n] rows.  Thread t owns the
+// trajectory r = t mod T_k and the spins t / T_k + s NT / T_k; the products,
+// their order and the update are those of batch_ell_euler, so a trajectory's
+// result does not depend on the variant.
+template <int NT, int E, bool UNI>
+__global__ void __launch_bounds__(NT)
+batch_ell_tw(BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int tid = threadIdx.x;
+    float *xl0 = reinterpret_cast<float *>(smem);
+    double *red = reinterpret_cast<double *>(smem);                   // reuse after the run
+    const uint2 *pk = reinterpret_cast<const uint2 *>(a.ell_pack);
+
+    for (int it = a.wg_off[blockIdx.x]; it < a.wg_off[blockIdx.x + 1]; ++it) {
+        const int item = a.items[it];
+        const int k = item / a.R, r0 = item % a.R;
+        const int tlog = a.inst_tlog[k];
+        const int T = 1 << tlog;
+        const int r = tid & (T - 1);
+        const int ibase = tid >> tlog;
+        const int ISTR = NT >> tlog;
+        const int n = a.inst_n[k];
+        const long long spin0 = a.inst_spin[k];
+        const long long blk = a.inst_state[k] + (long long)r0 * n;      // rows r0 .. r0 + T - 1 of [R][n]
+        const float inv_s = a.inst_inv_s[k];
+        const float mag = a.inst_wmag[k];
+        const int rows = n + 1;                                          // + the zero row n
+        float *xl1 = xl0 + (size_t)rows * T;
+        // stage the item's amplitudes (buffer 0) and gains (buffer 1) as [i][T]
+        // from coalesced reads of the [T][n] block
+        for (int q = tid; q < T * n; q += NT) {
+            const int rr = q / n, i = q - rr * n;
+            xl0[i * T + rr] = a.x[blk + q];
+            xl1[i * T + rr] = a.gam[blk + q];
+        }
+        __syncthreads();
+        float xo[E], go[E], ep[UNI ? 1 : E], hh[UNI ? 1 : E];
+        uint2 nb[E];
+        if constexpr (UNI) {
+            ep[0] = a.eps0;
+            hh[0] = -0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int i = ibase + s * ISTR;
+            xo[s] = go[s] = 0.0f;
+            if constexpr (!UNI) ep[s] = hh[s] = 0.0f;
+            nb[s] = uint2{0u, 0u};
+            if (i < n) {
+                xo[s] = xl0[i * T + r];
+                go[s] = xl1[i * T + r];
+                if constexpr (!UNI) {
+                    ep[s] = a.eps[spin0 + i];
+                    hh[s] = a.h1[spin0 + i];
+                }
+                nb[s] = pk[spin0 + i];
+            }
+        }
+        __syncthreads();                      // gains read before buffer 1 holds amplitudes
+        for (int q = tid; q < T; q += NT) {
+            xl0[n * T + q] = 0.0f;
+            xl1[n * T + q] = 0.0f;
+        }
+        __syncthreads();
+        const float dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
+        const int rb = r * 4, sh = tlog + 2;
+        for (int step = 0; step < a.steps; ++step) {
+            const unsigned char *src = reinterpret_cast<const unsigned char *>((step & 1) ? xl1 : xl0);
+            float *dst = (step & 1) ? xl0 : xl1;
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = ibase + s * ISTR;
+                if (i < n) {
+                    const uint2 w = nb[s];
+                    float c = 0.0f;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const unsigned int idx = d == 0 ? (w.x & 0xFFFFu) : (d == 1 ? (w.x >> 16) : (w.y & 0xFFFFu));
+                        const float v = *reinterpret_cast<const float *>(src + (idx << sh) + rb);
+                        const unsigned int sgn = (w.y << d) & 0x80000000u;
+                        c = __builtin_fmaf(__uint_as_float(__float_as_uint(v) ^ sgn), mag, c);
+                    }
+                    const float x = xo[s];
+                    const float rho = x * x;
+                    const float f = x * (go[s] - gc - rho) + c * inv_s + hh[UNI ? 0 : s];
+                    xo[s] = x + dt * f;
+                    go[s] = go[s] + dt * (ep[UNI ? 0 : s] * (rho_th - rho));
+                    dst[i * T + r] = xo[s];
+                }
+            }
+            __syncthreads();
+        }
+        // final amplitudes in buffer steps % 2 (the last step's target); the
+        // other buffer stages the gains for the write-back
+        const float *xf = (a.steps & 1) ? xl1 : xl0;
+        float *gs = (a.steps & 1) ? xl0 : xl1;
+        bool bad = false;
+        double e = 0.0;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int i = ibase + s * ISTR;
+            if (i < n) {
+                gs[i * T + r] = go[s];
+                bad |= !(__builtin_isfinite(xo[s]) && __builtin_isfinite(go[s]));
+                // Eq. (h) of the discretised state: -s_i sum_d w_id s_j + g_i s_i
+                const double si = xo[s] < 0.0f ? -1.0 : 1.0;
+                const uint2 w = nb[s];
+                const unsigned int idx[3] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu};
+                double h = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if ((int)idx[d] == n) continue;
+                    const float xj = xf[idx[d] * T + r];
+                    const double sg = ((w.y << d) & 0x80000000u) ? -1.0 : 1.0;
+                    h += (double)mag * sg * (xj < 0.0f ? -1.0 : 1.0);
+                }
+                e += -si * h + (double)a.g[spin0 + i] * si;
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < T * n; q += NT) {
+            const int rr = q / n, i = q - rr * n;
+            a.x[blk + q] = xf[i * T + rr];
+            a.gam[blk + q] = gs[i * T + rr];
+        }
+        // per trajectory: lanes of one trajectory within a wave by a butterfly
+        // over the lane bits from T up, then the waves in order
+        for (int m = 32; m >= T; m >>= 1) e += __shfl_xor(e, m);
+        __syncthreads();                       // all reads of the LDS buffers are done
+        const int tw = T < 64 ? T : 64;
+        if ((tid & 63) < tw) red[(tid >> 6) * tw + (tid & 63)] = e;
+        __syncthreads();
+        if (tid < T) {
+            // T <= 64: waves w hold lanes r of the trajectory tid
+            double tot = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tot += red[w * tw + tid];
+            a.E[(long long)k * a.R + r0 + tid] = tot;
+        }
+        if (bad) a.flags[(long long)k * a.R + r0 + r] = 1;
+        __syncthreads();                       // LDS is reused by the next item
+    }
+}
+
 // Variants {T, NT, E, PK, UNI, DB}: T trajectories per item, NT threads, E
 // slots per thread (n_max <= E * NT / T), PK neighbours in registers (packed
 // form; two more registers per slot), UNI uniform eps and no field (two
@@ -232,9 +383,20 @@ batch_ell_euler(BatchArgs a) {
     X(13, 4, 1024, 8, true, false, true)     \
     X(14, 2, 512, 8, true, false, true)
 
+// Variants of batch_ell_tw {NT, E, UNI} (ids after the fixed-width ones):
+// E NT spin-trajectories per item.
+#define GD_BATCH_TW_VARIANTS(X) \
+    X(15, 1024, 8, true)        \
+    X(16, 1024, 8, false)       \
+    X(17, 1024, 4, true)        \
+    X(18, 512, 8, true)
+
 constexpr int kBatchCfg[][6] = {
 #define GD_ROW(id, t, nt, e, pk, uni, db) {t, nt, e, pk, uni, db},
     GD_BATCH_VARIANTS(GD_ROW)
+#undef GD_ROW
+#define GD_ROW(id, nt, e, uni) {0, nt, e, 1, uni, 1},
+    GD_BATCH_TW_VARIANTS(GD_ROW)
 #undef GD_ROW
 };
 
@@ -254,7 +416,16 @@ BatchConfig batch_config(int idx) {
     return c;
 }
 
+int batch_item_capacity(const BatchConfig &c) { return c.slots * c.threads; }
+
 size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax) {
+    if (c.traj == 0) {
+        // two amplitude buffers of (n_k + 1) T_k <= E NT + 64 words; the
+        // per-trajectory energy partials of the waves reuse them
+        const size_t b = (size_t)(batch_item_capacity(c) + 64) * 4 * 2;
+        const size_t red = (size_t)(c.threads / 64) * 64 * 8;
+        return b > red ? b : red;
+    }
     size_t b = (size_t)(nmax + 1) * c.traj * 4 * (c.dbuf ? 2 : 1);   // + the zero row(s) of the packed form
     if (!c.packed) b += (size_t)nmax * dmax * 4 + (size_t)nmax * dmax * 2;
     b = (b + 15) / 16 * 16;
@@ -270,7 +441,32 @@ hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax) {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     switch (c.id) { GD_BATCH_VARIANTS(GD_CASE) }
 #undef GD_CASE
+#define GD_CASE(id, nt, e, uni)                                                                              \
+    case id:                                                                                                 \
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_ell_tw<nt, e, uni>),                \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    switch (c.id) { GD_BATCH_TW_VARIANTS(GD_CASE) }
+#undef GD_CASE
     return hipErrorInvalidValue;
+}
+
+int batch_occupancy(const BatchConfig &c, int nmax, int dmax) {
+    const size_t lds = batch_lds_bytes(c, nmax, dmax);
+    int occ = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define GD_CASE(id, t, nt, e_, pk, uni, db)                                                               \
+    case id:                                                                                              \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_ell_euler<t, nt, e_, pk, uni, db>, nt, lds); \
+        break;
+    switch (c.id) { GD_BATCH_VARIANTS(GD_CASE) }
+#undef GD_CASE
+#define GD_CASE(id, nt, e_, uni)                                                                          \
+    case id:                                                                                              \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_ell_tw<nt, e_, uni>, nt, lds);       \
+        break;
+    switch (c.id) { GD_BATCH_TW_VARIANTS(GD_CASE) }
+#undef GD_CASE
+    return e == hipSuccess && occ > 0 ? occ : 1;
 }
 
 // Running best of a batch run's checks, one workgroup per instance k: the
@@ -322,6 +518,16 @@ hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipSt
         batch_ell_euler<t, nt, e, pk, uni, db><<<nwg, nt, lds, st>>>(a); \
         return hipGetLastError();
     switch (c.id) { GD_BATCH_VARIANTS(GD_CASE) }
+#undef GD_CASE
+    // per-instance widths: the host checked T_k (n_k + 1) <= E NT + 64 and
+    // T_k <= 64 for every instance when it built the schedule
+#define GD_CASE(id, nt, e, uni)                                                                              \
+    case id:                                                                                                 \
+        if (!a.ell_pack || !a.inst_wmag || !a.inst_tlog || a.dmax > 3 || a.nmax > 65535)                     \
+            return hipErrorInvalidValue;                                                                     \
+        batch_ell_tw<nt, e, uni><<<nwg, nt, lds, st>>>(a);                                                   \
+        return hipGetLastError();
+    switch (c.id) { GD_BATCH_TW_VARIANTS(GD_CASE) }
 #undef GD_CASE
     return hipErrorInvalidValue;
 }

@@ -96,6 +96,7 @@ struct BatchSolver {
     BatchConfig cfg{};
     int nwg = 0;
     int *d_wg_off = nullptr, *d_items = nullptr;
+    int *d_tlog = nullptr;            // per-instance item widths (variants with traj = 0)
     hipGraphExec_t graph = nullptr;
     int graph_steps = -1;
     // stats
@@ -125,7 +126,8 @@ void free_schedule(BatchSolver *b) {
     b->graph_steps = -1;
     if (b->d_wg_off) (void)hipFree(b->d_wg_off);
     if (b->d_items) (void)hipFree(b->d_items);
-    b->d_wg_off = b->d_items = nullptr;
+    if (b->d_tlog) (void)hipFree(b->d_tlog);
+    b->d_wg_off = b->d_items = b->d_tlog = nullptr;
     b->nwg = 0;
 }
 
@@ -153,6 +155,7 @@ BatchArgs make_args(BatchSolver *b, int steps, float dt) {
     a.ell_w = b->d_w;
     a.ell_pack = b->d_pack;
     a.inst_wmag = b->d_wmag;
+    a.inst_tlog = b->d_tlog;
     a.eps = b->d_eps;
     a.h1 = b->d_h1;
     a.g = b->d_g;
@@ -162,7 +165,7 @@ BatchArgs make_args(BatchSolver *b, int steps, float dt) {
     a.flags = b->d_flags;
     a.wg_off = b->d_wg_off;
     a.items = b->d_items;
-    a.nslices = b->R / b->cfg.traj;
+    a.nslices = b->cfg.traj ? b->R / b->cfg.traj : 0;
     a.R = b->R;
     a.dmax = b->dmax;
     a.nmax = b->nmax;
@@ -182,11 +185,26 @@ bool uniform_rates(const BatchSolver *b) {
     return true;
 }
 
+// per-instance item width of the traj = 0 variants: the widest T = 2^t <= 64
+// dividing R with T (n + 1) <= E NT + 64 and T n <= E NT (-1: none fits)
+int width_log2(const BatchConfig &c, int n, int R) {
+    const long long cap = batch_item_capacity(c);
+    for (int t = 6; t >= 0; --t) {
+        const long long T = 1LL << t;
+        if (R % T == 0 && T * (n + 1) <= cap + 64 && T * n <= cap) return t;
+    }
+    return -1;
+}
+
 bool config_fits(const BatchSolver *b, const BatchConfig &c) {
-    if (b->R % c.traj) return false;
     if (c.packed && !b->packable) return false;
     if (c.uniform && !uniform_rates(b)) return false;
-    if ((long long)b->nmax * c.traj > (long long)c.slots * c.threads) return false;
+    if (c.traj == 0) {
+        if (width_log2(c, b->nmax, b->R) < 0) return false;
+    } else {
+        if (b->R % c.traj) return false;
+        if ((long long)b->nmax * c.traj > (long long)c.slots * c.threads) return false;
+    }
     return batch_lds_bytes(c, b->nmax, b->dmax) <= 160 * 1024;
 }
 
@@ -198,27 +216,57 @@ int build_schedule(BatchSolver *b, const BatchConfig &c) {
     int dev = 0, cus = 0, occ = 0;
     GD_TRY(hipGetDevice(&dev));
     GD_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const size_t lds = batch_lds_bytes(c, b->nmax, b->dmax);
     GD_TRY(prepare_batch(c, b->nmax, b->dmax));
-    // resident workgroups per CU: limited by LDS, threads (32 waves) and 8 groups
-    occ = std::min({int((160 * 1024) / lds), 2048 / c.threads, 8});
-    occ = std::max(occ, 1);
-    const int nslices = b->R / c.traj;
-    const long long nitems = (long long)b->K * nslices;
+    // resident workgroups per CU (registers, LDS, threads), so that the bin
+    // packing below spreads the items over workgroups that run at once
+    occ = batch_occupancy(c, b->nmax, b->dmax);
+    // items: (instance, slice of T trajectories); fixed T: item = k nslices + slice,
+    // cost n_k; per-instance T_k: item = k R + first trajectory, cost T_k n_k
+    std::vector<int> order;
+    std::vector<long long> costs;
+    if (c.traj) {
+        const int nslices = b->R / c.traj;
+        for (int k = 0; k < b->K; ++k)
+            for (int sl = 0; sl < nslices; ++sl) {
+                order.push_back(k * nslices + sl);
+                costs.push_back(b->n[k]);
+            }
+    } else {
+        std::vector<int> tl(b->K);
+        for (int k = 0; k < b->K; ++k) {
+            tl[k] = width_log2(c, b->n[k], b->R);
+            if (tl[k] < 0) return gd_fail(GD_E_UNSUPPORTED, "instance too large for the batch kernel variant");
+            for (int r0 = 0; r0 < b->R; r0 += 1 << tl[k]) {
+                order.push_back(k * b->R + r0);
+                costs.push_back((long long)b->n[k] << tl[k]);
+            }
+        }
+        if (int rc = upload(&b->d_tlog, tl); rc != GD_OK) return rc;
+    }
+    const long long nitems = (long long)order.size();
     int nwg = int(std::min<long long>((long long)cus * occ, nitems));
-    std::vector<int> order(nitems);
-    std::iota(order.begin(), order.end(), 0);
-    auto cost = [&](int item) { return (long long)b->n[item / nslices]; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    // positions sorted by cost (longest first; stable, so deterministic)
+    std::vector<long long> cost_of(order.size());
+    {
+        std::vector<int> pos(order.size());
+        std::iota(pos.begin(), pos.end(), 0);
+        std::stable_sort(pos.begin(), pos.end(), [&](int x, int y) { return costs[x] > costs[y]; });
+        std::vector<int> sorted(order.size());
+        for (size_t q = 0; q < pos.size(); ++q) {
+            sorted[q] = order[pos[q]];
+            cost_of[q] = costs[pos[q]];
+        }
+        order.swap(sorted);
+    }
     typedef std::pair<long long, int> LW;   // (load, wg)
     std::priority_queue<LW, std::vector<LW>, std::greater<LW>> heap;
     for (int w = 0; w < nwg; ++w) heap.push({0, w});
     std::vector<std::vector<int>> lists(nwg);
-    for (int item : order) {
+    for (size_t q = 0; q < order.size(); ++q) {
         LW top = heap.top();
         heap.pop();
-        lists[top.second].push_back(item);
-        heap.push({top.first + cost(item), top.second});
+        lists[top.second].push_back(order[q]);
+        heap.push({top.first + cost_of[q], top.second});
     }
     std::vector<int> off(nwg + 1, 0), items;
     items.reserve(nitems);
@@ -246,10 +294,22 @@ int choose_config(BatchSolver *b) {
         return build_schedule(b, batch_config(id));
     }
     auto key = std::make_tuple(b->K, b->R, b->nmax, b->dmax, b->total, int(b->packable) + 2 * int(uniform_rates(b)));
+    const std::vector<long long> fkey{b->K, b->R, b->nmax, b->dmax, b->total,
+                                      int(b->packable) + 2 * int(uniform_rates(b))};
+    auto is_cand = [&](int id) { return std::find(cands.begin(), cands.end(), id) != cands.end(); };
+    {
+        // the cache file first (GD_AUTOTUNE_CACHE), then this process's table
+        const int fid = tune_cache_lookup("batch", fkey);
+        if (fid >= 0 && is_cand(fid)) {
+            std::lock_guard<std::mutex> lk(g_btune_mu);
+            g_btune[key] = fid;
+            return build_schedule(b, batch_config(fid));
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_btune_mu);
         auto it = g_btune.find(key);
-        if (it != g_btune.end()) return build_schedule(b, batch_config(it->second));
+        if (it != g_btune.end() && is_cand(it->second)) return build_schedule(b, batch_config(it->second));
     }
     int best = cands[0];
     if (cands.size() > 1 && b->total * (long long)b->R >= (1 << 16)) {
@@ -277,6 +337,7 @@ int choose_config(BatchSolver *b) {
         std::lock_guard<std::mutex> lk(g_btune_mu);
         g_btune[key] = best;
     }
+    tune_cache_store("batch", fkey, best);
     return build_schedule(b, batch_config(best));
 }
 
@@ -458,7 +519,8 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
     // packed neighbours: at most 3 per spin, indices below 2^16 - 1 and every
     // nonzero coupling of an instance of one magnitude (e.g. +-1 max-cut
     // couplings); each coupling becomes a neighbour index and a sign bit, a
-    // missing one the index n_max of an all-zero amplitude row
+    // missing one the index n_k of an all-zero amplitude row (one past the
+    // instance's spins)
     std::vector<unsigned int> pack;
     std::vector<float> wmag(count, 1.0f);
     b->packable = b->dmax <= 3 && b->nmax < 65535;
@@ -478,7 +540,7 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
         for (int k = 0; k < count; ++k)
             for (int i = 0; i < b->n[k]; ++i) {
                 const long long q = b->spin_off[k] + i;
-                const unsigned int zero_row = (unsigned int)b->nmax;
+                const unsigned int zero_row = (unsigned int)b->n[k];
                 unsigned int id[3] = {zero_row, zero_row, zero_row}, neg[3] = {0u, 0u, 0u};
                 for (int d = 0; d < b->dmax; ++d) {
                     const float v = w[(size_t)q * b->dmax + d];

@@ -333,17 +333,20 @@ __device__ inline u32x4 widen_fp8x8(unsigned int w0, unsigned int w1) {
 // outstanding, all its LDS operations complete (expcnt at its maximum)
 constexpr int lp_vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
 
-// PFX = LDS floor (KiB) * 16 + PF.  PF > 0: the state operands of the first
-// update groups (at most 16 wave loads per thread, a register budget) are
-// loaded during the last K chunks, one per chunk after that chunk's copies;
-// a wave then waits for its copies with vmcnt(loads issued since), since
-// vector-memory loads complete in issue order, and meets the others at a
-// plain barrier, so each load has the chunk's matrix work to land in.
+// PFX = 4096 * S3 + LDS floor (KiB) * 16 + PF.  PF > 0: the state operands
+// of the first update groups (at most 16 wave loads per thread, a register
+// budget) are loaded during the last K chunks, one per chunk after that
+// chunk's copies; a wave then waits for its copies with vmcnt(loads issued
+// since), since vector-memory loads complete in issue order, and meets the
+// others at a plain barrier, so each load has the chunk's matrix work to
+// land in.  S3 = 1: three LDS stages, the copies of chunk k + 2 issued at
+// the start of chunk k (two chunks of matrix work to land in), waited for
+// the same way.
 template <int BM, int BN, int WM, int WN, bool CPLX, int MODE, int OPT, bool JFP8, int PFX>
 __global__ void __launch_bounds__(64 * WM * WN)
 dense_step_lp_dl(DenseStepArgs a) {
     constexpr int PF = PFX & 15;
-    constexpr int LDSMIN = (PFX >> 4) * 1024;
+    constexpr int LDSMIN = ((PFX >> 4) & 255) * 1024;
     constexpr int BK = 64;
     constexpr int NT = 64 * WM * WN, NW = WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -355,13 +358,16 @@ dense_step_lp_dl(DenseStepArgs a) {
     constexpr int RB = 2 * BK;                        // bytes per B (Psi) row
     constexpr int ABYTES = BM * RA, TILEB = ABYTES + BN * RB;
     constexpr int NIA = ABYTES / 1024, NI = TILEB / 1024;   // 1 KiB copies per chunk
+    // three stages where they fit the 160 KiB of LDS (J in 16 bits doubles
+    // the A tile), else two
+    constexpr int NSTG = ((PFX >> 12) & 1) && 3 * TILEB <= 160 * 1024 ? 3 : 2;
     static_assert(NI % NW == 0 && ABYTES % 1024 == 0, "copy split");
     constexpr int NCW = NI / NW;
     // staged state update: one wave column (TRAJ / WN trajectories) per pass
     constexpr int TP = BM + 4;
     constexpr int TRP = TRAJ / WN;
     constexpr int STB = (CPLX ? 2 : 1) * TRP * TP * 4;
-    constexpr int LDSB0 = 2 * TILEB > STB ? 2 * TILEB : STB;
+    constexpr int LDSB0 = NSTG * TILEB > STB ? NSTG * TILEB : STB;
     constexpr int LDSB = LDSB0 > LDSMIN ? LDSB0 : LDSMIN;
     __shared__ __attribute__((aligned(1024))) unsigned char lds[LDSB];
 
@@ -438,12 +444,26 @@ dense_step_lp_dl(DenseStepArgs a) {
         return (long long)(r0 + p * TRP + g / RG) * Np + m0 + (g % RG) * 4;
     };
     copy_chunk(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    if constexpr (NSTG == 3) {
+        // chunk 0 has landed; chunk 1 may still be in flight
+        if (nk > 1) {
+            copy_chunk(BK, 1);
+            __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(NCW));
+        } else {
+            __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(0));
+        }
+        __asm__ __volatile__("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        __asm__ __volatile__("" ::: "memory");
+    } else {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     auto chunk = [&](int kc, auto pslot) {
         constexpr int PS = decltype(pslot)::value;
-        const int buf = kc & 1;
-        if (kc + 1 < nk) copy_chunk((kc + 1) * BK, buf ^ 1);
+        const int buf = NSTG == 3 ? kc % 3 : kc & 1;
+        const bool ahead = kc + NSTG - 1 < nk;     // copies of chunk kc + NSTG - 1 issued here
+        if (ahead) copy_chunk((kc + NSTG - 1) * BK, NSTG == 3 ? (kc + 2) % 3 : buf ^ 1);
         constexpr int NL = PS < 0 ? 0 : 1;
         if constexpr (NL > 0) {
             __builtin_amdgcn_sched_barrier(0);
@@ -495,11 +515,14 @@ dense_step_lp_dl(DenseStepArgs a) {
                         acc[mb][nb] = mfma32<OPT>(av[set][mb][s], bv[set][nb][s], acc[mb][nb]);
         }
         // this wave's copies of the next chunk have landed (an operand load
-        // issued after them may still be in flight); then a plain workgroup
-        // barrier with compiler-only fences (a release fence would also wait
-        // for the operand load)
-        __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(NL));
-        if constexpr (PF > 0) {
+        // and, with three stages, the copies of the chunk after it, issued
+        // later, may still be in flight); then a plain workgroup barrier with
+        // compiler-only fences (a release fence would wait for those too)
+        if (NSTG == 3 && ahead)
+            __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(NCW + NL));
+        else
+            __builtin_amdgcn_s_waitcnt(lp_vmcnt_imm(NL));
+        if constexpr (PF > 0 || NSTG == 3) {
             __asm__ __volatile__("" ::: "memory");
             __builtin_amdgcn_s_barrier();
             __asm__ __volatile__("" ::: "memory");
@@ -650,9 +673,9 @@ hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &
 }
 
 // Variants {BM, BN (GEMM columns), BK, WM, WN, DL (0: register-staged; else
-// direct-to-LDS copies with J kept FP8 in LDS, DL - 1 = LDS floor in KiB * 16
-// + state-operand loads per tail chunk)}.  Ids 0-6 are instantiated in
-// gd_dense_lp.hip, the larger workgroup tiles 7-10 in gd_dense_lp_big.hip
+// direct-to-LDS copies with J kept FP8 in LDS, DL - 1 = 4096 for three LDS
+// stages + LDS floor in KiB * 16 + state-operand loads per tail chunk)}.  Ids 0-6 are instantiated in
+// gd_dense_lp.hip, the larger workgroup tiles 7-13 in gd_dense_lp_big.hip
 // (two translation units that compile in parallel).  256 x 256 tiles (eight
 // waves of 128 x 64) halve the LDS bytes written per flop against 128 x 128
 // and put one workgroup on each CU at N = 4096.
@@ -668,7 +691,10 @@ hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &
     X(7, 256, 256, 64, 2, 4, 1)     \
     X(8, 256, 128, 64, 2, 2, 1)     \
     X(9, 128, 256, 64, 2, 4, 1)     \
-    X(10, 256, 128, 64, 4, 2, 1)
+    X(10, 256, 128, 64, 4, 2, 1)    \
+    X(11, 256, 256, 64, 2, 4, 4097) \
+    X(12, 256, 256, 64, 2, 4, 4099) \
+    X(13, 256, 128, 64, 2, 2, 4097)
 
 }  // namespace
 

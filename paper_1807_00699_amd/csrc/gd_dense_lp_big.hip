@@ -1,5 +1,5 @@
 // Reduced-precision coupling step, the larger workgroup tiles (variants
-// 7-10 of gd_dense_lp.h), in a translation unit of their own.
+// 7-13 of gd_dense_lp.h), in a translation unit of their own.
 #include "gd_dense_lp.h"
 
 namespace gd {

@@ -33,11 +33,21 @@ namespace gemv {
 
 // storage of J: FP32, FP8 E4M3 (exact for couplings such as {-1, 0, +1}),
 // or the 16-bit operand type
-enum JKind : int { J_F32 = 0, J_FP8 = 1, J_B16 = 2 };
+// J_FP8N: FP8 couplings read four per lane at the positions of J_F32's
+// 16-byte loads, so every lane multiplies and sums the couplings J_F32 gives
+// it, in the same order: results equal those of FP32 couplings bit for bit
+// when every coupling is exact in FP8 (FP32 solvers), with a quarter of the bytes
+enum JKind : int { J_F32 = 0, J_FP8 = 1, J_B16 = 2, J_FP8N = 3 };
 
 template <int JK>
 constexpr int j_bytes() {
-    return JK == J_F32 ? 4 : (JK == J_FP8 ? 1 : 2);
+    return JK == J_F32 ? 4 : (JK == J_FP8 || JK == J_FP8N ? 1 : 2);
+}
+
+// couplings per lane per load (J_FP8N: the four of J_F32)
+template <int JK>
+constexpr int j_epl() {
+    return JK == J_FP8 ? 16 : (JK == J_B16 ? 8 : 4);
 }
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -49,7 +59,7 @@ __device__ inline f32x4 widen_quad(const u32x4 &w, int j) {
     if constexpr (JK == J_F32) {
         (void)j;   // one quad per 16-byte word
         return f32x4{__uint_as_float(w[0]), __uint_as_float(w[1]), __uint_as_float(w[2]), __uint_as_float(w[3])};
-    } else if constexpr (JK == J_FP8) {
+    } else if constexpr (JK == J_FP8 || JK == J_FP8N) {
         const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(int(w[j]), false);
         const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(int(w[j]), true);
         return f32x4{lo[0], lo[1], hi[0], hi[1]};
@@ -129,7 +139,7 @@ constexpr int ilog2() {
 // `budget` floats holds for CM columns, a multiple of the wave-wide block
 template <int JK, int CM>
 constexpr int chunk_width(int budget) {
-    constexpr int BW = 64 * (16 / j_bytes<JK>());
+    constexpr int BW = 64 * j_epl<JK>();
     const int w = budget / CM / BW * BW;
     return w < BW ? BW : w;
 }
@@ -137,7 +147,7 @@ constexpr int chunk_width(int budget) {
 template <int MODE, bool CPLX, int JK, int OPT, int CM, int W, int RPW, int KCM, int U, int KS>
 __global__ void __launch_bounds__(64 * W) gemv_step_k(DenseStepArgs a) {
     constexpr int JB = j_bytes<JK>();
-    constexpr int EPL = 16 / JB;   // couplings per lane per load
+    constexpr int EPL = j_epl<JK>();   // couplings per lane per load
     constexpr int QPL = EPL / 4;   // operand slots (4 floats) per lane per load
     constexpr int BW = 64 * EPL;   // columns of one wave-wide load
     constexpr int SB = BW / 4;     // slots per block
@@ -182,9 +192,14 @@ __global__ void __launch_bounds__(64 * W) gemv_step_k(DenseStepArgs a) {
             const int k = k0 + ((b0 + u) * KS + kp) * BW + EPL * lane;
             const bool ok = (b0 + u < nb) && k < Np;
 #pragma unroll
-            for (int q = 0; q < RPW; ++q)
-                jw[u][q] = ok ? *reinterpret_cast<const u32x4 *>(Jb + ((long long)(i0 + q) * Np + k) * JB)
-                              : u32x4{0u, 0u, 0u, 0u};
+            for (int q = 0; q < RPW; ++q) {
+                if constexpr (JK == J_FP8N)
+                    jw[u][q] = u32x4{ok ? *reinterpret_cast<const unsigned int *>(Jb + (long long)(i0 + q) * Np + k)
+                                        : 0u, 0u, 0u, 0u};
+                else
+                    jw[u][q] = ok ? *reinterpret_cast<const u32x4 *>(Jb + ((long long)(i0 + q) * Np + k) * JB)
+                                  : u32x4{0u, 0u, 0u, 0u};
+            }
         }
     };
     auto fma_batch = [&](const u32x4 (&jw)[U][RPW], int b0, int nb) {
@@ -373,7 +388,7 @@ hipError_t launch_one(const DenseStepArgs &a, hipStream_t st) {
     constexpr int KCM = chunk_width<JK, CM>(BUD);
     // 16-bit and FP8 couplings widen to 2x / 4x the registers per load: with
     // 8 or more columns one batch in flight keeps the kernel out of scratch
-    constexpr int UE = (JK != J_F32 && CM >= 8) ? 1 : U;
+    constexpr int UE = (JK != J_F32 && JK != J_FP8N && CM >= 8) ? 1 : U;
     if constexpr (!fits_registers(JK, CM, W)) {
         return hipErrorInvalidValue;
     } else {

@@ -1,6 +1,7 @@
 // Internal interfaces between the host runtime and the gfx950 kernels of
 // libgd.so.  Not part of the public ABI (include/gd.h).
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
@@ -119,15 +120,16 @@ struct BatchArgs {
     // packed form (dmax <= 3, one coupling magnitude per instance, n_max < 2^16 - 1):
     // [sum n][2] words, word 0 = idx0 | idx1 << 16, word 1 = idx2 | neg2 << 29 |
     // neg1 << 30 | neg0 << 31 (neg: coupling -mag, else +mag); a missing
-    // coupling has index n_max, an amplitude row that holds zeros
+    // coupling has index n_k (the instance's size), an amplitude row that holds zeros
     const unsigned int *ell_pack;
     const float *inst_wmag;       // [K] the magnitude of instance k's couplings
+    const int *inst_tlog;         // [K] per-instance-width variants: log2 of instance k's item width
     const float *eps, *h1, *g;    // [sum n]
     float *x, *gam;               // state [sum_k R n_k]
     double *E;                    // [K][R] energies after the launch
     int *flags;                   // [K][R] non-finite flags
     const int *wg_off;            // [nwg + 1] item ranges per workgroup
-    const int *items;             // item = k * nslices + slice
+    const int *items;             // item = k * nslices + slice (per-instance widths: k * R + first trajectory)
     int nslices, R, dmax, nmax, steps;
     float dt, gamma_c, rho_th;
     float eps0;                   // the rate of every spin, for variants that need uniform eps and no field
@@ -135,7 +137,7 @@ struct BatchArgs {
 
 struct BatchConfig {
     int id;
-    int traj;     // trajectories per work item
+    int traj;     // trajectories per work item (0: chosen per instance, at most 64)
     int threads;  // workgroup size
     int slots;    // spins per thread (n_max <= slots * threads / traj)
     bool packed;  // neighbours in registers from the packed form (LDS: amplitudes only)
@@ -146,6 +148,15 @@ struct BatchConfig {
 int batch_config_count();
 BatchConfig batch_config(int idx);
 size_t batch_lds_bytes(const BatchConfig &c, int nmax, int dmax);
+int batch_item_capacity(const BatchConfig &c);   // spin-trajectories of one item (slots x threads)
+// resident workgroups per CU of a variant (registers, LDS and threads)
+int batch_occupancy(const BatchConfig &c, int nmax, int dmax);
+
+// ---- persistent tuner cache (gd_tune_cache.hip; GD_AUTOTUNE_CACHE=<file>)
+// the variant id stored for (kind, key) by this or an earlier process on the
+// same device and library build, or -1
+int tune_cache_lookup(const char *kind, const std::vector<long long> &key);
+void tune_cache_store(const char *kind, const std::vector<long long> &key, int id);
 hipError_t prepare_batch(const BatchConfig &c, int nmax, int dmax);   // once per variant, outside capture
 hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipStream_t st);
 // Per instance k < K: (best_E[k], best_r[k]) takes the lowest E[k * R + r]

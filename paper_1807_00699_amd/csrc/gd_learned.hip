@@ -15,13 +15,15 @@
 //  mlp_*       20 -> 64 -> 64 -> 2 ReLU network: FP32 forward, per-instance
 //              flip-invariant loss, backward, weight-gradient partials over
 //              spin chunks, fixed-order reduction fused with Adam; FP16
-//              inference (packed half arithmetic).
+//              inference on the matrix cores (FP32 accumulation).
 //  propose_k   writes psi0 = a (alpha m_i + (1 - alpha) xi) and eps_i into a
 //              batched solver's state, xi from SplitMix64.
 #include "gd_internal.h"
 #include "gd_learned.h"
 
 #include <hip/hip_fp16.h>
+
+#include <algorithm>
 
 namespace gd {
 
@@ -342,55 +344,124 @@ __global__ void __launch_bounds__(MT) mlp_forward_k(const float *__restrict__ p,
     out[(long long)m * NO + 1] = o[1];
 }
 
-__device__ inline __half2 relu2(__half2 v) {
-    const __half z = __float2half(0.0f);
-    return __halves2half2(__hmax(__low2half(v), z), __hmax(__high2half(v), z));
-}
+// FP16 inference on the matrix cores (v_mfma_f32_32x32x16_f16, FP32
+// accumulation).  Each wave takes 32 spins at a time and computes the
+// transposed layers, Z1^T = W1^T X^T (features padded from 20 to 32) and
+// Z2^T = W2^T relu(Z1)^T, so that a lane holds one spin's column: lane l
+// (half h = l / 32) owns the accumulator rows 8q + 4h + e (q, e < 4) of each
+// 32-row block for spin l mod 32.  Those 16 values, rectified and rounded to
+// FP16, are already the second layer's B operand for two 16-deep K steps if
+// the K order of W2^T is permuted to match: step s, slot j of half h reads
+// hidden unit 8 (2 s + j / 4) + 4 h + j mod 4 of the block (every product is
+// still summed once).  The two outputs take the 32 hidden units of each lane
+// on the vector ALUs and add the other lane half.  The weight operands are
+// built once per workgroup in LDS in the lane order of the instruction.
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int MFT = 256;   // 4 waves
 
-// FP16 inference: parameters and activations in half precision (packed pairs)
-__global__ void __launch_bounds__(MT) mlp_forward_f16_k(const float *__restrict__ p, const float *__restrict__ X,
-                                                       float *__restrict__ out, int M) {
-    __shared__ __half2 w1[F][H / 2], w2[H][H / 2], w3[H];
-    __shared__ __half2 b1[H / 2], b2[H / 2];
-    __shared__ float b3[NO];
-    for (int q = threadIdx.x; q < F * H / 2; q += MT) {
-        const int f = q / (H / 2), j = q % (H / 2);
-        w1[f][j] = __floats2half2_rn(p[OFF_W1 + f * H + 2 * j], p[OFF_W1 + f * H + 2 * j + 1]);
+__global__ void __launch_bounds__(MFT) mlp_forward_mfma_k(const float *__restrict__ p, const float *__restrict__ X,
+                                                         float *__restrict__ out, int M) {
+    static_assert(H == 64 && F <= 32 && NO == 2, "layer shapes of the MFMA forward");
+    // A1[rb][s][lane]: W1^T rows 32 rb + l % 32, features 16 s + 8 h + j
+    // A2[rb][ib][s][lane]: W2^T rows 32 rb + l % 32, hidden 32 ib + 8 (2 s + j / 4) + 4 h + j % 4
+    __shared__ f16x8_t A1[2][2][64], A2[2][2][2][64];
+    __shared__ float B1s[2][2][16], B2s[2][2][16], W3s[2][2][16][2];   // [rb][h][4q + e](...)
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 2 * 2 * 64; q += MFT) {
+        const int rb = q / 128, st = (q / 64) % 2, l = q % 64, h = l / 32, row = 32 * rb + l % 32;
+        f16x8_t v;
+        for (int j = 0; j < 8; ++j) {
+            const int f = 16 * st + 8 * h + j;
+            v[j] = (_Float16)(f < F ? p[OFF_W1 + f * H + row] : 0.0f);
+        }
+        A1[rb][st][l] = v;
     }
-    for (int q = threadIdx.x; q < H * H / 2; q += MT) {
-        const int a0 = q / (H / 2), j = q % (H / 2);
-        w2[a0][j] = __floats2half2_rn(p[OFF_W2 + a0 * H + 2 * j], p[OFF_W2 + a0 * H + 2 * j + 1]);
+    for (int q = tid; q < 2 * 2 * 2 * 64; q += MFT) {
+        const int rb = q / 256, ib = (q / 128) % 2, st = (q / 64) % 2, l = q % 64, h = l / 32;
+        const int row = 32 * rb + l % 32;
+        f16x8_t v;
+        for (int j = 0; j < 8; ++j) {
+            const int hin = 32 * ib + 8 * (2 * st + j / 4) + 4 * h + j % 4;
+            v[j] = (_Float16)p[OFF_W2 + hin * H + row];
+        }
+        A2[rb][ib][st][l] = v;
     }
-    for (int q = threadIdx.x; q < H; q += MT) w3[q] = __floats2half2_rn(p[OFF_W3 + q * NO], p[OFF_W3 + q * NO + 1]);
-    for (int q = threadIdx.x; q < H / 2; q += MT) {
-        b1[q] = __floats2half2_rn(p[OFF_B1 + 2 * q], p[OFF_B1 + 2 * q + 1]);
-        b2[q] = __floats2half2_rn(p[OFF_B2 + 2 * q], p[OFF_B2 + 2 * q + 1]);
+    for (int q = tid; q < 2 * 2 * 16; q += MFT) {
+        const int rb = q / 32, h = (q / 16) % 2, k = q % 16;
+        const int row = 32 * rb + 8 * (k / 4) + 4 * h + k % 4;
+        B1s[rb][h][k] = p[OFF_B1 + row];
+        B2s[rb][h][k] = p[OFF_B2 + row];
+        W3s[rb][h][k][0] = p[OFF_W3 + row * NO];
+        W3s[rb][h][k][1] = p[OFF_W3 + row * NO + 1];
     }
-    if (threadIdx.x < NO) b3[threadIdx.x] = p[OFF_B3 + threadIdx.x];
     __syncthreads();
-    const int m = blockIdx.x * MT + threadIdx.x;
-    if (m >= M) return;
-    __half2 h1[H / 2], h2[H / 2];
-    for (int j = 0; j < H / 2; ++j) h1[j] = b1[j];
-    for (int f = 0; f < F; ++f) {
-        const __half2 xf = __float2half2_rn(X[(long long)m * F + f]);
-        for (int j = 0; j < H / 2; ++j) h1[j] = __hfma2(xf, w1[f][j], h1[j]);
+    const int lane = tid & 63, h = lane >> 5, l32 = lane & 31;
+    const float b30 = p[OFF_B3], b31 = p[OFF_B3 + 1];
+    const int ntiles = (M + 31) / 32;
+    for (int t = blockIdx.x * (MFT / 64) + (tid >> 6); t < ntiles; t += gridDim.x * (MFT / 64)) {
+        const long long m = (long long)t * 32 + l32;
+        const bool ok = m < M;
+        // B1: features 16 s + 8 h + j of spin m (rows of F = 20 floats are
+        // 16-byte aligned: four-float loads, zeros past feature 19)
+        static_assert(F == 20, "feature row of five 16-byte words");
+        f16x8_t xb[2];
+        {
+            const float4 *xr = reinterpret_cast<const float4 *>(X + (ok ? m : 0) * F);
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 a0 = ok ? xr[2 * h] : z4, a1 = ok ? xr[2 * h + 1] : z4;
+            const float4 c0 = ok && h == 0 ? xr[4] : z4;
+            const float v0[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const float v1[4] = {c0.x, c0.y, c0.z, c0.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                xb[0][j] = (_Float16)v0[j];
+                xb[1][j] = (_Float16)(j < 4 ? v1[j] : 0.0f);
+            }
+        }
+        f32x16_t z1[2], z2[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z1[rb][k] = B1s[rb][h][k];
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+                z1[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1[rb][st][lane], xb[st], z1[rb], 0, 0, 0);
+        }
+        // relu(Z1)^T as the B operand of layer 2, in the permuted K order
+        f16x8_t hb[2][2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) hb[ib][st][j] = (_Float16)fmaxf(z1[ib][8 * st + j], 0.0f);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z2[rb][k] = B2s[rb][h][k];
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int st = 0; st < 2; ++st)
+                    z2[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[rb][ib][st][lane], hb[ib][st], z2[rb], 0, 0, 0);
+        }
+        float o0 = 0.0f, o1 = 0.0f;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float r = fmaxf(z2[rb][k], 0.0f);
+                o0 = fmaf(r, W3s[rb][h][k][0], o0);
+                o1 = fmaf(r, W3s[rb][h][k][1], o1);
+            }
+        o0 += __shfl_xor(o0, 32);
+        o1 += __shfl_xor(o1, 32);
+        if (h == 0 && ok) {
+            out[m * NO] = o0 + b30;
+            out[m * NO + 1] = o1 + b31;
+        }
     }
-    for (int j = 0; j < H / 2; ++j) h1[j] = relu2(h1[j]);
-    for (int j = 0; j < H / 2; ++j) h2[j] = b2[j];
-    for (int a0 = 0; a0 < H; ++a0) {
-        const __half ha = (a0 & 1) ? __high2half(h1[a0 / 2]) : __low2half(h1[a0 / 2]);
-        const __half2 hh = __half2half2(ha);
-        for (int j = 0; j < H / 2; ++j) h2[j] = __hfma2(hh, w2[a0][j], h2[j]);
-    }
-    __half2 acc = __float2half2_rn(0.0f);
-    for (int j = 0; j < H / 2; ++j) {
-        const __half2 r = relu2(h2[j]);
-        acc = __hfma2(__half2half2(__low2half(r)), w3[2 * j], acc);
-        acc = __hfma2(__half2half2(__high2half(r)), w3[2 * j + 1], acc);
-    }
-    out[(long long)m * NO] = __low2float(acc) + b3[0];
-    out[(long long)m * NO + 1] = __high2float(acc) + b3[1];
 }
 
 // per instance: sigma_k (flip alignment) and loss sums
@@ -609,8 +680,15 @@ hipError_t launch_mlp_forward(const float *params, const float *X, float *out, i
                               hipStream_t st) {
     if (M <= 0) return hipSuccess;
     const int g = (M + MT - 1) / MT;
-    if (fp16) mlp_forward_f16_k<<<g, MT, 0, st>>>(params, X, out, M);
-    else mlp_forward_k<<<g, MT, 0, st>>>(params, X, out, M);
+    if (fp16) {
+        // one wave per 32 spins at a time; at most the workgroups that are
+        // resident at once (two per CU), so each builds the weight operands once
+        const int tiles = (M + 31) / 32;
+        const int gm = std::min((tiles + MFT / 64 - 1) / (MFT / 64), 512);
+        mlp_forward_mfma_k<<<gm, MFT, 0, st>>>(params, X, out, M);
+    } else {
+        mlp_forward_k<<<g, MT, 0, st>>>(params, X, out, M);
+    }
     return hipGetLastError();
 }
 

@@ -131,8 +131,9 @@ int scratch_address(int dev, void **out) {
 }
 
 std::mutex g_tune_mu;
-// (complex + 2 precision + 8 FP8-stored J, Np, Rp, integrator, R if the
-// matrix-vector kernels compete else 0) -> kernel variant id
+// (complex + 2 precision + 8 FP8-stored J + 32 FP8 copy of FP32 J, Np, Rp,
+// integrator, R if the matrix-vector kernels compete else 0) -> kernel variant
+// id; with GD_AUTOTUNE_CACHE also kept in that file across processes
 std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;
 
 }  // namespace
@@ -163,6 +164,11 @@ struct gd_solver {
     int op = OP_F32;           // operand precision of the coupling GEMM
     bool jfp8 = false;         // J stored as FP8 E4M3 (reduced-precision modes)
     void *dJlp = nullptr;      // J in FP8 or in the operand type
+    // FP32 solvers whose couplings are all exact in FP8 E4M3 (e.g. {-1, 0, +1}):
+    // a one-byte copy of J for the few-trajectory kernels, which stream J from
+    // HBM every step and widen it exactly to FP32, in the FP32 kernels' order
+    // (the same results bit for bit); GD_J8_COPY=0 keeps FP32 J only
+    void *dJ8 = nullptr;
     void *shadow[3] = {nullptr, nullptr, nullptr};   // operand copies of psi[k]
     void *shadowD = nullptr;   // operand copy of the discretised state
     // state
@@ -352,7 +358,10 @@ DenseStepArgs base_args(gd_solver *s) {
 hipError_t launch_coupling(gd_solver *s, const DenseConfig &cfg, int mode, const DenseStepArgs &a) {
     DenseStepArgs b = a;
     if (s->op != OP_F32) b.J = s->dJlp;
-    if (cfg.id >= kGemvBase) return launch_gemv_step(cfg, s->complex_mode(), mode, s->op, s->jfp8, b, s->stream);
+    if (cfg.id >= kGemvBase) {
+        if (s->op == OP_F32 && s->dJ8) b.J = s->dJ8;
+        return launch_gemv_step(cfg, s->complex_mode(), mode, s->op, s->jfp8 || s->dJ8 != nullptr, b, s->stream);
+    }
     if (s->op == OP_F32) return launch_dense_step(cfg, s->complex_mode(), mode, OP_F32, b, s->stream);
     return launch_dense_step_lp(cfg, s->complex_mode(), mode, s->op, s->jfp8, b, s->stream);
 }
@@ -460,7 +469,9 @@ int choose_config(gd_solver *s) {
     const bool cx = s->complex_mode();
     const bool lp = s->op != OP_F32;
     const int nc = lp ? dense_lp_config_count() : dense_config_count(cx);
-    auto gemv_ok = [&](int k) { return !s->mod() && gemv_fits(k, s->Np, s->R, cx, s->op, s->jfp8); };
+    auto gemv_ok = [&](int k) {
+        return !s->mod() && gemv_fits(k, s->Np, s->R, cx, s->op, s->jfp8 || s->dJ8 != nullptr);
+    };
     const bool gv = gemv_ok(0);
     const int ng = gv ? gemv_config_count() : 0;
     auto cfg_of = [&](int id) {
@@ -483,12 +494,24 @@ int choose_config(gd_solver *s) {
         if (fits(id)) ids.push_back(id);
     for (int k = 0; k < ng; ++k)
         if (gemv_ok(k)) ids.push_back(kGemvBase + k);
-    auto key = std::make_tuple(int(cx) + 2 * s->op + 8 * int(s->jfp8), s->Np, s->Rp, s->integrator(),
-                               gv ? s->R : 0);
+    auto key = std::make_tuple(int(cx) + 2 * s->op + 8 * int(s->jfp8) + 32 * int(s->dJ8 != nullptr), s->Np,
+                               s->Rp, s->integrator(), gv ? s->R : 0);
+    const std::vector<long long> fkey{std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key),
+                                      std::get<4>(key)};
+    {
+        // the cache file first (GD_AUTOTUNE_CACHE), then this process's table
+        const int fid = tune_cache_lookup("dense", fkey);
+        if (fid >= 0 && fits(fid)) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = fid;
+            s->cfg = cfg_of(fid);
+            return GD_OK;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
+        if (it != g_tune_cache.end() && fits(it->second)) {
             s->cfg = cfg_of(it->second);
             return GD_OK;
         }
@@ -541,6 +564,7 @@ int choose_config(gd_solver *s) {
     s->cfg = cfg_of(best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
+    tune_cache_store("dense", fkey, best);
     return GD_OK;
 }
 
@@ -833,6 +857,20 @@ int gd_create(gd_solver **out, int32_t n, const float *J, const float *g, int32_
                                                    "operand precision (nor in FP8)"));
         }
     }
+    const char *j8env = std::getenv("GD_J8_COPY");
+    if (prm.precision == GD_PREC_FP32 && prm.variant != GD_VARIANT_MOD && !(j8env && std::atoi(j8env) == 0)) {
+        bool fp8 = true;
+        j8.assign((size_t)Np * Np, 0);
+        for (int i = 0; i < n && fp8; ++i)
+            for (int j = 0; j < n && fp8; ++j)
+                if (i != j) fp8 = e4m3_encode_exact(hj[(size_t)i * n + j], &j8[(size_t)i * Np + j]);
+        if (fp8) {
+            if ((rc = dalloc(reinterpret_cast<uint8_t **>(&s->dJ8), j8.size())) != GD_OK) return bail(rc);
+            if (hipMemcpy(s->dJ8, j8.data(), j8.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(GD_E_DEVICE, "upload of FP8 J failed"));
+        }
+        j8.clear();
+    }
     if ((rc = dalloc(&s->dJ, (size_t)Np * Np)) != GD_OK) return bail(rc);
     if (s->jfp8) {
         if ((rc = dalloc(reinterpret_cast<uint8_t **>(&s->dJlp), j8.size())) != GD_OK) return bail(rc);
@@ -869,6 +907,7 @@ void gd_destroy(gd_solver *s) {
     if (s->dH1) (void)hipFree(s->dH1);
     if (s->dG) (void)hipFree(s->dG);
     if (s->dJlp) (void)hipFree(s->dJlp);
+    if (s->dJ8) (void)hipFree(s->dJ8);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (hipEvent_t e : {s->ev_chk[0], s->ev_chk[1], s->ev_run0, s->ev_end})
         if (e) (void)hipEventDestroy(e);

@@ -68,8 +68,7 @@ def test_batch_parity_against_oracle_per_instance():
         prev = 0
         ox = [x.astype(np.float64) for x in x0]
         og = [np.zeros_like(x, np.float64) for x in x0]
-        fx = [x.copy() for x in x0]
-        fg = [np.zeros_like(x) for x in x0]
+        fl = [P.Floor(J, x0[k], None, model="ising", dt=0.05, eps=0.1) for k, J in enumerate(dense)]
         for st in (1, 10, 50, 100, 200):
             B.run(st - prev)
             xs, gs, step = B.state()
@@ -77,10 +76,10 @@ def test_batch_parity_against_oracle_per_instance():
             strict = []
             for k, J in enumerate(dense):
                 ox[k], og[k] = O.run(J, ox[k], og[k], model="ising", steps=st - prev, dt=0.05, eps=0.1)
-                fx[k], fg[k] = O.run_f32(J, fx[k], fg[k], model="ising", steps=st - prev, dt=0.05, eps=0.1)
+                fl[k].advance(st - prev)
                 ep = _rel(B.split(xs)[k], ox[k])
                 eg = _rel(B.split(gs)[k], og[k])
-                floor = np.maximum(_rel(fx[k], ox[k]), _rel(fg[k], og[k]))
+                floor = fl[k].floor(ox[k], og[k])
                 P.check(ep, eg, floor, min_strict=0.0, label=f"instance {k} n={sizes[k]} step {st}")
                 strict.append((ep <= TOL) & (eg <= TOL))
             assert np.mean(np.concatenate(strict)) >= 0.9, st
@@ -102,19 +101,25 @@ def test_batch_independence_variants_and_graph_chunks_bitwise():
     x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 20)])
     ref = None
     # 0-6: couplings in LDS; 7-14: neighbours in registers (packed form),
-    # 11-12 uniform rates, 12-14 double-buffered amplitudes
-    for cfg in ("0", "1", "2", "6", "7", "8", "9", "10", "11", "12", "13", "14"):
+    # 11-12 uniform rates, 12-14 double-buffered amplitudes; 15-18: item width
+    # chosen per instance (all 16 trajectories in one item at 8192
+    # spin-trajectories per item, 15-16; the 258-spin instance in items of 8
+    # at 4096, 17-18), the state staged through LDS; the energies of the
+    # final state (a zero-step launch of the same variant) too
+    for cfg in ("0", "1", "2", "6", "7", "8", "9", "10", "11", "12", "13", "14", "15", "16", "17", "18"):
         os.environ["GD_BATCH_CONFIG"] = cfg
         try:
             with gd.BatchSolver(insts, check_interval=25) as B:
                 B.set_init(R, x0)
                 B.run(200)
-                out = B.state()
+                out = B.state() + B.energy()
+                assert B.stats().kernel_config == int(cfg)
         finally:
             del os.environ["GD_BATCH_CONFIG"]
         if ref is None:
             ref = out
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), cfg
+        assert np.array_equal(out[3], ref[3]) and np.array_equal(out[4], ref[4]), cfg
     # one graph of 200 steps vs 8 replays of a 25-step graph (autotuned variant)
     with gd.BatchSolver(insts) as B:
         B.set_init(R, x0)
@@ -185,10 +190,11 @@ def test_batch256_full_size_sampled():
     for k in (int(np.argmin(sizes)), int(np.argmax(sizes)), 100):
         J = I.edges_to_dense(int(sizes[k]), *dense[k])
         sub = [0, 1, 31, 63]
-        xo, _ = O.run(J, x0[k][sub], model="ising", steps=200, dt=0.05, eps=0.1)
-        xf, _ = O.run_f32(J, x0[k][sub], model="ising", steps=200, dt=0.05, eps=0.1)
+        xo, go = O.run(J, x0[k][sub], model="ising", steps=200, dt=0.05, eps=0.1)
+        fl = P.Floor(J, x0[k][sub], None, model="ising", dt=0.05, eps=0.1)
+        fl.advance(200)
         ep = _rel(xk[k][sub], xo)
-        assert np.all(ep <= np.maximum(TOL, 4 * _rel(xf, xo))), (k, ep)
+        assert np.all(ep <= np.maximum(TOL, 4 * fl.floor(xo, go))), (k, ep)
         Eo = O.energy_ising(J, sp[k])
         assert np.array_equal(E[k], Eo.astype(np.float64))
 

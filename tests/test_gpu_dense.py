@@ -49,7 +49,8 @@ def _parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, g=None, eps=0.1
         sub = np.arange(R) if R_sub is None else np.asarray(R_sub)
         op = psi0[sub].astype(np.float64)
         og = np.zeros((len(sub), n))
-        fp, fg = psi0[sub].copy(), np.zeros((len(sub), n), np.float32)
+        fl = None if strict else P.Floor(J, psi0[sub], None, model=model, dt=dt, eps=eps, g=g,
+                                         integrator=integrator, s=s, **okw)
         prev = 0
         worst = []
         for st in steps_list:
@@ -57,15 +58,14 @@ def _parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, g=None, eps=0.1
             op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=eps, g=g,
                            integrator=integrator, nthreads=oracle_threads, s=s, **okw)
             if not strict:
-                fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=eps, g=g,
-                                   integrator=integrator, s=s, **okw)
+                fl.advance(st - prev)
             prev = st
             p, gm, step = S.state()
             assert step == st
             ep = _rel(p[sub], op)
             eg = _rel(gm[sub], og)
             worst.append((st, float(ep.max()), float(eg.max())))
-            floor = None if strict else np.maximum(_rel(fp, op), _rel(fg, og))
+            floor = None if strict else fl.floor(op, og)
             P.check(ep, eg, floor, strict=strict, max_used=max_used, label=f"{model} n={n} step {st}")
         print("worst per snapshot (step, psi, gamma):", worst)
         return S, worst
@@ -134,13 +134,13 @@ def test_every_fp32_variant_parity_n1000(monkeypatch, model, integrator, dt):
     s = O.coupling_scale(J.astype(np.float64))
     ref = []
     op, og = psi0.astype(np.float64), np.zeros((R, n))
-    fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
+    fl = P.Floor(J, psi0, None, model=model, dt=dt, eps=0.1, integrator=integrator, s=s)
     prev = 0
     for st in steps:
         op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
-        fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
+        fl.advance(st - prev)
         prev = st
-        ref.append((op, og, np.maximum(_rel(fp, op), _rel(fg, og))))
+        ref.append((op, og, fl.floor(op, og)))
     mdl = gd.GD_XY if cx else gd.GD_ISING
     for cid in FP32_VARIANTS:
         monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))

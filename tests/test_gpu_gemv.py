@@ -49,17 +49,16 @@ def _gemv_parity(J, psi0, model, integrator, dt, steps_list=(1, 50, 200), strict
         assert abs(S.scale - s) <= 1e-12 * s
         S.set_init(R, psi0)
         op, og = psi0.astype(np.float64), np.zeros((R, n))
-        fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
+        fl = P.Floor(J, psi0, None, model=model, dt=dt, eps=0.1, integrator=integrator, s=s)
         prev = 0
         for st in steps_list:
             S.run(st - prev)
             op, og = O.run(J, op, og, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator, s=s)
-            fp, fg = O.run_f32(J, fp, fg, model=model, steps=st - prev, dt=dt, eps=0.1, integrator=integrator,
-                               s=s)
+            fl.advance(st - prev)
             prev = st
             p, gm, step = S.state()
             assert step == st
-            P.check(P.rel(p, op), P.rel(gm, og), None if strict else np.maximum(P.rel(fp, op), P.rel(fg, og)),
+            P.check(P.rel(p, op), P.rel(gm, og), None if strict else fl.floor(op, og),
                     min_strict=min_strict, label=f"gemv {model} n={n} R={R} step {st}")
         stats = S.stats()
         spins = S.spins() if model == "ising" else None
@@ -142,10 +141,10 @@ def test_gemv_field_per_spin_eps_and_gamma_c(monkeypatch):
             assert S.stats().kernel_config == 100
         op, og = O.run(J, x0, model=model, steps=200, dt=dt, eps=eps, g=gs, gamma_c=0.2, s=s,
                        integrator=O.RK4 if integ == gd.GD_RK4 else O.EULER)
-        fp, fg = O.run_f32(J, x0, np.zeros((x0.shape[0], n), np.float32), model=model, steps=200, dt=dt,
-                           eps=eps, g=gs, gamma_c=0.2, s=s, integrator=O.RK4 if integ == gd.GD_RK4 else O.EULER)
-        P.check(P.rel(p, op), P.rel(gm, og), np.maximum(P.rel(fp, op), P.rel(fg, og)),
-                label=f"gemv field {model}")
+        fl = P.Floor(J, x0, None, model=model, dt=dt, eps=eps, g=gs, gamma_c=0.2, s=s,
+                     integrator=O.RK4 if integ == gd.GD_RK4 else O.EULER)
+        fl.advance(200)
+        P.check(P.rel(p, op), P.rel(gm, og), fl.floor(op, og), label=f"gemv field {model}")
 
 
 def test_gemv_deterministic_and_matches_gemm(monkeypatch):
@@ -233,3 +232,33 @@ def test_gemv_graph_replay_matches_eager_bitwise():
             assert S.stats().kernel_config >= 100
             out.append(S.state())
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("cid", GEMV_IDS)
+def test_fp32_solver_fp8_copy_of_j_equals_fp32_couplings_bitwise(monkeypatch, cid):
+    """An FP32 solver whose couplings are all exact in FP8 streams a one-byte
+    copy of J in the few-trajectory kernels, read where the FP32 kind reads its
+    16-byte words and summed in the same order: every variant gives, bit for
+    bit, the state and energies of the same run on FP32 couplings (the copy
+    turned off with GD_J8_COPY=0), for ragged real (Euler) and complex (RK4)
+    problems."""
+    monkeypatch.setenv("GD_DENSE_CONFIG", str(cid))
+    for model, n, integ, dt in (("ising", 1001, gd.GD_EULER, 0.05), ("xy", 999, gd.GD_RK4, 0.02)):
+        cx = model == "xy"
+        R = min(3, max_columns(cid) // (2 if cx else 1))
+        J = I.dense_pm1(n, 61)
+        psi0 = I.psi0_complex(n, R, 61) if cx else I.psi0_real(n, R, 61)
+        out = []
+        for copy in ("1", "0"):
+            monkeypatch.setenv("GD_J8_COPY", copy)
+            with gd.Solver(J, model=gd.GD_XY if cx else gd.GD_ISING, integrator=integ, dt=dt, eps=0.1,
+                           check_interval=25) as S:
+                S.set_init(R, psi0)
+                S.run(60)
+                p, g, _ = S.state()
+                E, b = S.energy(device_path=True)
+                assert S.stats().kernel_config == cid
+                out.append((p, g, E, b, S.stats().best_energy))
+        (p1, g1, E1, b1, be1), (p0, g0, E0, b0, be0) = out
+        assert np.array_equal(p1, p0) and np.array_equal(g1, g0), (model, cid)
+        assert np.array_equal(E1, E0) and b1 == b0 and be1 == be0, (model, cid)

@@ -106,7 +106,7 @@ def test_one_step_bound_complex_rk4():
 
 # every reduced-precision variant of the runtime's table (tile shapes, BK),
 # each forced in turn
-LP_VARIANTS = range(11)
+LP_VARIANTS = range(14)
 
 
 def test_every_lowprec_variant_one_step_bound(monkeypatch):

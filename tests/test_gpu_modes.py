@@ -66,21 +66,20 @@ def parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, strict=False, ma
         h = _hq_rows(model, q, kw.get("h_q") or default_hq(J, s), n)
         op = psi0.astype(np.float64)
         og = np.zeros((R, n))
-        fp, fg = psi0.copy(), np.zeros((R, n), np.float32)
+        fl = P.Floor(J, psi0, None, model=om, dt=dt, integrator=integrator, s=s, h=h, **okw)
         prev = 0
         worst = []
         for st in steps_list:
             S.run(st - prev)
             op, og = O.run(J, op, og, model=om, steps=st - prev, dt=dt, integrator=integrator,
                            s=s, h=h, t0=prev, **okw)
-            fp, fg = O.run_f32(J, fp, fg, model=om, steps=st - prev, dt=dt, integrator=integrator,
-                               s=s, h=h, t0=prev, **okw)
+            fl.advance(st - prev, t0=prev)
             prev = st
             p, gm, step = S.state()
             assert step == st
             ep, eg = _rel(p, op), _rel(gm, og)
             worst.append((st, float(ep.max()), float(eg.max())))
-            P.check(ep, eg, np.maximum(_rel(fp, op), _rel(fg, og)), strict=strict, max_used=max_used,
+            P.check(ep, eg, fl.floor(op, og), strict=strict, max_used=max_used,
                     label=f"model {model} n={n} step {st}")
         print("worst per snapshot (step, psi, gamma):", worst)
     except BaseException:

@@ -213,3 +213,42 @@ def test_run_f32_floor_follows_rounding_model(name, model, integrator, dt, n, R,
     ratio = floor / model_dist
     assert np.all(ratio <= 4.0), (name, ratio.max(), int(np.argmax(ratio)))
     assert np.all(ratio >= 1.0 / 300), (name, ratio.min(), int(np.argmin(ratio)))
+
+
+def test_multi_order_floor_is_rounding_only():
+    """The parity floor takes the largest distance of float32 runs that differ
+    only in the order of the coupling sums (spins relabelled).  Relabelling
+    is exact for the FP64 oracle (equivariance to FP64 rounding), each
+    relabelled float32 run stays inside the single-precision band of the
+    natural one, and the floor over orders is at least the natural floor."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import _parity as P
+    n, R = 120, 6
+    J = I.dense_pm1(n, 61)
+    x0 = I.psi0_real(n, R, 61)
+    rng = np.random.default_rng(61)
+    eps = rng.uniform(0.05, 0.2, n)
+    g = rng.integers(-2, 3, n).astype(np.float64)
+    s = O.coupling_scale(J.astype(np.float64))
+    kw = dict(model="ising", dt=0.05, eps=eps, g=g, s=s)
+    xo, go = O.run(J, x0.astype(np.float64), None, steps=100, **kw)
+    perm = np.random.default_rng(1234 + n).permutation(n)
+    xp, gp = O.run(J[np.ix_(perm, perm)], x0[:, perm].astype(np.float64), None, steps=100,
+                   model="ising", dt=0.05, eps=eps[perm], g=g[perm], s=s)
+    inv = np.argsort(perm)
+    assert np.abs(xp[:, inv] - xo).max() <= 1e-10 * np.abs(xo).max()
+    fl = P.Floor(J, x0, None, **kw)
+    assert len(fl.runs) == 3
+    fl.advance(60)
+    fl.advance(40)
+    floors = [np.maximum(P.rel(x, xo), P.rel(gm, go)) for x, gm in fl.states()]
+    assert all(np.all(f < 1e-3) and np.all(f > 0) for f in floors)
+    assert np.array_equal(fl.floor(xo, go), np.max(floors, axis=0))
+    assert np.all(fl.floor(xo, go) >= floors[0])
+    one = P.Floor(J, x0, None, orders=1, **kw)
+    one.advance(100)
+    xf, gf = O.run_f32(J, x0, None, steps=100, **kw)
+    assert np.array_equal(one.states()[0][0], xf)
+    noisy = P.Floor(J, x0, None, noise_D=0.01, **kw)
+    assert len(noisy.runs) == 1
