@@ -422,7 +422,10 @@ int gd_mlp_set_params(gd_mlp *m, const float *params);
 int gd_mlp_get_params(gd_mlp *m, float *params);
 
 /* outputs [M][2] for features X [M][GD_NFEAT]; fp16 != 0 runs the FP16
- * inference kernel (parameters and activations in half precision). */
+ * inference kernel (parameters, features and activations rounded to half
+ * precision, products summed in FP32 on the matrix cores).  With
+ * GD_F_DEVICE_PTRS the FP16 kernel reads X in 16-byte words: X must be
+ * 16-byte aligned (GD_E_INVALID_ARG otherwise). */
 int gd_mlp_forward(gd_mlp *m, int32_t M, const float *X, float *out, int32_t fp16);
 
 /*

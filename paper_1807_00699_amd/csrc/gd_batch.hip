@@ -17,8 +17,9 @@
 //   c   = (1/s_k) sum_d w_id x_{j(i,d)}
 //   x  += dt [ x (gamma - gamma_c - x^2) + c + h_1 ]
 //   gamma += dt eps_i (rho_th - x^2)
-// The update order is fixed (sum over d in list order), so a trajectory's
-// result does not depend on T, NT or the rest of the batch.
+// The arithmetic is fixed (fused multiply-adds over d in list order, then
+// batch_euler_update with contraction off), so a trajectory's result does not
+// depend on the variant, T, NT or the rest of the batch.
 // After the last step the Eq. (h) energy of the discretised state
 // (s_i = sign x_i) is reduced per trajectory in FP64 in a fixed order.
 #include "gd_internal.h"
@@ -39,6 +40,20 @@ __device__ inline float signed_nb(const unsigned char *xlb, const uint2 w, int r
     const float v = *reinterpret_cast<const float *>(xlb + (idx << SH) + rb);
     const unsigned int sgn = (w.y << D) & 0x80000000u;      // bit 31 - D
     return __uint_as_float(__float_as_uint(v) ^ sgn);
+}
+
+// One explicit Euler step of Eq. (main) and Eq. (gamma) for a real amplitude
+// x with gain g and coupling sum c: the operations and their rounding are
+// written out (no contraction beyond the written fmas), so every batch kernel
+// variant produces the same bits whatever its instruction schedule.
+__device__ inline void batch_euler_update(float &x, float &g, float c, float inv_s, float h1, float eps,
+                                          float gc, float rho_th, float dt) {
+#pragma clang fp contract(off)
+    const float rho = x * x;
+    const float f = __builtin_fmaf(x, (g - gc) - rho, __builtin_fmaf(c, inv_s, h1));
+    const float gn = __builtin_fmaf(dt, eps * (rho_th - rho), g);
+    x = __builtin_fmaf(dt, f, x);
+    g = gn;
 }
 
 // PK: the neighbours of the thread's spins live in registers (two words per
@@ -129,13 +144,10 @@ batch_ell_euler(BatchArgs a) {
                         c = __builtin_fmaf(signed_nb<1, T>(src, nb[s], rb), mag, c);
                         c = __builtin_fmaf(signed_nb<2, T>(src, nb[s], rb), mag, c);
                     } else {
-                        for (int d = 0; d < dmax; ++d) c += wl[i * dmax + d] * xl[il[i * dmax + d] * T + r];
+                        for (int d = 0; d < dmax; ++d)
+                            c = __builtin_fmaf(wl[i * dmax + d], xl[il[i * dmax + d] * T + r], c);
                     }
-                    const float x = xo[s];
-                    const float rho = x * x;
-                    const float f = x * (go[s] - gc - rho) + c * inv_s + hh[UNI ? 0 : s];
-                    xo[s] = x + dt * f;
-                    go[s] = go[s] + dt * (ep[UNI ? 0 : s] * (rho_th - rho));
+                    batch_euler_update(xo[s], go[s], c, inv_s, hh[UNI ? 0 : s], ep[UNI ? 0 : s], gc, rho_th, dt);
                     if constexpr (DB) dst[i * T + r] = xo[s];
                 }
             }
@@ -299,11 +311,7 @@ batch_ell_tw(BatchArgs a) {
                         const unsigned int sgn = (w.y << d) & 0x80000000u;
                         c = __builtin_fmaf(__uint_as_float(__float_as_uint(v) ^ sgn), mag, c);
                     }
-                    const float x = xo[s];
-                    const float rho = x * x;
-                    const float f = x * (go[s] - gc - rho) + c * inv_s + hh[UNI ? 0 : s];
-                    xo[s] = x + dt * f;
-                    go[s] = go[s] + dt * (ep[UNI ? 0 : s] * (rho_th - rho));
+                    batch_euler_update(xo[s], go[s], c, inv_s, hh[UNI ? 0 : s], ep[UNI ? 0 : s], gc, rho_th, dt);
                     dst[i * T + r] = xo[s];
                 }
             }

@@ -399,26 +399,42 @@ __global__ void __launch_bounds__(MFT) mlp_forward_mfma_k(const float *__restric
     const int lane = tid & 63, h = lane >> 5, l32 = lane & 31;
     const float b30 = p[OFF_B3], b31 = p[OFF_B3 + 1];
     const int ntiles = (M + 31) / 32;
-    for (int t = blockIdx.x * (MFT / 64) + (tid >> 6); t < ntiles; t += gridDim.x * (MFT / 64)) {
+    const int stride = gridDim.x * (MFT / 64);
+    // the feature words of a tile (rows of F = 20 floats are 16-byte aligned:
+    // four-float loads, zeros past feature 19); the next tile's are loaded
+    // while the current one is multiplied
+    static_assert(F == 20, "feature row of five 16-byte words");
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto load_x = [&](int t, float4 &w0, float4 &w1, float4 &w2) {
+        const long long m = (long long)t * 32 + l32;
+        const bool ok = t < ntiles && m < M;
+        const float4 *xr = reinterpret_cast<const float4 *>(X + (ok ? m : 0) * F);
+        w0 = ok ? xr[2 * h] : z4;
+        w1 = ok ? xr[2 * h + 1] : z4;
+        w2 = ok && h == 0 ? xr[4] : z4;
+    };
+    int t = blockIdx.x * (MFT / 64) + (tid >> 6);
+    float4 c0, c1, c2;
+    load_x(t, c0, c1, c2);
+    for (; t < ntiles; t += stride) {
         const long long m = (long long)t * 32 + l32;
         const bool ok = m < M;
-        // B1: features 16 s + 8 h + j of spin m (rows of F = 20 floats are
-        // 16-byte aligned: four-float loads, zeros past feature 19)
-        static_assert(F == 20, "feature row of five 16-byte words");
+        float4 n0, n1, n2;
+        load_x(t + stride, n0, n1, n2);
+        // B1: features 16 s + 8 h + j of spin m
         f16x8_t xb[2];
         {
-            const float4 *xr = reinterpret_cast<const float4 *>(X + (ok ? m : 0) * F);
-            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float4 a0 = ok ? xr[2 * h] : z4, a1 = ok ? xr[2 * h + 1] : z4;
-            const float4 c0 = ok && h == 0 ? xr[4] : z4;
-            const float v0[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-            const float v1[4] = {c0.x, c0.y, c0.z, c0.w};
+            const float v0[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const float v1[4] = {c2.x, c2.y, c2.z, c2.w};
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 xb[0][j] = (_Float16)v0[j];
                 xb[1][j] = (_Float16)(j < 4 ? v1[j] : 0.0f);
             }
         }
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
         f32x16_t z1[2], z2[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
@@ -681,6 +697,8 @@ hipError_t launch_mlp_forward(const float *params, const float *X, float *out, i
     if (M <= 0) return hipSuccess;
     const int g = (M + MT - 1) / MT;
     if (fp16) {
+        // the feature rows are read as 16-byte words
+        if (reinterpret_cast<uintptr_t>(X) % 16) return hipErrorInvalidValue;
         // one wave per 32 spins at a time; at most the workgroups that are
         // resident at once (two per CU), so each builds the weight operands once
         const int tiles = (M + 31) / 32;

@@ -187,6 +187,8 @@ int gd_mlp_forward(gd_mlp *m, int32_t M, const float *X, float *out, int32_t fp1
     int rc = ensure_ws(m, M, 0);
     if (rc != GD_OK) return rc;
     const float *Xd = X;
+    if (fp16 && (m->flags & GD_F_DEVICE_PTRS) && reinterpret_cast<uintptr_t>(X) % 16)
+        return gd_fail(GD_E_INVALID_ARG, "X must be 16-byte aligned for the FP16 kernel");
     if (!(m->flags & GD_F_DEVICE_PTRS)) {
         GD_TRY(hipMemcpyAsync(m->X, X, (size_t)M * kMlpF * 4, hipMemcpyHostToDevice, m->stream));
         Xd = m->X;

@@ -95,6 +95,16 @@ def test_mlp_device_pointer_calls_match_host_calls():
         for fp16 in (False, True):
             md.forward_device(Xd, od, fp16)
             assert np.array_equal(od.cpu().numpy(), mh.forward(X, fp16=fp16))
+        # the FP16 kernel reads feature rows as 16-byte words: a device X off
+        # that alignment is refused (the FP32 kernel takes it)
+        buf = torch.zeros(X.size + 1, dtype=torch.float32, device="cuda")
+        buf[1:] = Xd.reshape(-1)
+        Xm = buf[1:].view(X.shape)
+        with pytest.raises(gd.GDError) as ei:
+            md.forward_device(Xm, od, True)
+        assert ei.value.code == gd.GD_E_INVALID_ARG
+        md.forward_device(Xm, od, False)
+        assert np.array_equal(od.cpu().numpy(), mh.forward(X, fp16=False))
         for _ in range(3):
             lh = mh.train_step(X, lab, seg, 1e-3)
             ld = md.train_step_device(Xd, Ld, seg, 1e-3)
