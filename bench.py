@@ -247,7 +247,7 @@ def bench_batch(args, wl, steps):
                    "energy_check_every": args.check, "kernel_config": st.kernel_config},
         "roofline": {"bound": "lds", "achieved": lds_bytes / kern_s / 1e9, "peak": PEAK_LDS_GBS,
                      "unit": "GB/s", "frac": lds_bytes / kern_s / 1e9 / PEAK_LDS_GBS,
-                     "traffic": None, "kernel": "batch_ell_euler",
+                     "traffic": None, "kernel": "batch_ell_tw" if st.kernel_config >= 15 else "batch_ell_euler",
                      "launches": int(st.kernel_launches - st0.kernel_launches),
                      "kernel_seconds": kern_s, "lds_bytes_per_update": 16,
                      "alu_tflops": flops / kern_s / 1e12, "alu_peak_tflops": PEAK_FP32_VALU_TFLOPS},
