@@ -103,9 +103,11 @@ def fp8_exact(J):
 
 def kernel_traffic(config_id, kern="dense_step_f32", workload="xy1024"):
     """HBM bytes per launch of a coupling kernel from its committed counter
-    summary (profiles/<kernel>_<workload>_counters.txt), or None when there is
-    none, the kernel sources changed since the counters were taken or another
-    variant runs."""
+    summary (profiles/<kernel>_<workload>_counters.txt: one
+    traffic_bytes_per_launch for kernel_config_id, or one
+    traffic_bytes_per_launch_cfg<id> per variant measured), or None when there
+    is none, the kernel sources changed since the counters were taken or the
+    running variant was not measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_counters.txt")
     if not os.path.exists(path):
@@ -115,6 +117,8 @@ def kernel_traffic(config_id, kern="dense_step_f32", workload="xy1024"):
     src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES[kern])
     if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_source_sha256_16"):
         return None
+    if f"traffic_bytes_per_launch_cfg{int(config_id)}" in kv:
+        return float(kv[f"traffic_bytes_per_launch_cfg{int(config_id)}"])
     if int(kv.get("kernel_config_id", -1)) != int(config_id):
         return None
     return float(kv["traffic_bytes_per_launch"])

@@ -693,7 +693,7 @@ hipError_t launch_lp(bool cx, int op, bool jfp8, int mode, const DenseStepArgs &
     X(9, 128, 256, 64, 2, 4, 1)     \
     X(10, 256, 128, 64, 4, 2, 1)    \
     X(11, 256, 256, 64, 2, 4, 4097) \
-    X(12, 256, 256, 64, 2, 4, 4099) \
+    X(12, 128, 256, 64, 2, 4, 4097) \
     X(13, 256, 128, 64, 2, 2, 4097)
 
 }  // namespace
