@@ -811,15 +811,18 @@ def headline(args):
     print(json.dumps(out), flush=True)
 
 
-def tts99(reach_s, horizons_s):
+def tts99(reach, horizons):
     """Time to solution with 99% confidence from independent starts: for a
     run length T, p(T) = fraction of starts that reached the target by T and
     TTS99(T) = T ln(0.01) / ln(1 - p(T)) (T itself when every start reached
-    it); the minimum over the check times T.  None when no start reached it."""
+    it); the minimum over the check times T.  None when no start reached it.
+    `reach` and `horizons` share one unit (steps here, so that a start is
+    counted at the check where it reached the target whatever its own time
+    per step)."""
     best, at = None, None
-    m = len(reach_s)
-    for T in horizons_s:
-        p = sum(1 for x in reach_s if x is not None and x <= T) / m
+    m = len(reach)
+    for T in horizons:
+        p = sum(1 for x in reach if x is not None and x <= T) / m
         if p == 0:
             continue
         v = T if p == 1 else T * np.log(0.01) / np.log(1.0 - p)
@@ -884,7 +887,9 @@ def headline_ttt(args, J, x0, n, R, dt):
         srt = sorted(x if x is not None else np.inf for x in secs)
         med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
         sps_med = float(np.median([r[2] for r in rs]))
-        tts, at = tts99(secs, [c * sps_med for c in range(chk, budget + 1, chk)])
+        tts, at = tts99(steps_at, range(chk, budget + 1, chk))
+        tts = None if tts is None else float(tts * sps_med)
+        at = None if at is None else float(at * sps_med)
         forms[name] = {"seconds": secs, "steps": steps_at, "best_energy": [float(r[1][-1]) for r in rs],
                        "seconds_per_step": sps_med,
                        "median_seconds": None if not np.isfinite(med) else float(med),

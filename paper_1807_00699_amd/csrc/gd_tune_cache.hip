@@ -7,10 +7,13 @@
 // and build stamp); a file with another first line is ignored and rewritten
 // on the next store.  Each further line: "<kind> <key fields...> <variant id>".
 // The callers check every id they read against the problem (fits) and tune
-// again when it does not fit.  Host code only.
+// again when it does not fit.  Stores replace the file atomically (a
+// temporary file renamed over it); two processes storing at once may each
+// drop the other's new entry, which then is tuned again.  Host code only.
 #include "gd_internal.h"
 
 #include <sys/stat.h>
+#include <unistd.h>
 
 #include <cstdio>
 #include <cstdlib>
@@ -107,12 +110,22 @@ void tune_cache_store(const char *kind, const std::vector<long long> &key, int i
     if (g_path.empty()) return;
     const std::string k = entry_key(kind, key);
     g_entries[k] = id;
-    // rewrite the whole file: the header of this device and build, then every entry
+    // write the whole file (the header of this device and build, then every
+    // entry) under a temporary name and rename it over the old one, so that
+    // another process reading the file sees either version whole
+    const std::string tmp = g_path + ".tmp" + std::to_string((long long)getpid());
+    bool ok;
     {
-        std::ofstream out(g_path, std::ios::trunc);
+        std::ofstream out(tmp, std::ios::trunc);
         if (!out) return;
         out << header() << "\n";
         for (const auto &e : g_entries) out << e.first << " " << e.second << "\n";
+        out.flush();
+        ok = bool(out);
+    }
+    if (!ok || std::rename(tmp.c_str(), g_path.c_str()) != 0) {
+        std::remove(tmp.c_str());
+        return;
     }
     file_stamp(g_path, g_size, g_mtime);
 }
