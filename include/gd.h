@@ -185,7 +185,12 @@ typedef struct gd_run_stats {
                                  GD_E_INVALID_ARG if that id does not fit).  Problems of
                                  at most 128 padded spins (FP32, no pinned variant) use a
                                  fused multi-step kernel instead of the variants.  Batches
-                                 of instances: the same with GD_BATCH_CONFIG=<id>.  With
+                                 of instances: the same with GD_BATCH_CONFIG=<id>; the
+                                 variants with per-instance item widths also relabel each
+                                 instance's spins at set-up (host threads, deterministic,
+                                 results unchanged bit for bit) so that their LDS gathers
+                                 avoid bank conflicts; GD_BATCH_RELABEL=0 keeps the
+                                 given order.  With
                                  GD_AUTOTUNE_CACHE=<file> the picks persist across
                                  processes: the file names the device and library build
                                  in its first line (a file of another device or build is

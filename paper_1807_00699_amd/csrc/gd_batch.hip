@@ -24,6 +24,8 @@
 // (s_i = sign x_i) is reduced per trajectory in FP64 in a fixed order.
 #include "gd_internal.h"
 
+#include <type_traits>
+
 namespace gd {
 
 namespace {
@@ -233,14 +235,29 @@ batch_ell_euler(BatchArgs a) {
 // trajectory r = t mod T_k and the spins t / T_k + s NT / T_k; the products,
 // their order and the update are those of batch_ell_euler, so a trajectory's
 // result does not depend on the variant.
+// The spins of an instance are relabeled by the host (label = LDS row and
+// position of the slot that updates the spin) so that the d-th neighbours of
+// the G = 64 / T_k spins one gather instruction serves fall on different
+// banks as far as possible; the state is staged through the labels, the
+// per-spin constants are read at the spin's own index.
+// The step loop is written for the vector ALU, which bounds it: each slot
+// keeps the byte offsets of its three neighbour amplitudes and of its own
+// amplitude in buffer 0, and the three couplings as signed magnitudes
+// (+-mag times x is bit for bit the product of mag and +-x, so no sign flip
+// per term); buffer 1 sits at the fixed offset (E NT + 64) words, and the
+// steps run in pairs so that the buffer a step reads or writes is a constant
+// offset folded into the LDS instruction.
 template <int NT, int E, bool UNI>
 __global__ void __launch_bounds__(NT)
 batch_ell_tw(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr unsigned B1 = (unsigned)(E * NT + 64) * 4u;             // byte offset of buffer 1
+    static_assert(B1 < 65536, "the offset of buffer 1 fits the LDS instruction's immediate");
     const int tid = threadIdx.x;
     float *xl0 = reinterpret_cast<float *>(smem);
+    float *xl1 = reinterpret_cast<float *>(smem + B1);
     double *red = reinterpret_cast<double *>(smem);                   // reuse after the run
-    const uint2 *pk = reinterpret_cast<const uint2 *>(a.ell_pack);
+    const uint2 *pk = reinterpret_cast<const uint2 *>(a.tw_pack);    // in label order
 
     for (int it = a.wg_off[blockIdx.x]; it < a.wg_off[blockIdx.x + 1]; ++it) {
         const int item = a.items[it];
@@ -255,18 +272,21 @@ batch_ell_tw(BatchArgs a) {
         const long long blk = a.inst_state[k] + (long long)r0 * n;      // rows r0 .. r0 + T - 1 of [R][n]
         const float inv_s = a.inst_inv_s[k];
         const float mag = a.inst_wmag[k];
-        const int rows = n + 1;                                          // + the zero row n
-        float *xl1 = xl0 + (size_t)rows * T;
-        // stage the item's amplitudes (buffer 0) and gains (buffer 1) as [i][T]
-        // from coalesced reads of the [T][n] block
+        // stage the item's amplitudes (buffer 0) and gains (buffer 1) as
+        // [label][T] from coalesced reads of the [T][n] block
+        const int *lab = a.tw_label + spin0;
+        const int *spn = a.tw_spin + spin0;
         for (int q = tid; q < T * n; q += NT) {
             const int rr = q / n, i = q - rr * n;
-            xl0[i * T + rr] = a.x[blk + q];
-            xl1[i * T + rr] = a.gam[blk + q];
+            const int p = lab[i];
+            xl0[p * T + rr] = a.x[blk + q];
+            xl1[p * T + rr] = a.gam[blk + q];
         }
         __syncthreads();
         float xo[E], go[E], ep[UNI ? 1 : E], hh[UNI ? 1 : E];
-        uint2 nb[E];
+        const float *na[E][3];           // in buffer 0: the neighbours' amplitudes (row n if missing)
+        float *wa[E];                    // and the own amplitude
+        float sm[E][3];                  // couplings as signed magnitudes
         if constexpr (UNI) {
             ep[0] = a.eps0;
             hh[0] = -0.0f;
@@ -276,15 +296,27 @@ batch_ell_tw(BatchArgs a) {
             const int i = ibase + s * ISTR;
             xo[s] = go[s] = 0.0f;
             if constexpr (!UNI) ep[s] = hh[s] = 0.0f;
-            nb[s] = uint2{0u, 0u};
-            if (i < n) {
+            wa[s] = xl0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                na[s][d] = xl0;
+                sm[s][d] = 0.0f;
+            }
+            if (i < n) {                      // i: the label of the slot's spin
                 xo[s] = xl0[i * T + r];
                 go[s] = xl1[i * T + r];
                 if constexpr (!UNI) {
-                    ep[s] = a.eps[spin0 + i];
-                    hh[s] = a.h1[spin0 + i];
+                    ep[s] = a.eps[spin0 + spn[i]];
+                    hh[s] = a.h1[spin0 + spn[i]];
                 }
-                nb[s] = pk[spin0 + i];
+                const uint2 w = pk[spin0 + i];
+                const unsigned idx[3] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    na[s][d] = xl0 + ((int)idx[d] << tlog) + r;
+                    sm[s][d] = __uint_as_float(__float_as_uint(mag) ^ ((w.y << d) & 0x80000000u));
+                }
+                wa[s] = xl0 + (i << tlog) + r;
             }
         }
         __syncthreads();                      // gains read before buffer 1 holds amplitudes
@@ -294,29 +326,31 @@ batch_ell_tw(BatchArgs a) {
         }
         __syncthreads();
         const float dt = a.dt, gc = a.gamma_c, rho_th = a.rho_th;
-        const int rb = r * 4, sh = tlog + 2;
-        for (int step = 0; step < a.steps; ++step) {
-            const unsigned char *src = reinterpret_cast<const unsigned char *>((step & 1) ? xl1 : xl0);
-            float *dst = (step & 1) ? xl0 : xl1;
+        // one step reading the buffer at byte offset RD, writing the other
+        auto step = [&](auto rd) {
+            constexpr int RD = decltype(rd)::value / 4;           // in words
+            constexpr int WR = RD ? 0 : (int)B1 / 4;
 #pragma unroll
             for (int s = 0; s < E; ++s) {
-                const int i = ibase + s * ISTR;
-                if (i < n) {
-                    const uint2 w = nb[s];
-                    float c = 0.0f;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const unsigned int idx = d == 0 ? (w.x & 0xFFFFu) : (d == 1 ? (w.x >> 16) : (w.y & 0xFFFFu));
-                        const float v = *reinterpret_cast<const float *>(src + (idx << sh) + rb);
-                        const unsigned int sgn = (w.y << d) & 0x80000000u;
-                        c = __builtin_fmaf(__uint_as_float(__float_as_uint(v) ^ sgn), mag, c);
-                    }
+                if (ibase + s * ISTR < n) {
+                    const float v0 = na[s][0][RD];
+                    const float v1 = na[s][1][RD];
+                    const float v2 = na[s][2][RD];
+                    float c = __builtin_fmaf(v0, sm[s][0], 0.0f);
+                    c = __builtin_fmaf(v1, sm[s][1], c);
+                    c = __builtin_fmaf(v2, sm[s][2], c);
                     batch_euler_update(xo[s], go[s], c, inv_s, hh[UNI ? 0 : s], ep[UNI ? 0 : s], gc, rho_th, dt);
-                    dst[i * T + r] = xo[s];
+                    wa[s][WR] = xo[s];
                 }
             }
             __syncthreads();
+        };
+        int t = 0;
+        for (; t + 1 < a.steps; t += 2) {
+            step(std::integral_constant<unsigned, 0u>{});
+            step(std::integral_constant<unsigned, B1>{});
         }
+        if (t < a.steps) step(std::integral_constant<unsigned, 0u>{});
         // final amplitudes in buffer steps % 2 (the last step's target); the
         // other buffer stages the gains for the write-back
         const float *xf = (a.steps & 1) ? xl1 : xl0;
@@ -331,24 +365,24 @@ batch_ell_tw(BatchArgs a) {
                 bad |= !(__builtin_isfinite(xo[s]) && __builtin_isfinite(go[s]));
                 // Eq. (h) of the discretised state: -s_i sum_d w_id s_j + g_i s_i
                 const double si = xo[s] < 0.0f ? -1.0 : 1.0;
-                const uint2 w = nb[s];
-                const unsigned int idx[3] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu};
                 double h = 0.0;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    if ((int)idx[d] == n) continue;
-                    const float xj = xf[idx[d] * T + r];
-                    const double sg = ((w.y << d) & 0x80000000u) ? -1.0 : 1.0;
+                    const int j = (int)(na[s][d] - xl0) >> tlog;
+                    if (j == n) continue;                                     // missing coupling
+                    const float xj = xf[(j << tlog) + r];
+                    const double sg = (__float_as_uint(sm[s][d]) & 0x80000000u) ? -1.0 : 1.0;
                     h += (double)mag * sg * (xj < 0.0f ? -1.0 : 1.0);
                 }
-                e += -si * h + (double)a.g[spin0 + i] * si;
+                e += -si * h + (double)a.g[spin0 + spn[i]] * si;
             }
         }
         __syncthreads();
         for (int q = tid; q < T * n; q += NT) {
             const int rr = q / n, i = q - rr * n;
-            a.x[blk + q] = xf[i * T + rr];
-            a.gam[blk + q] = gs[i * T + rr];
+            const int p = lab[i];
+            a.x[blk + q] = xf[p * T + rr];
+            a.gam[blk + q] = gs[p * T + rr];
         }
         // per trajectory: lanes of one trajectory within a wave by a butterfly
         // over the lane bits from T up, then the waves in order
@@ -531,7 +565,8 @@ hipError_t launch_batch(const BatchConfig &c, int nwg, const BatchArgs &a, hipSt
     // T_k <= 64 for every instance when it built the schedule
 #define GD_CASE(id, nt, e, uni)                                                                              \
     case id:                                                                                                 \
-        if (!a.ell_pack || !a.inst_wmag || !a.inst_tlog || a.dmax > 3 || a.nmax > 65535)                     \
+        if (!a.tw_pack || !a.tw_label || !a.tw_spin || !a.inst_wmag || !a.inst_tlog || a.dmax > 3 ||          \
+            a.nmax > 65535)                                                                                  \
             return hipErrorInvalidValue;                                                                     \
         batch_ell_tw<nt, e, uni><<<nwg, nt, lds, st>>>(a);                                                   \
         return hipGetLastError();

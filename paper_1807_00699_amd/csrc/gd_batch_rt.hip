@@ -10,8 +10,10 @@
 // the launch for a chunk of steps is captured once in a hipGraph and replayed.
 #include "gd_batch_rt.h"
 #include "gd_internal.h"
+#include "gd_relabel.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -21,6 +23,7 @@
 #include <numeric>
 #include <queue>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -82,6 +85,10 @@ struct BatchSolver {
     unsigned int *d_pack = nullptr;
     float *d_wmag = nullptr;
     bool packable = false;
+    std::vector<unsigned int> pack_host;
+    // spin labels of the per-instance-width variants, per (instance, groups
+    // per gather instruction), computed once
+    std::map<std::pair<int, int>, std::vector<int>> labels;
     bool no_field = true;             // every g_i = 0
     // state
     int R = 0;
@@ -97,6 +104,8 @@ struct BatchSolver {
     int nwg = 0;
     int *d_wg_off = nullptr, *d_items = nullptr;
     int *d_tlog = nullptr;            // per-instance item widths (variants with traj = 0)
+    int *d_tw_label = nullptr, *d_tw_spin = nullptr;   // and their spin labels
+    unsigned int *d_tw_pack = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_steps = -1;
     // stats
@@ -127,7 +136,12 @@ void free_schedule(BatchSolver *b) {
     if (b->d_wg_off) (void)hipFree(b->d_wg_off);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_tlog) (void)hipFree(b->d_tlog);
+    if (b->d_tw_label) (void)hipFree(b->d_tw_label);
+    if (b->d_tw_spin) (void)hipFree(b->d_tw_spin);
+    if (b->d_tw_pack) (void)hipFree(b->d_tw_pack);
     b->d_wg_off = b->d_items = b->d_tlog = nullptr;
+    b->d_tw_label = b->d_tw_spin = nullptr;
+    b->d_tw_pack = nullptr;
     b->nwg = 0;
 }
 
@@ -156,6 +170,9 @@ BatchArgs make_args(BatchSolver *b, int steps, float dt) {
     a.ell_pack = b->d_pack;
     a.inst_wmag = b->d_wmag;
     a.inst_tlog = b->d_tlog;
+    a.tw_label = b->d_tw_label;
+    a.tw_spin = b->d_tw_spin;
+    a.tw_pack = b->d_tw_pack;
     a.eps = b->d_eps;
     a.h1 = b->d_h1;
     a.g = b->d_g;
@@ -208,6 +225,67 @@ bool config_fits(const BatchSolver *b, const BatchConfig &c) {
     return batch_lds_bytes(c, b->nmax, b->dmax) <= 160 * 1024;
 }
 
+// Spin labels of the per-instance-width variants (gather_relabel, per
+// instance with G = 64 / T_k groups per gather instruction; the identity
+// when G <= 2 or with GD_BATCH_RELABEL=0), computed on host threads, and the
+// device arrays made from them: label of each spin, spin of each label, and
+// the packed neighbour words in label order with labels as indices.
+int build_labels(BatchSolver *b, const std::vector<int> &tl) {
+    const char *env = std::getenv("GD_BATCH_RELABEL");
+    const bool on = !(env && std::strcmp(env, "0") == 0);
+    std::vector<std::pair<int, int>> todo;
+    for (int k = 0; k < b->K; ++k) {
+        const int g = on ? 64 >> tl[k] : 1;
+        if (!b->labels.count({k, g})) todo.push_back({k, g});
+    }
+    std::vector<std::vector<int>> got(todo.size());
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t q; (q = next.fetch_add(1)) < todo.size();) {
+            const int k = todo[q].first, g = todo[q].second, n = b->n[k];
+            std::vector<int> nb((size_t)3 * n);
+            for (int i = 0; i < n; ++i) {
+                const unsigned int *w = &b->pack_host[(size_t)(b->spin_off[k] + i) * 2];
+                nb[3 * i] = int(w[0] & 0xFFFFu);
+                nb[3 * i + 1] = int(w[0] >> 16);
+                nb[3 * i + 2] = int(w[1] & 0xFFFFu);
+            }
+            // blocks of G / 2 labels: the rows of one 32-lane pass of a gather
+            got[q] = gather_relabel(n, nb, g, g / 2, uint64_t(k) * 64 + uint64_t(g), 12LL * n).label;
+        }
+    };
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const size_t nth = std::min<size_t>(hw, todo.size());
+    if (nth > 1) {
+        std::vector<std::thread> pool;
+        for (size_t t = 0; t < nth; ++t) pool.emplace_back(work);
+        for (auto &t : pool) t.join();
+    } else {
+        work();
+    }
+    for (size_t q = 0; q < todo.size(); ++q) b->labels[todo[q]] = std::move(got[q]);
+    std::vector<int> label(b->total), spin(b->total);
+    std::vector<unsigned int> tpack((size_t)b->total * 2);
+    for (int k = 0; k < b->K; ++k) {
+        const std::vector<int> &L = b->labels[{k, on ? 64 >> tl[k] : 1}];
+        const int n = b->n[k];
+        const long long off = b->spin_off[k];
+        auto relab = [&](unsigned int j) { return j < (unsigned)n ? (unsigned)L[j] : j; };   // n: the zero row
+        for (int i = 0; i < n; ++i) {
+            const int p = L[i];
+            label[off + i] = p;
+            spin[off + p] = i;
+            const unsigned int *w = &b->pack_host[(size_t)(off + i) * 2];
+            tpack[(size_t)(off + p) * 2] = relab(w[0] & 0xFFFFu) | (relab(w[0] >> 16) << 16);
+            tpack[(size_t)(off + p) * 2 + 1] = relab(w[1] & 0xFFFFu) | (w[1] & 0xE0000000u);
+        }
+    }
+    int rc = upload(&b->d_tw_label, label);
+    if (rc == GD_OK) rc = upload(&b->d_tw_spin, spin);
+    if (rc == GD_OK) rc = upload(&b->d_tw_pack, tpack);
+    return rc;
+}
+
 // Longest processing time first: items sorted by cost, each to the least
 // loaded workgroup (ties -> lowest workgroup id).  Deterministic.
 int build_schedule(BatchSolver *b, const BatchConfig &c) {
@@ -242,6 +320,7 @@ int build_schedule(BatchSolver *b, const BatchConfig &c) {
             }
         }
         if (int rc = upload(&b->d_tlog, tl); rc != GD_OK) return rc;
+        if (int rc = build_labels(b, tl); rc != GD_OK) return rc;
     }
     const long long nitems = (long long)order.size();
     int nwg = int(std::min<long long>((long long)cus * occ, nitems));
@@ -566,6 +645,7 @@ int batch_create(BatchSolver **out, int count, const gd_instance *inst, int mode
     if (rc == GD_OK) rc = upload(&b->d_idx, idx);
     if (rc == GD_OK) rc = upload(&b->d_w, w);
     if (rc == GD_OK && b->packable) rc = upload(&b->d_pack, pack);
+    b->pack_host = std::move(pack);
     if (rc == GD_OK && b->packable) rc = upload(&b->d_wmag, wmag);
     if (rc == GD_OK) rc = upload(&b->d_eps, b->eps_host);
     if (rc == GD_OK) rc = upload(&b->d_h1, h1);

@@ -124,6 +124,12 @@ struct BatchArgs {
     const unsigned int *ell_pack;
     const float *inst_wmag;       // [K] the magnitude of instance k's couplings
     const int *inst_tlog;         // [K] per-instance-width variants: log2 of instance k's item width
+    // per-instance-width variants: spins relabeled per instance for the LDS
+    // gathers (label = LDS row and slot of a spin): label of spin i, spin of
+    // label p (both [sum n], instance-local values), and the packed
+    // neighbours in label order with labels as indices ([sum n][2] words)
+    const int *tw_label, *tw_spin;
+    const unsigned int *tw_pack;
     const float *eps, *h1, *g;    // [sum n]
     float *x, *gam;               // state [sum_k R n_k]
     double *E;                    // [K][R] energies after the launch
