@@ -564,11 +564,13 @@ def learned_bench(args):
     inference over all spins; gd_propose (features + FP16 network + initial
     state) for the 256 instances x R = 64.  Flops per spin row: forward
     2 (20*64 + 64*64 + 64*2) = 11 008, a training step about three times that
-    (forward, activation and weight gradients).  Training and FP32 inference
-    run on the FP32 vector ALUs (78.6 TFLOP/s without packed math); FP16
-    inference on the matrix cores (FP16 MFMA 2.5 PFLOP/s), where the features
-    it reads (80 B per row) and the outputs it writes (8 B) make HBM (8 TB/s)
-    the bound."""
+    (forward, activation and weight gradients).  Training runs on the FP32
+    matrix cores (157.3 TFLOP/s) and the step's time includes its host round
+    trip (the loss is read back every step); FP32 inference, the reference
+    form of the network, on the FP32 vector ALUs (78.6 TFLOP/s without packed
+    math); FP16 inference on the matrix cores (FP16 MFMA 2.5 PFLOP/s), where
+    the features it reads (80 B per row) and the outputs it writes (8 B) make
+    HBM (8 TB/s) the bound."""
     import torch
 
     from paper_1807_00699_amd import gd
@@ -610,7 +612,7 @@ def learned_bench(args):
         out["train"] = {"steps": steps, "rows_per_s": rows / el, "instances_per_s": 64 * steps / el,
                         "ms_per_step": 1e3 * el / steps,
                         "tflops": 3 * fwd * rows / el / 1e12,
-                        "frac": 3 * fwd * rows / el / 1e12 / peak}
+                        "frac_fp32_mfma": 3 * fwd * rows / el / 1e12 / PEAKS_TFLOPS["fp32"]}
         o = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
         for name, fp16 in (("infer_fp16", True), ("infer_fp32", False)):
             for _ in range(3):

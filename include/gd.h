@@ -441,7 +441,9 @@ int gd_mlp_forward(gd_mlp *m, int32_t M, const float *X, float *out, int32_t fp1
  *   L = (1/M) sum_i [(m_i - sigma_k s_i)^2 + 0.5 BCE(c_i, [m_i sigma_k s_i > 0])].
  * lr > 0 applies Adam (0.9, 0.999, 1e-8, bias-corrected); lr = 0 only
  * evaluates.  loss and grad [GD_MLP_NPARAM] (host, nullable) receive the
- * loss and the gradient at the parameters before the update.
+ * loss and the gradient at the parameters before the update.  Computed on
+ * the FP32 matrix cores (FP32 products and sums; the gradient summed over
+ * rows in a fixed order, so repeated calls give the same bits).
  */
 int gd_mlp_train_step(gd_mlp *m, int32_t M, const float *X, const float *labels, int32_t K,
                       const int32_t *seg, float lr, double *loss, float *grad);

@@ -104,8 +104,11 @@ struct BatchSolver {
     int nwg = 0;
     int *d_wg_off = nullptr, *d_items = nullptr;
     int *d_tlog = nullptr;            // per-instance item widths (variants with traj = 0)
-    int *d_tw_label = nullptr, *d_tw_spin = nullptr;   // and their spin labels
+    // their spin labels (kept across schedules; tw_key: the groups per gather
+    // instruction of each instance they were made for)
+    int *d_tw_label = nullptr, *d_tw_spin = nullptr;
     unsigned int *d_tw_pack = nullptr;
+    std::vector<int> tw_key;
     hipGraphExec_t graph = nullptr;
     int graph_steps = -1;
     // stats
@@ -136,13 +139,17 @@ void free_schedule(BatchSolver *b) {
     if (b->d_wg_off) (void)hipFree(b->d_wg_off);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_tlog) (void)hipFree(b->d_tlog);
+    b->d_wg_off = b->d_items = b->d_tlog = nullptr;
+    b->nwg = 0;
+}
+
+void free_labels(BatchSolver *b) {
     if (b->d_tw_label) (void)hipFree(b->d_tw_label);
     if (b->d_tw_spin) (void)hipFree(b->d_tw_spin);
     if (b->d_tw_pack) (void)hipFree(b->d_tw_pack);
-    b->d_wg_off = b->d_items = b->d_tlog = nullptr;
     b->d_tw_label = b->d_tw_spin = nullptr;
     b->d_tw_pack = nullptr;
-    b->nwg = 0;
+    b->tw_key.clear();
 }
 
 void free_state(BatchSolver *b) {
@@ -233,11 +240,12 @@ bool config_fits(const BatchSolver *b, const BatchConfig &c) {
 int build_labels(BatchSolver *b, const std::vector<int> &tl) {
     const char *env = std::getenv("GD_BATCH_RELABEL");
     const bool on = !(env && std::strcmp(env, "0") == 0);
+    std::vector<int> key(b->K);
+    for (int k = 0; k < b->K; ++k) key[k] = on ? 64 >> tl[k] : 1;
+    if (b->d_tw_label && key == b->tw_key) return GD_OK;
     std::vector<std::pair<int, int>> todo;
-    for (int k = 0; k < b->K; ++k) {
-        const int g = on ? 64 >> tl[k] : 1;
-        if (!b->labels.count({k, g})) todo.push_back({k, g});
-    }
+    for (int k = 0; k < b->K; ++k)
+        if (!b->labels.count({k, key[k]})) todo.push_back({k, key[k]});
     std::vector<std::vector<int>> got(todo.size());
     std::atomic<size_t> next{0};
     auto work = [&]() {
@@ -280,9 +288,11 @@ int build_labels(BatchSolver *b, const std::vector<int> &tl) {
             tpack[(size_t)(off + p) * 2 + 1] = relab(w[1] & 0xFFFFu) | (w[1] & 0xE0000000u);
         }
     }
+    free_labels(b);
     int rc = upload(&b->d_tw_label, label);
     if (rc == GD_OK) rc = upload(&b->d_tw_spin, spin);
     if (rc == GD_OK) rc = upload(&b->d_tw_pack, tpack);
+    if (rc == GD_OK) b->tw_key = key;
     return rc;
 }
 
@@ -660,6 +670,7 @@ void batch_destroy(BatchSolver *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     free_state(b);
+    free_labels(b);
     void *ps[] = {b->d_n, b->d_spin, b->d_state, b->d_inv_s, b->d_w, b->d_eps, b->d_h1, b->d_g, b->d_idx,
                   b->d_pack, b->d_wmag};
     for (void *p : ps)

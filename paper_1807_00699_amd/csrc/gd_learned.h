@@ -31,10 +31,8 @@ struct MlpTrainArgs {
     int M;
     float *out;                    // [M][2]
     float *sigma;                  // [K]
-    float *spin_loss;              // [M]
-    float *dO;                     // [M][2]
-    float *H1, *H2, *dH1, *dH2;    // feature-major [H][M]: activations and their gradients
-    float *partial;                // [nparts][kMlpNParam]
+    float *partial;                // [nparts][kMlpNParam] gradient partials of the training workgroups
+    double *loss_part;             // [nparts] their loss partials
     float *grad_out;               // [kMlpNParam] (nullable)
     double *loss;                  // [1]
 };

@@ -12,10 +12,12 @@
 //              iteration, Rayleigh-Ritz (8x8 cyclic Jacobi in FP64), sign
 //              fix (largest-magnitude entry of each vector positive, ties to
 //              the lowest index), then 20 features per spin.
-//  mlp_*       20 -> 64 -> 64 -> 2 ReLU network: FP32 forward, per-instance
-//              flip-invariant loss, backward, weight-gradient partials over
-//              spin chunks, fixed-order reduction fused with Adam; FP16
-//              inference on the matrix cores (FP32 accumulation).
+//  mlp_*       20 -> 64 -> 64 -> 2 ReLU network: FP32 forward (vector ALUs,
+//              the reference inference), per-instance flip-invariant loss;
+//              the training step on the FP32 matrix cores (forward,
+//              backward and weight-gradient partials of a workgroup's
+//              spins in one kernel), fixed-order reduction fused with Adam;
+//              FP16 inference on the matrix cores (FP32 accumulation).
 //  propose_k   writes psi0 = a (alpha m_i + (1 - alpha) xi) and eps_i into a
 //              batched solver's state, xi from SplitMix64.
 #include "gd_internal.h"
@@ -497,135 +499,312 @@ __global__ void __launch_bounds__(256) mlp_segment_k(const float *__restrict__ o
     if (threadIdx.x == 0) sigma[k] = v[0] <= v[1] ? 1.0f : -1.0f;
 }
 
-// backward per spin: dO, dH2, dH1 and the activations needed for weight grads
-// Activations and their gradients are written feature-major ([H][M]), so the
-// stores of a wave (consecutive spins) are contiguous.
-__global__ void __launch_bounds__(MT) mlp_backward_k(MlpTrainArgs a) {
-    __shared__ float sp[NPAR];
-    for (int q = threadIdx.x; q < NPAR; q += MT) sp[q] = a.params[q];
+// Training step on the matrix cores (v_mfma_f32_32x32x2_f32, FP32 products
+// and sums).  Each wave takes 32 spins at a time (one spin per lane column,
+// as in the FP16 inference kernel: lane l, half h = l / 32, holds rows
+// 8q + 4h + e of each 32-row block for spin l mod 32) and computes
+//   Z1^T = W1^T X^T + b1, Z2^T = W2^T relu(Z1)^T + b2   (forward),
+//   O = W3^T relu(Z2) + b3 on the vector ALUs, the per-spin loss and dO,
+//   dH2 = (W3 dO) * [Z2 > 0], dH1^T = W2 dH2^T * [Z1 > 0]   (backward),
+// the K = 2 steps of the layer products taking each lane's rows in the order
+// it holds them (the weight operand permuted to match, every product summed
+// once).  The weight gradients contract over spins, so each wave transposes
+// its tile through two LDS buffers ([spin][feature], rows padded to 65
+// words): dW2 = relu(Z1)^T dH2 and dW1 = X^T dH1 on the matrix cores, the
+// bias gradients and dW3 = relu(Z2)^T dO as column sums on the vector ALUs.
+// The weights are staged in LDS once per workgroup (the operand of a K step
+// is then one conflict-free LDS read per lane, W2 in rows of 65 words so that
+// both its row and its column order read across banks).
+// The accumulators stay in registers over all of the wave's tiles; at the
+// end the four waves of a workgroup add theirs into one partial in a fixed
+// order (partial[block][param], loss_part[block]).  Without TRAIN the kernel
+// only writes the two outputs of every spin.
+constexpr int TT = 256;           // 4 waves
+constexpr int PS = 65;            // padded row of W2 and of the transposition buffers
+// LDS: the weights (W1 [f][j], W2 [j][b] in rows of PS, b1, b2, W3), then
+// (training) the transposition buffers of the four waves
+constexpr int kWLds = F * H + H * PS + 2 * H + H * NO;
+constexpr size_t kFwdLds = (size_t)kWLds * 4;
+constexpr size_t kTrainLds = (size_t)(kWLds + 4 * 2 * 32 * PS) * 4;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool TRAIN>
+__device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
+    static_assert(H == 64 && F <= 32 && F % 2 == 0 && NO == 2, "layer shapes of the MFMA training step");
+    const float *__restrict__ p = a.params;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, c = lane & 31;
+    float *W1s = smem;                                        // W1[f][j] at f H + j
+    float *W2s = W1s + F * H;                                 // W2[j][b] at j PS + b
+    float *B1s = W2s + H * PS, *B2s = B1s + H, *W3s = B2s + H;
+    float *P = smem + kWLds + (size_t)w * 2 * 32 * PS;        // this wave's buffers
+    float *Q = P + 32 * PS;
+    for (int q = tid; q < F * H; q += TT) W1s[q] = p[OFF_W1 + q];
+    for (int q = tid; q < H * H; q += TT) W2s[(q / H) * PS + q % H] = p[OFF_W2 + q];
+    for (int q = tid; q < H; q += TT) {
+        B1s[q] = p[OFF_B1 + q];
+        B2s[q] = p[OFF_B2 + q];
+    }
+    for (int q = tid; q < H * NO; q += TT) W3s[q] = p[OFF_W3 + q];
     __syncthreads();
-    const int m = blockIdx.x * MT + threadIdx.x;
-    if (m >= a.M) return;
-    const int k = a.spin_inst[m];
-    float x[F], z1[H], z2[H], o[NO];
-    for (int f = 0; f < F; ++f) x[f] = a.X[(long long)m * F + f];
-    mlp_fwd1(sp, x, z1, z2, o);
-    const float mm = tanhf(o[0]);
-    const float cc = 1.0f / (1.0f + expf(-o[1]));
-    const float t = a.sigma[k] * a.labels[m];
-    const float y = (mm * t > 0.0f) ? 1.0f : 0.0f;
+    f32x16_t g2[4], g1[2];               // dW2 blocks (j-block, b-block), dW1 blocks (j-block)
+    float gb1 = 0.f, gb2 = 0.f, gw30 = 0.f, gw31 = 0.f, gb30 = 0.f, gb31 = 0.f;
+    double lsum = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g2[u][k] = 0.f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g1[u][k] = 0.f;
     const float invM = 1.0f / float(a.M);
-    const float d0 = 2.0f * (mm - t) * (1.0f - mm * mm) * invM;
-    const float d1 = LAMBDA_C * (cc - y) * invM;
-    // BCE(sigmoid(o1), y) in the stable logit form softplus(o1) - y o1
-    const float bce = fmaxf(o[1], 0.0f) - y * o[1] + log1pf(expf(-fabsf(o[1])));
-    a.spin_loss[m] = ((mm - t) * (mm - t) + LAMBDA_C * bce) * invM;
-    a.dO[(long long)m * NO] = d0;
-    a.dO[(long long)m * NO + 1] = d1;
-    float dh2[H];
-    for (int b = 0; b < H; ++b) {
-        const float g = d0 * sp[OFF_W3 + b * NO] + d1 * sp[OFF_W3 + b * NO + 1];
-        dh2[b] = z2[b] > 0.0f ? g : 0.0f;
-        a.H2[(long long)b * a.M + m] = fmaxf(z2[b], 0.0f);
-        a.dH2[(long long)b * a.M + m] = dh2[b];
+    const float b30 = p[OFF_B3], b31 = p[OFF_B3 + 1];
+    const int ntiles = (a.M + 31) / 32;
+    for (int t = blockIdx.x * (TT / 64) + w; t < ntiles; t += gridDim.x * (TT / 64)) {
+        const int m = t * 32 + c;
+        const bool ok = m < a.M;
+        // features 2 i + h of spin m
+        float xv[F / 2];
+        {
+            const float *xr = a.X + (long long)(ok ? m : 0) * F;
+#pragma unroll
+            for (int i = 0; i < F / 2; ++i) xv[i] = ok ? xr[2 * i + h] : 0.0f;
+        }
+        f32x16_t z1[2], z2[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z1[rb][k] = B1s[32 * rb + 8 * (k / 4) + 4 * h + k % 4];
+#pragma unroll
+            for (int i = 0; i < F / 2; ++i)
+                z1[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(W1s[(2 * i + h) * H + 32 * rb + c], xv[i],
+                                                             z1[rb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) z2[rb2][k] = B2s[32 * rb2 + 8 * (k / 4) + 4 * h + k % 4];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int j = 32 * rb + 8 * (k / 4) + 4 * h + k % 4;
+                    z2[rb2] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2s[j * PS + 32 * rb2 + c],
+                                                                  fmaxf(z1[rb][k], 0.0f), z2[rb2], 0, 0, 0);
+                }
+        }
+        float o0 = 0.0f, o1 = 0.0f;
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
+                const float r = fmaxf(z2[rb2][k], 0.0f);
+                o0 = fmaf(r, W3s[b * NO], o0);
+                o1 = fmaf(r, W3s[b * NO + 1], o1);
+            }
+        o0 += __shfl_xor(o0, 32) + b30;
+        o1 += __shfl_xor(o1, 32) + b31;
+        if constexpr (!TRAIN) {
+            if (h == 0 && ok) {
+                a.out[(long long)m * NO] = o0;
+                a.out[(long long)m * NO + 1] = o1;
+            }
+            continue;
+        } else {
+            // loss of the spin and the output gradient (zero past M)
+            float d0 = 0.0f, d1 = 0.0f;
+            if (ok) {
+                const float mm = tanhf(o0);
+                const float cc = 1.0f / (1.0f + expf(-o1));
+                const float tg = a.sigma[a.spin_inst[m]] * a.labels[m];
+                const float y = (mm * tg > 0.0f) ? 1.0f : 0.0f;
+                d0 = 2.0f * (mm - tg) * (1.0f - mm * mm) * invM;
+                d1 = LAMBDA_C * (cc - y) * invM;
+                // BCE(sigmoid(o1), y) in the stable logit form softplus(o1) - y o1
+                const float bce = fmaxf(o1, 0.0f) - y * o1 + log1pf(expf(-fabsf(o1)));
+                if (h == 0) lsum += (double)(((mm - tg) * (mm - tg) + LAMBDA_C * bce) * invM);
+            }
+            f32x16_t dh2[2], dh1[2];
+#pragma unroll
+            for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
+                    const float g = d0 * W3s[b * NO] + d1 * W3s[b * NO + 1];
+                    dh2[rb2][k] = z2[rb2][k] > 0.0f ? g : 0.0f;
+                }
+#pragma unroll
+            for (int rbj = 0; rbj < 2; ++rbj) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) dh1[rbj][k] = 0.0f;
+#pragma unroll
+                for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
+                        dh1[rbj] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2s[(32 * rbj + c) * PS + b], dh2[rb2][k],
+                                                                       dh1[rbj], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) dh1[rbj][k] = z1[rbj][k] > 0.0f ? dh1[rbj][k] : 0.0f;
+            }
+            // dW2 += relu(Z1)^T dH2 over the tile's spins; db2
+            wave_sync();
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int j = 32 * rb + 8 * (k / 4) + 4 * h + k % 4;
+                    P[c * PS + j] = fmaxf(z1[rb][k], 0.0f);
+                    Q[c * PS + j] = dh2[rb][k];
+                }
+            wave_sync();
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int row = (2 * s2 + h) * PS + c;
+                const float hj0 = P[row], hj1 = P[row + 32], db0 = Q[row], db1 = Q[row + 32];
+                g2[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(hj0, db0, g2[0], 0, 0, 0);
+                g2[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(hj0, db1, g2[1], 0, 0, 0);
+                g2[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(hj1, db0, g2[2], 0, 0, 0);
+                g2[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(hj1, db1, g2[3], 0, 0, 0);
+            }
+            for (int s = 0; s < 32; ++s) gb2 += Q[s * PS + lane];
+            // dW1 += X^T dH1 (features padded to 32 rows with zeros); db1
+            wave_sync();
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) P[c * PS + 32 * rb + 8 * (k / 4) + 4 * h + k % 4] = dh1[rb][k];
+#pragma unroll
+            for (int i = 0; i < F / 2; ++i) Q[c * PS + 2 * i + h] = xv[i];
+            for (int f = F + h; f < 32; f += 2) Q[c * PS + f] = 0.0f;
+            wave_sync();
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int row = (2 * s2 + h) * PS + c;
+                const float xf = Q[row];
+                g1[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf, P[row], g1[0], 0, 0, 0);
+                g1[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(xf, P[row + 32], g1[1], 0, 0, 0);
+            }
+            for (int s = 0; s < 32; ++s) gb1 += P[s * PS + lane];
+            // dW3 += relu(Z2)^T dO; db3
+            wave_sync();
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    P[c * PS + 32 * rb + 8 * (k / 4) + 4 * h + k % 4] = fmaxf(z2[rb][k], 0.0f);
+            if (h == 0) {
+                Q[2 * c] = d0;
+                Q[2 * c + 1] = d1;
+            }
+            wave_sync();
+            for (int s = 0; s < 32; ++s) {
+                const float hv = P[s * PS + lane];
+                gw30 = fmaf(hv, Q[2 * s], gw30);
+                gw31 = fmaf(hv, Q[2 * s + 1], gw31);
+                gb30 += Q[2 * s];
+                gb31 += Q[2 * s + 1];
+            }
+        }
     }
-    for (int j = 0; j < H; ++j) {
-        float g = 0.0f;
-        for (int b = 0; b < H; ++b) g += dh2[b] * sp[OFF_W2 + j * H + b];
-        a.H1[(long long)j * a.M + m] = fmaxf(z1[j], 0.0f);
-        a.dH1[(long long)j * a.M + m] = z1[j] > 0.0f ? g : 0.0f;
+    if constexpr (TRAIN) {
+        // the workgroup's partial: the waves add theirs in order (wave 0 writes)
+        for (int q = 1; q < 64; q <<= 1) lsum += __shfl_xor(lsum, q);
+        __syncthreads();
+        float *R = smem + kWLds;                        // NPAR floats, then 4 doubles
+        double *RL = reinterpret_cast<double *>(R + ((NPAR + 1) & ~1));
+        for (int v = 0; v < TT / 64; ++v) {
+            if (w == v) {
+                auto put = [&](int q, float val) { R[q] = v == 0 ? val : R[q] + val; };
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int j = 32 * (u >> 1) + 8 * (k / 4) + 4 * h + k % 4, b = 32 * (u & 1) + c;
+                        put(OFF_W2 + j * H + b, g2[u][k]);
+                    }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int f = 8 * (k / 4) + 4 * h + k % 4, j = 32 * u + c;
+                        if (f < F) put(OFF_W1 + f * H + j, g1[u][k]);
+                    }
+                put(OFF_B1 + lane, gb1);
+                put(OFF_B2 + lane, gb2);
+                put(OFF_W3 + lane * NO, gw30);
+                put(OFF_W3 + lane * NO + 1, gw31);
+                if (lane == 0) {
+                    put(OFF_B3, gb30);
+                    put(OFF_B3 + 1, gb31);
+                    RL[v] = lsum;
+                }
+            }
+            __syncthreads();
+        }
+        float *part = a.partial + (long long)blockIdx.x * NPAR;
+        for (int q = tid; q < NPAR; q += TT) part[q] = R[q];
+        if (tid == 0) a.loss_part[blockIdx.x] = ((RL[0] + RL[1]) + RL[2]) + RL[3];
     }
 }
 
-// weight-gradient partials: block p reduces spins [p*chunk, (p+1)*chunk) into
-// partial[p][NPAR], each parameter summed over the spins in order.  Tiles of
-// WG_TILE spins are staged in LDS; register blocks per thread: a 4 x 4 block
-// of W2 (16 products per 8 LDS reads), 5 entries of one W1 column, and one of
-// B1 / B2 / W3 (plus B3 for two threads).
-constexpr int WG_TILE = 32;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-static_assert(MT == 256 && H == 64 && F == 20 && NO == 2, "thread map of mlp_wgrad_k");
-__global__ void __launch_bounds__(MT) mlp_wgrad_k(MlpTrainArgs a, int chunk) {
-    // rows padded to H + 4 floats: the transposing LDS stores (consecutive
-    // spins) spread over banks, the 16-byte reads stay aligned
-    constexpr int HP = H + 4;
-    __shared__ __attribute__((aligned(16))) float sX[WG_TILE][F], sH1[WG_TILE][HP], sH2[WG_TILE][HP];
-    __shared__ __attribute__((aligned(16))) float sD1[WG_TILE][HP], sD2[WG_TILE][HP], sDO[WG_TILE][NO];
-    const int t = threadIdx.x;
-    const int j0 = (t / 16) * 4, b0 = (t % 16) * 4;    // W2 block
-    const int wj = t % 64, f0 = (t / 64) * 5;           // W1: rows f0..f0+4 of column wj
-    float w2[4][4], w1[5], one = 0.0f, b3 = 0.0f;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) w2[u][v] = 0.0f;
-#pragma unroll
-    for (int u = 0; u < 5; ++u) w1[u] = 0.0f;
-    const int m0 = blockIdx.x * chunk;
-    const int m1 = min(a.M, m0 + chunk);
-    for (int r0 = m0; r0 < m1; r0 += WG_TILE) {
-        const int cnt = min(WG_TILE, m1 - r0);
-        for (int q = t; q < WG_TILE * H; q += MT) {
-            const int r = q % WG_TILE, c = q / WG_TILE;     // feature-major sources
-            const bool in = r < cnt;
-            const long long mc = (long long)c * a.M + r0 + r;
-            sH1[r][c] = in ? a.H1[mc] : 0.0f;
-            sH2[r][c] = in ? a.H2[mc] : 0.0f;
-            sD1[r][c] = in ? a.dH1[mc] : 0.0f;
-            sD2[r][c] = in ? a.dH2[mc] : 0.0f;
-        }
-        for (int q = t; q < WG_TILE * F; q += MT) {
-            const int r = q / F, c = q % F;
-            sX[r][c] = r < cnt ? a.X[(long long)(r0 + r) * F + c] : 0.0f;
-        }
-        if (t < WG_TILE * NO) {
-            const int r = t / NO, c = t % NO;
-            sDO[r][c] = r < cnt ? a.dO[(long long)(r0 + r) * NO + c] : 0.0f;
-        }
-        __syncthreads();
-        for (int r = 0; r < WG_TILE; ++r) {
-            const f32x4 h1 = *reinterpret_cast<const f32x4 *>(&sH1[r][j0]);
-            const f32x4 d2 = *reinterpret_cast<const f32x4 *>(&sD2[r][b0]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) w2[u][v] = fmaf(h1[u], d2[v], w2[u][v]);
-            const float d1 = sD1[r][wj];
-#pragma unroll
-            for (int u = 0; u < 5; ++u) w1[u] = fmaf(sX[r][f0 + u], d1, w1[u]);
-            if (t < 64) one += sD1[r][t];                                      // B1
-            else if (t < 128) one += sD2[r][t - 64];                           // B2
-            else one = fmaf(sH2[r][(t - 128) / 2], sDO[r][(t - 128) % 2], one);  // W3
-            if (t < NO) b3 += sDO[r][t];                                       // B3
-        }
-        __syncthreads();
-    }
-    float *part = a.partial + (long long)blockIdx.x * NPAR;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) part[OFF_W2 + (j0 + u) * H + b0 + v] = w2[u][v];
-#pragma unroll
-    for (int u = 0; u < 5; ++u) part[OFF_W1 + (f0 + u) * H + wj] = w1[u];
-    if (t < 64) part[OFF_B1 + t] = one;
-    else if (t < 128) part[OFF_B2 + t - 64] = one;
-    else part[OFF_W3 + (t - 128)] = one;
-    if (t < NO) part[OFF_B3 + t] = b3;
+// the training step: one wave per SIMD (its accumulators and operands take
+// the whole register file)
+__global__ void __launch_bounds__(TT) mlp_train_mfma_k(MlpTrainArgs a) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    mlp_mfma32<true>(a, smem);
 }
 
-// fixed-order sum of the partials, then Adam; loss = fixed-order sum of spin losses
-__global__ void __launch_bounds__(MT) mlp_adam_k(MlpTrainArgs a, int nparts, float lr, int step) {
-    const int q = blockIdx.x * MT + threadIdx.x;
+// the forward pass alone (outputs for the flip alignment)
+__global__ void __launch_bounds__(TT) mlp_forward_mfma32_k(MlpTrainArgs a) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    mlp_mfma32<false>(a, smem);
+}
+
+// Fixed-order sum of the workgroup partials, then Adam.  A workgroup of
+// 1024 threads (16 waves) takes 64 parameters: wave v sums its sixteenth of
+// the partials (eight interleaved running sums, loads in flight), the waves'
+// sums are added in wave order.  The last workgroup adds the loss partials.
+constexpr int AT = 1024, AP = 64;
+__global__ void __launch_bounds__(AT) mlp_adam_k(MlpTrainArgs a, int nparts, float lr, int step) {
+    __shared__ float ws[AT / 64][AP];
+    __shared__ double ls[AT];
+    const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+    if (blockIdx.x == gridDim.x - 1) {
+        double x = 0.0;
+        for (int q = threadIdx.x; q < nparts; q += AT) x += a.loss_part[q];
+        ls[threadIdx.x] = x;
+        __syncthreads();
+        for (int s = AT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) ls[threadIdx.x] += ls[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.loss[0] = ls[0];
+        return;
+    }
+    const int q = blockIdx.x * AP + lane;
+    const int per = (nparts + AT / 64 - 1) / (AT / 64);
+    const int p0 = min(nparts, v * per), p1 = min(nparts, p0 + per);
+    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (q < NPAR) {
-        // eight interleaved running sums (independent loads in flight),
-        // combined in a fixed order
-        float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        int pp = 0;
-        for (; pp + 8 <= nparts; pp += 8)
+        int pp = p0;
+        for (; pp + 8 <= p1; pp += 8)
 #pragma unroll
             for (int u = 0; u < 8; ++u) s8[u] += a.partial[(long long)(pp + u) * NPAR + q];
-        for (; pp < nparts; ++pp) s8[pp & 7] += a.partial[(long long)pp * NPAR + q];
-        const float g = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+        for (; pp < p1; ++pp) s8[(pp - p0) & 7] += a.partial[(long long)pp * NPAR + q];
+    }
+    ws[v][lane] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    __syncthreads();
+    if (v == 0 && q < NPAR) {
+        float g = 0.0f;
+        for (int u = 0; u < AT / 64; ++u) g += ws[u][lane];
         if (a.grad_out) a.grad_out[q] = g;
         if (lr > 0.0f) {
             const float b1 = 0.9f, b2 = 0.999f;
@@ -638,21 +817,6 @@ __global__ void __launch_bounds__(MT) mlp_adam_k(MlpTrainArgs a, int nparts, flo
             a.params[q] -= lr * mh / (sqrtf(vh) + 1e-8f);
         }
     }
-}
-
-// loss = sum of the per-spin terms, fixed order (strided per thread, then a tree)
-__global__ void __launch_bounds__(1024) mlp_loss_k(const float *__restrict__ spin_loss, int M,
-                                                  double *__restrict__ loss) {
-    __shared__ double s[1024];
-    double v = 0.0;
-    for (int m = threadIdx.x; m < M; m += 1024) v += spin_loss[m];
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[0] = s[0];
 }
 
 __global__ void propose_k(ProposeArgs a) {
@@ -712,14 +876,17 @@ hipError_t launch_mlp_forward(const float *params, const float *X, float *out, i
 
 hipError_t launch_mlp_train_step(const MlpTrainArgs &a, int K, int nparts, float lr, int step,
                                  hipStream_t st) {
-    const int g = (a.M + MT - 1) / MT;
-    mlp_forward_k<<<g, MT, 0, st>>>(a.params, a.X, a.out, a.M);
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_train_mfma_k),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       int(kTrainLds));
+    if (attr != hipSuccess) return attr;
+    const int ntiles = (a.M + 31) / 32;
+    const int gw = (ntiles + TT / 64 - 1) / (TT / 64);
+    mlp_forward_mfma32_k<<<std::min(gw, 512), TT, kFwdLds, st>>>(a);
     mlp_segment_k<<<K, 256, 0, st>>>(a.out, a.labels, a.seg, a.sigma, nullptr);
-    mlp_backward_k<<<g, MT, 0, st>>>(a);
-    const int chunk = (a.M + nparts - 1) / nparts;
-    mlp_wgrad_k<<<nparts, MT, 0, st>>>(a, chunk);
-    mlp_adam_k<<<(NPAR + MT - 1) / MT, MT, 0, st>>>(a, nparts, lr, step);
-    mlp_loss_k<<<1, 1024, 0, st>>>(a.spin_loss, a.M, a.loss);
+    const int np = std::max(1, std::min(nparts, gw));
+    mlp_train_mfma_k<<<np, TT, kTrainLds, st>>>(a);
+    mlp_adam_k<<<(NPAR + AP - 1) / AP + 1, AT, 0, st>>>(a, np, lr, step);
     return hipGetLastError();
 }
 

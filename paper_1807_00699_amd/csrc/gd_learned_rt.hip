@@ -26,19 +26,20 @@ struct gd_mlp {
     int step = 0;
     // workspace for M rows
     int cap = 0;
-    float *out = nullptr, *spin_loss = nullptr, *dO = nullptr, *H1 = nullptr, *H2 = nullptr;
-    float *dH1 = nullptr, *dH2 = nullptr, *X = nullptr, *labels = nullptr;
+    float *out = nullptr, *X = nullptr, *labels = nullptr;
     int *spin_inst = nullptr;
     int capK = 0;
     float *sigma = nullptr;
     int *seg = nullptr;
     float *partial = nullptr, *grad = nullptr;
-    double *loss = nullptr;
+    double *loss_part = nullptr, *loss = nullptr;
 };
 
 namespace {
 
-constexpr int kParts = 512;   // weight-gradient partials (workgroups)
+// workgroups of the training step, each writing one gradient partial: one
+// per compute unit of the GPU (a workgroup's LDS fills half a CU)
+constexpr int kParts = 256;
 
 #define GD_TRY(expr)                                                                     \
     do {                                                                                 \
@@ -54,10 +55,10 @@ hipError_t dm(T **p, size_t n) {
 }
 
 void free_ws(gd_mlp *m) {
-    void *ps[] = {m->out, m->spin_loss, m->dO, m->H1, m->H2, m->dH1, m->dH2, m->X, m->labels, m->spin_inst};
+    void *ps[] = {m->out, m->X, m->labels, m->spin_inst};
     for (void *p : ps)
         if (p) (void)hipFree(p);
-    m->out = m->spin_loss = m->dO = m->H1 = m->H2 = m->dH1 = m->dH2 = m->X = m->labels = nullptr;
+    m->out = m->X = m->labels = nullptr;
     m->spin_inst = nullptr;
     m->cap = 0;
 }
@@ -65,10 +66,8 @@ void free_ws(gd_mlp *m) {
 int ensure_ws(gd_mlp *m, int M, int K) {
     if (M > m->cap) {
         free_ws(m);
-        const size_t H = kMlpH;
-        if (dm(&m->out, (size_t)M * 2) || dm(&m->spin_loss, M) || dm(&m->dO, (size_t)M * 2) ||
-            dm(&m->H1, M * H) || dm(&m->H2, M * H) || dm(&m->dH1, M * H) || dm(&m->dH2, M * H) ||
-            dm(&m->X, (size_t)M * kMlpF) || dm(&m->labels, M) || dm(&m->spin_inst, M)) {
+        if (dm(&m->out, (size_t)M * 2) || dm(&m->X, (size_t)M * kMlpF) || dm(&m->labels, M) ||
+            dm(&m->spin_inst, M)) {
             free_ws(m);
             return gd_fail(GD_E_OOM, "MLP workspace allocation failed");
         }
@@ -121,7 +120,8 @@ int gd_mlp_create(gd_mlp **out, const float *params, uint64_t seed, uint32_t fla
     if (!m) return gd_fail(GD_E_OOM, "host allocation failed");
     m->flags = flags;
     if (dm(&m->params, kMlpNParam) || dm(&m->mom, kMlpNParam) || dm(&m->vel, kMlpNParam) ||
-        dm(&m->partial, (size_t)kParts * kMlpNParam) || dm(&m->grad, kMlpNParam) || dm(&m->loss, 1)) {
+        dm(&m->partial, (size_t)kParts * kMlpNParam) || dm(&m->loss_part, kParts) || dm(&m->grad, kMlpNParam) ||
+        dm(&m->loss, 1)) {
         gd_mlp_destroy(m);
         return gd_fail(GD_E_OOM, "MLP allocation failed");
     }
@@ -150,7 +150,7 @@ void gd_mlp_destroy(gd_mlp *m) {
     if (!m) return;
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     free_ws(m);
-    void *ps[] = {m->params, m->mom, m->vel, m->partial, m->grad, m->loss, m->sigma, m->seg};
+    void *ps[] = {m->params, m->mom, m->vel, m->partial, m->grad, m->loss_part, m->loss, m->sigma, m->seg};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (m->stream) (void)hipStreamDestroy(m->stream);
@@ -229,13 +229,8 @@ int gd_mlp_train_step(gd_mlp *m, int32_t M, const float *X, const float *labels,
     a.M = M;
     a.out = m->out;
     a.sigma = m->sigma;
-    a.spin_loss = m->spin_loss;
-    a.dO = m->dO;
-    a.H1 = m->H1;
-    a.H2 = m->H2;
-    a.dH1 = m->dH1;
-    a.dH2 = m->dH2;
     a.partial = m->partial;
+    a.loss_part = m->loss_part;
     a.grad_out = m->grad;
     a.loss = m->loss;
     GD_TRY(launch_mlp_train_step(a, K, kParts, lr, std::max(m->step, 1), m->stream));
