@@ -375,13 +375,16 @@ __global__ void __launch_bounds__(64 * W) gemv_step_k(DenseStepArgs a) {
 // K range of one row group}.  Rows per workgroup (W / KS) x RPW are 16 or 32
 // (the row tile of the energy partials); 16 puts 256 workgroups, one per CU,
 // on N = 4096, and KS > 1 gives each CU 2 or 4 times the waves (and loads in
-// flight) at the price of one more fixed-order sum through LDS.
+// flight) at the price of one more fixed-order sum through LDS.  Variants 5
+// and 6 keep 128 KiB of J in flight per CU on N = 4096 (twice the others).
 #define GD_GEMV_VARIANTS(X)    \
     X(0, 4, 4, 8192, 2, 1)     \
     X(1, 4, 4, 8192, 4, 1)     \
     X(2, 8, 4, 8192, 2, 1)     \
     X(3, 8, 4, 8192, 2, 2)     \
-    X(4, 16, 4, 8192, 1, 4)
+    X(4, 16, 4, 8192, 1, 4)    \
+    X(5, 8, 4, 8192, 4, 2)     \
+    X(6, 16, 4, 8192, 2, 4)
 
 template <int MODE, bool CPLX, int JK, int OPT, int CM, int W, int RPW, int BUD, int U, int KS>
 hipError_t launch_one(const DenseStepArgs &a, hipStream_t st) {
