@@ -81,6 +81,21 @@ def test_mlp_forward_gradient_and_adam_match_oracle():
         assert np.abs(m.params - p1)[big].max() < 1e-6
 
 
+@pytest.mark.parametrize("M,K", [(7, 2), (33, 3), (64, 1)])
+def test_mlp_gradient_on_small_and_ragged_batches(M, K):
+    """The training kernel takes 32 rows per wave: a batch smaller than one
+    tile, one row past a tile, and exactly two tiles."""
+    p, X, lab, seg = _toy(seed=M, M=M, K=K)
+    with gd.MLP(p) as m:
+        loss, g = m.train_step(X, lab, seg, 0.0, want_grad=True)
+        Lo, go = L.loss_and_grad(p.astype(np.float64), X.astype(np.float64), lab.astype(np.float64), seg)
+        assert loss == pytest.approx(Lo, rel=1e-5)
+        assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+        # the same bits again (fixed-order sums)
+        loss2, g2 = m.train_step(X, lab, seg, 0.0, want_grad=True)
+        assert loss2 == loss and np.array_equal(g2, g)
+
+
 def test_mlp_device_pointer_calls_match_host_calls():
     """GD_F_DEVICE_PTRS handle (device X, labels, outputs and parameters):
     the same outputs, losses and trained parameters as the host handle."""
