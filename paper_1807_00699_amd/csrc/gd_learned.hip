@@ -565,16 +565,30 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
     const float invM = 1.0f / float(a.M);
     const float b30 = p[OFF_B3], b31 = p[OFF_B3 + 1];
     const int ntiles = (a.M + 31) / 32;
-    for (int t = blockIdx.x * (TT / 64) + w; t < ntiles; t += gridDim.x * (TT / 64)) {
+    const int tstride = gridDim.x * (TT / 64);
+    // features 2 i + h of spin 32 t + c (zeros past M); the next tile's are
+    // loaded while the current one is multiplied
+    auto load_x = [&](int t, float (&xd)[F / 2]) {
+        const int m = t * 32 + c;
+        const bool ok = t < ntiles && m < a.M;
+        const float *xr = a.X + (long long)(ok ? m : 0) * F;
+#pragma unroll
+        for (int i = 0; i < F / 2; ++i) xd[i] = ok ? xr[2 * i + h] : 0.0f;
+    };
+    float xn[F / 2];
+    int t = blockIdx.x * (TT / 64) + w;
+    load_x(t, xn);
+    for (; t < ntiles; t += tstride) {
         const int m = t * 32 + c;
         const bool ok = m < a.M;
-        // features 2 i + h of spin m
         float xv[F / 2];
-        {
-            const float *xr = a.X + (long long)(ok ? m : 0) * F;
 #pragma unroll
-            for (int i = 0; i < F / 2; ++i) xv[i] = ok ? xr[2 * i + h] : 0.0f;
-        }
+        for (int i = 0; i < F / 2; ++i) xv[i] = xn[i];
+        load_x(t + tstride, xn);
+        // the spin's target sigma_k s_i, loaded before the products
+        float tg = 0.0f;
+        if constexpr (TRAIN)
+            if (ok) tg = a.sigma[a.spin_inst[m]] * a.labels[m];
         f32x16_t z1[2], z2[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
@@ -622,7 +636,6 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
             if (ok) {
                 const float mm = tanhf(o0);
                 const float cc = 1.0f / (1.0f + expf(-o1));
-                const float tg = a.sigma[a.spin_inst[m]] * a.labels[m];
                 const float y = (mm * tg > 0.0f) ? 1.0f : 0.0f;
                 d0 = 2.0f * (mm - tg) * (1.0f - mm * mm) * invM;
                 d1 = LAMBDA_C * (cc - y) * invM;
