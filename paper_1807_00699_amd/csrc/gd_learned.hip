@@ -585,6 +585,13 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
 #pragma unroll
         for (int i = 0; i < F / 2; ++i) xv[i] = xn[i];
         load_x(t + tstride, xn);
+        // the forward pass alone reads the weights from LDS in every tile (an
+        // offset the compiler cannot see through keeps them out of the
+        // registers, so that two waves fit a SIMD); the training step keeps
+        // them in registers
+        int wo = 0;
+        if constexpr (!TRAIN) __asm__ volatile("" : "+v"(wo));
+        const float *W1t = W1s + wo, *W2t = W2s + wo, *B1t = B1s + wo, *B2t = B2s + wo, *W3t = W3s + wo;
         // the spin's target sigma_k s_i, loaded before the products
         float tg = 0.0f;
         if constexpr (TRAIN)
@@ -593,22 +600,22 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) z1[rb][k] = B1s[32 * rb + 8 * (k / 4) + 4 * h + k % 4];
+            for (int k = 0; k < 16; ++k) z1[rb][k] = B1t[32 * rb + 8 * (k / 4) + 4 * h + k % 4];
 #pragma unroll
             for (int i = 0; i < F / 2; ++i)
-                z1[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(W1s[(2 * i + h) * H + 32 * rb + c], xv[i],
+                z1[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(W1t[(2 * i + h) * H + 32 * rb + c], xv[i],
                                                              z1[rb], 0, 0, 0);
         }
 #pragma unroll
         for (int rb2 = 0; rb2 < 2; ++rb2) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) z2[rb2][k] = B2s[32 * rb2 + 8 * (k / 4) + 4 * h + k % 4];
+            for (int k = 0; k < 16; ++k) z2[rb2][k] = B2t[32 * rb2 + 8 * (k / 4) + 4 * h + k % 4];
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     const int j = 32 * rb + 8 * (k / 4) + 4 * h + k % 4;
-                    z2[rb2] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2s[j * PS + 32 * rb2 + c],
+                    z2[rb2] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2t[j * PS + 32 * rb2 + c],
                                                                   fmaxf(z1[rb][k], 0.0f), z2[rb2], 0, 0, 0);
                 }
         }
@@ -619,8 +626,8 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
             for (int k = 0; k < 16; ++k) {
                 const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
                 const float r = fmaxf(z2[rb2][k], 0.0f);
-                o0 = fmaf(r, W3s[b * NO], o0);
-                o1 = fmaf(r, W3s[b * NO + 1], o1);
+                o0 = fmaf(r, W3t[b * NO], o0);
+                o1 = fmaf(r, W3t[b * NO + 1], o1);
             }
         o0 += __shfl_xor(o0, 32) + b30;
         o1 += __shfl_xor(o1, 32) + b31;
@@ -649,7 +656,7 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
-                    const float g = d0 * W3s[b * NO] + d1 * W3s[b * NO + 1];
+                    const float g = d0 * W3t[b * NO] + d1 * W3t[b * NO + 1];
                     dh2[rb2][k] = z2[rb2][k] > 0.0f ? g : 0.0f;
                 }
 #pragma unroll
@@ -661,7 +668,7 @@ __device__ __forceinline__ void mlp_mfma32(const MlpTrainArgs &a, float *smem) {
 #pragma unroll
                     for (int k = 0; k < 16; ++k) {
                         const int b = 32 * rb2 + 8 * (k / 4) + 4 * h + k % 4;
-                        dh1[rbj] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2s[(32 * rbj + c) * PS + b], dh2[rb2][k],
+                        dh1[rbj] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2t[(32 * rbj + c) * PS + b], dh2[rb2][k],
                                                                        dh1[rbj], 0, 0, 0);
                     }
 #pragma unroll
@@ -775,8 +782,9 @@ __global__ void __launch_bounds__(TT) mlp_train_mfma_k(MlpTrainArgs a) {
     mlp_mfma32<true>(a, smem);
 }
 
-// the forward pass alone (outputs for the flip alignment)
-__global__ void __launch_bounds__(TT) mlp_forward_mfma32_k(MlpTrainArgs a) {
+// the forward pass alone (outputs for the flip alignment): at least two
+// waves per SIMD (the weights are re-read from LDS in every tile)
+__global__ void __launch_bounds__(TT, 2) mlp_forward_mfma32_k(MlpTrainArgs a) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     mlp_mfma32<false>(a, smem);
 }
@@ -895,7 +903,7 @@ hipError_t launch_mlp_train_step(const MlpTrainArgs &a, int K, int nparts, float
     if (attr != hipSuccess) return attr;
     const int ntiles = (a.M + 31) / 32;
     const int gw = (ntiles + TT / 64 - 1) / (TT / 64);
-    mlp_forward_mfma32_k<<<std::min(gw, 512), TT, kFwdLds, st>>>(a);
+    mlp_forward_mfma32_k<<<std::min(gw, 2048), TT, kFwdLds, st>>>(a);
     mlp_segment_k<<<K, 256, 0, st>>>(a.out, a.labels, a.seg, a.sigma, nullptr);
     const int np = std::max(1, std::min(nparts, gw));
     mlp_train_mfma_k<<<np, TT, kTrainLds, st>>>(a);

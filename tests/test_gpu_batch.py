@@ -136,6 +136,33 @@ def test_batch_independence_variants_and_graph_chunks_bitwise():
     assert np.array_equal(alone[0], ref[0][off:off + sizes[k] * R])
 
 
+def test_relabeled_gathers_give_the_same_bits():
+    """The per-instance-width variants relabel each instance's spins for
+    their LDS gathers; with GD_BATCH_RELABEL=0 they keep the given order.
+    Same states, gains and energies either way (sizes from one-row items to
+    items of two trajectories, where the relabeling has most to do)."""
+    sizes = [40, 120, 500, 1000, 2000]
+    R = 32
+    insts, _ = _instances(sizes, 41)
+    x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 41)])
+    outs = []
+    for relabel in ("1", "0"):
+        os.environ["GD_BATCH_CONFIG"] = "18"
+        if relabel == "0":
+            os.environ["GD_BATCH_RELABEL"] = "0"
+        try:
+            with gd.BatchSolver(insts, check_interval=30) as B:
+                B.set_init(R, x0)
+                B.run(90)
+                outs.append(B.state() + B.energy())
+        finally:
+            del os.environ["GD_BATCH_CONFIG"]
+            os.environ.pop("GD_BATCH_RELABEL", None)
+    a, b = outs
+    for q in (0, 1, 3, 4):
+        assert np.array_equal(a[q], b[q]), q
+
+
 def test_batch_gauge_symmetry_and_dense_input():
     n, R = 120, 8
     e, w, s = I.regular3_maxcut(n, 33)
