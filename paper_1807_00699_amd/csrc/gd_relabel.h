@@ -5,9 +5,10 @@
 // consecutive words, row p at word p T, and one wave instruction gathers,
 // for the G = 64 / T spins of G consecutive labels, the rows of their d-th
 // neighbours.  The LDS has 64 banks of one word, so row p covers the banks of
-// residue p mod G, and it serves a 64-lane read in two passes of 32 lanes,
-// i.e. of G / 2 rows; two different rows of one residue in a pass are read
-// one after the other.  The relabeling permutes the spins so that in every
+// residue p mod G.  The model used here, which measurement favoured over
+// whole 64-lane blocks, is that a 64-lane read is served in two passes of
+// 32 lanes, i.e. of G / 2 rows, and that two different rows of one residue
+// in a pass are read one after the other.  The relabeling permutes the spins so that in every
 // block of `bs` consecutive labels (the rows of one pass: bs = G / 2) the
 // d-th neighbours of the block's spins have different residues, for each d,
 // as far as a local search gets.  Nothing numerical changes: a spin keeps its
