@@ -431,7 +431,9 @@ batch_ell_tw(BatchArgs a) {
     X(15, 1024, 8, true)        \
     X(16, 1024, 8, false)       \
     X(17, 1024, 4, true)        \
-    X(18, 512, 8, true)
+    X(18, 512, 8, true)         \
+    X(19, 512, 6, true)         \
+    X(20, 256, 8, true)
 
 constexpr int kBatchCfg[][6] = {
 #define GD_ROW(id, t, nt, e, pk, uni, db) {t, nt, e, pk, uni, db},

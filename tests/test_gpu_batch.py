@@ -101,12 +101,13 @@ def test_batch_independence_variants_and_graph_chunks_bitwise():
     x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 20)])
     ref = None
     # 0-6: couplings in LDS; 7-14: neighbours in registers (packed form),
-    # 11-12 uniform rates, 12-14 double-buffered amplitudes; 15-18: item width
+    # 11-12 uniform rates, 12-14 double-buffered amplitudes; 15-20: item width
     # chosen per instance (all 16 trajectories in one item at 8192
     # spin-trajectories per item, 15-16; the 258-spin instance in items of 8
-    # at 4096, 17-18), the state staged through LDS; the energies of the
-    # final state (a zero-step launch of the same variant) too
-    for cfg in ("0", "1", "2", "6", "7", "8", "9", "10", "11", "12", "13", "14", "15", "16", "17", "18"):
+    # at 4096, 17-18, and at 3072 and 2048, 19-20), spins relabeled, the
+    # state staged through LDS; the energies of the final state (a zero-step
+    # launch of the same variant) too
+    for cfg in ("0", "1", "2", "6", "7", "8", "9", "10", "11", "12", "13", "14", "15", "16", "17", "18", "19", "20"):
         os.environ["GD_BATCH_CONFIG"] = cfg
         try:
             with gd.BatchSolver(insts, check_interval=25) as B:
