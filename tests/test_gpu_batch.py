@@ -287,6 +287,39 @@ def test_batch_deferred_best_matches_per_check_readback():
     assert all(np.all(np.isfinite(s[0])) for s in out[0])
 
 
+def test_missing_couplings_pad_to_the_zero_row():
+    """Instances of degree 1-3 (3-regular graphs with every fifth edge
+    removed): the packed, relabeled variants point a missing coupling at the
+    instance's zero row; they agree bit for bit with the ELL variant 0 and
+    their readout's energies are the oracle's."""
+    sizes = [60, 300, 1500]
+    R = 16
+    insts, dense = [], []
+    for k, n in enumerate(sizes):
+        e, w, _ = I.regular3_maxcut(n, 70 + k)
+        keep = np.arange(e.shape[0]) % 5 != 0
+        insts.append(I.edges_to_csr(n, e[keep], w[keep]))
+        dense.append(I.edges_to_dense(n, e[keep], w[keep]))
+        assert np.diff(insts[-1]["row_ptr"]).min() < 3
+    x0 = np.concatenate([x.ravel() for x in _psi0(sizes, R, 70)])
+    outs = {}
+    for cfg in ("0", "18", "20"):
+        os.environ["GD_BATCH_CONFIG"] = cfg
+        try:
+            with gd.BatchSolver(insts, check_interval=40) as B:
+                B.set_init(R, x0)
+                B.run(120)
+                outs[cfg] = B.state() + B.energy()
+                sp = B.split(B.spins())
+        finally:
+            del os.environ["GD_BATCH_CONFIG"]
+        for k, J in enumerate(dense):
+            assert np.array_equal(outs[cfg][3][k], O.energy_ising(J, sp[k]).astype(np.float64)), (cfg, k)
+    for cfg in ("18", "20"):
+        for q in (0, 1, 3):
+            assert np.array_equal(outs[cfg][q], outs["0"][q]), (cfg, q)
+
+
 def test_packed_variants_need_one_coupling_magnitude_per_instance():
     """A batch whose instance mixes coupling magnitudes (+-1 and +-2) has no
     packed form: pinning a packed variant is refused, a general one runs and
