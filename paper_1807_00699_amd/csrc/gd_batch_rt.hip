@@ -248,29 +248,41 @@ int build_labels(BatchSolver *b, const std::vector<int> &tl) {
         if (!b->labels.count({k, key[k]})) todo.push_back({k, key[k]});
     std::vector<std::vector<int>> got(todo.size());
     std::atomic<size_t> next{0};
+    std::atomic<bool> failed{false};
     auto work = [&]() {
         for (size_t q; (q = next.fetch_add(1)) < todo.size();) {
-            const int k = todo[q].first, g = todo[q].second, n = b->n[k];
-            std::vector<int> nb((size_t)3 * n);
-            for (int i = 0; i < n; ++i) {
-                const unsigned int *w = &b->pack_host[(size_t)(b->spin_off[k] + i) * 2];
-                nb[3 * i] = int(w[0] & 0xFFFFu);
-                nb[3 * i + 1] = int(w[0] >> 16);
-                nb[3 * i + 2] = int(w[1] & 0xFFFFu);
+            // an exception must not leave a worker thread (host memory)
+            try {
+                const int k = todo[q].first, g = todo[q].second, n = b->n[k];
+                std::vector<int> nb((size_t)3 * n);
+                for (int i = 0; i < n; ++i) {
+                    const unsigned int *w = &b->pack_host[(size_t)(b->spin_off[k] + i) * 2];
+                    nb[3 * i] = int(w[0] & 0xFFFFu);
+                    nb[3 * i + 1] = int(w[0] >> 16);
+                    nb[3 * i + 2] = int(w[1] & 0xFFFFu);
+                }
+                // blocks of G / 2 labels: the rows of one 32-lane pass of a gather
+                got[q] = gather_relabel(n, nb, g, g / 2, uint64_t(k) * 64 + uint64_t(g), 12LL * n).label;
+            } catch (...) {
+                failed = true;
             }
-            // blocks of G / 2 labels: the rows of one 32-lane pass of a gather
-            got[q] = gather_relabel(n, nb, g, g / 2, uint64_t(k) * 64 + uint64_t(g), 12LL * n).label;
         }
     };
+    // up to 15 helper threads; the calling thread works too, and takes what
+    // is left when no thread can be started
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     const size_t nth = std::min<size_t>(hw, todo.size());
-    if (nth > 1) {
-        std::vector<std::thread> pool;
-        for (size_t t = 0; t < nth; ++t) pool.emplace_back(work);
-        for (auto &t : pool) t.join();
-    } else {
-        work();
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nth; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (...) {
+            break;
+        }
     }
+    work();
+    for (auto &t : pool) t.join();
+    if (failed) return gd_fail(GD_E_OOM, "spin relabeling ran out of host memory");
     for (size_t q = 0; q < todo.size(); ++q) b->labels[todo[q]] = std::move(got[q]);
     std::vector<int> label(b->total), spin(b->total);
     std::vector<unsigned int> tpack((size_t)b->total * 2);
