@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--val", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--label-steps", type=int, default=3000)
-    ap.add_argument("--out", default="gpurun_out")
+    ap.add_argument("--out", default="proposal_out", help="folder for the weights, the log and the validation record")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     logf = open(os.path.join(args.out, "train_proposal.log"), "w")
