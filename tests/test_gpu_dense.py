@@ -37,7 +37,7 @@ def oracle_scale(J, S):
 
 
 def _parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, g=None, eps=0.1, R_sub=None,
-                oracle_threads=None, strict=False, max_used=None, **kw):
+                oracle_threads=None, strict=False, max_used=None, min_strict=0.9, **kw):
     n = J.shape[0]
     mdl = gd.GD_ISING if model == "ising" else gd.GD_XY
     okw = {k: v for k, v in kw.items() if k in ("rho_th", "gamma_c")}
@@ -66,7 +66,8 @@ def _parity_run(J, psi0, model, integrator, dt, steps_list=SNAP, g=None, eps=0.1
             eg = _rel(gm[sub], og)
             worst.append((st, float(ep.max()), float(eg.max())))
             floor = None if strict else fl.floor(op, og)
-            P.check(ep, eg, floor, strict=strict, max_used=max_used, label=f"{model} n={n} step {st}")
+            P.check(ep, eg, floor, strict=strict, max_used=max_used, min_strict=min_strict,
+                    label=f"{model} n={n} step {st}")
         print("worst per snapshot (step, psi, gamma):", worst)
         return S, worst
 
@@ -112,6 +113,24 @@ def test_xy1024_full_size_sampled_parity():
     psi0 = I.psi0_complex(n, R, 1)
     sub = [0, 1, 63, 64, 511, 777, 1000, 1023]
     _parity_run(J, psi0, "xy", gd.GD_RK4, 0.02, R_sub=sub, steps_list=(1, 50, 200), strict=True)
+
+
+def test_ising4096_full_size_sampled_parity():
+    """N = 4096, R = 4096, Euler dt = 0.05, couplings in {-1, 0, +1} at
+    density 0.5 (the Ising workload of the default bench line, FP32 form, in
+    the tile the autotuner picks for it), checked on sampled trajectories.
+    At this size the dynamics amplify FP32 rounding by about 3x every 25
+    steps: the oracle's own float32 run stays within 7e-6 of the FP64 run up
+    to step 125 and leaves 1e-4 near step 200 (2.3e-4 on trajectory 4095).
+    Steps 1-125 are therefore held to 1e-4 outright, step 200 to the floor
+    rule with at most two of the eight trajectories needing it."""
+    n, R = 4096, 4096
+    J = I.sparse_pm1(n, 1)
+    psi0 = I.psi0_real(n, R, 1)
+    sub = [0, 1, 736, 1365, 2048, 2730, 4094, 4095]
+    _parity_run(J, psi0, "ising", gd.GD_EULER, 0.05, R_sub=sub, steps_list=(1, 50, 125), strict=True)
+    _parity_run(J, psi0, "ising", gd.GD_EULER, 0.05, R_sub=sub, steps_list=(200,), max_used=2,
+                min_strict=0.75)
 
 
 # every FP32 coupling-kernel variant of the runtime's table (tile shapes, K
