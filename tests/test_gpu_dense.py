@@ -6,7 +6,8 @@ relative error <= 1e-4 of psi and gamma at steps {1, 10, 50, 100, 200}; a
 trajectory whose FP32 rounding the dynamics amplify (the oracle's own float32
 run shows it) may be held to 4x that floor, and every check reports how many
 needed it.  The Ising N = 64, R = 100 workload and the sampled XY N = 1024,
-R = 1024 workload are held to 1e-4 outright.  The coupling scale s is the
+R = 1024 workload are held to 1e-4 outright, the sampled Ising N = 4096,
+R = 4096 workload through step 125.  The coupling scale s is the
 oracle's own (checked against the library's).
 Integer results (discretised spins, integer-J energies) are compared
 bit-exactly, with both sides deciding from the same FP32 state.
