@@ -42,3 +42,37 @@ def test_fp8_exact():
     Jd = J.copy()
     np.fill_diagonal(Jd, 0.3)                    # the diagonal is not a coupling
     assert bench.fp8_exact(Jd)
+
+
+def _profile_commands():
+    """(file name, argument list) of every bench.py command quoted in profiles/"""
+    import os
+    import re
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles")
+    out = []
+    for name in sorted(os.listdir(root)):
+        for line in open(os.path.join(root, name)):
+            m = re.search(r"python3? -u bench\.py([^`'\"()]*)", line)
+            if m:
+                out.append((name, m.group(1).split()))
+    return out
+
+
+def test_profile_commands_parse_and_name_their_workload(monkeypatch):
+    """Every bench.py command that a profile summary quotes is accepted by the
+    bench's argument parser, and the coupling-kernel summaries run the workload
+    they are named for (the bench's default workload is Ising N = 4096)."""
+    import sys
+    cmds = _profile_commands()
+    assert len(cmds) >= 10
+    named = {"dense_step_f32_xy1024": ("xy1024",),
+             "dense_step_f32_ising4096": ("ising4096", "ising4096_fp32"),
+             "dense_step_lp_ising4096": ("ising4096", "ising4096_bf16")}
+    for name, args in cmds:
+        monkeypatch.setattr(sys, "argv", ["bench.py", *args])
+        a = bench.parse()
+        if a.copy_calibration:
+            continue
+        for prefix, workloads in named.items():
+            if name.startswith(prefix):
+                assert a.workload in workloads, (name, args)
