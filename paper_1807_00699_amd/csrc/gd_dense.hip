@@ -553,6 +553,45 @@ dense_step_f32_dl(DenseStepArgs a) {
                 a.partial[(long long)mt * a.Rp + r0 + tcol(tb) + l16] = s;
             }
         }
+    } else if constexpr ((CPLX ? 2 : 1) * TRAJ * (BM + 4) > 2 * TILE) {
+        // sums of the whole tile exceed the two chunk buffers: stage and
+        // update one wave column (TRAJ / WN trajectories) per pass
+        constexpr int TP = BM + 4;
+        constexpr int TRP = TRAJ / WN;
+        static_assert(NPF == 0, "operand loads ahead follow the one-pass group order");
+        static_assert((CPLX ? 2 : 1) * TRP * TP <= 2 * TILE, "staging fits LDS");
+        static_assert((TRP * RG) % NT == 0, "epilogue split");
+        constexpr int NUPP = TRP * RG / NT;
+        float *st = &lds[0][0];
+        float *sti = st + TRP * TP;
+#pragma unroll
+        for (int p = 0; p < WN; ++p) {
+            if (wn == p) {
+#pragma unroll
+                for (int tb = 0; tb < NP; ++tb) {
+                    const int tr = tcol(tb) - p * TRP + l16;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        const int row = wm * TM + mb * 16 + 4 * lq;
+                        *reinterpret_cast<f32x4 *>(&st[tr * TP + row]) = acc[mb][tb];
+                        if (CPLX) *reinterpret_cast<f32x4 *>(&sti[tr * TP + row]) = acc[mb][NP + tb];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < NUPP; ++u) {
+                const int g = tid + u * NT;
+                const int tr = g / RG, row = (g % RG) * 4;
+                const int r = r0 + p * TRP + tr;
+                const bool rvalid = r < a.R;
+                const f32x4 cr = *reinterpret_cast<const f32x4 *>(&st[tr * TP + row]);
+                const f32x4 ci = CPLX ? *reinterpret_cast<const f32x4 *>(&sti[tr * TP + row]) : cr;
+                const bool bad = step_epilogue4<MODE, CPLX, OP_F32>(a, m0 + row, r, rvalid, cr, ci);
+                if (bad && rvalid) a.flags[r] = 1;
+            }
+            if (p + 1 < WN) __syncthreads();
+        }
     } else {
         constexpr int TP = BM + 4;
         static_assert((CPLX ? 2 : 1) * TRAJ * TP <= 2 * TILE, "staging fits LDS");
@@ -660,7 +699,8 @@ hipError_t launch_modes(int mode, const DenseStepArgs &a, hipStream_t st) {
     X(11, 64, 128, 32, 2, 2, 1, 1, 1)      \
     X(12, 64, 64, 32, 2, 2, 1, 1, 2)       \
     X(13, 64, 64, 32, 2, 2, 1, 1, 3)       \
-    X(14, 64, 64, 64, 2, 2, 1, 1, 3)
+    X(14, 64, 64, 64, 2, 2, 1, 1, 3)       \
+    X(15, 128, 128, 32, 2, 2, 1, 1, 1)
 
 constexpr int kCfg[][8] = {
 #define GD_ROW(id, bm, bn, bk, wm, wn, ks, la, dl) {bm, bn, bk, wm, wn, ks, la, dl},

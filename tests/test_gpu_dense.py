@@ -138,7 +138,7 @@ def test_ising4096_full_size_sampled_parity():
 # groups, load lookahead, direct-to-LDS copies with and without the spread
 # state-operand loads); N = 1000 pads to 1024 so each of them tiles it and the
 # direct-to-LDS load tails fit
-FP32_VARIANTS = range(15)
+FP32_VARIANTS = range(16)
 
 
 @pytest.mark.parametrize("model,integrator,dt", [("xy", gd.GD_RK4, 0.02), ("ising", gd.GD_EULER, 0.05)])
